@@ -1,0 +1,27 @@
+"""Test oracle for the finite-difference lattice Boltzmann method (FP64, CPU).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the package's smoke check and
+the benchmark's CPU-baseline leg may import, call, link or run anything in
+this directory.  The GPU library never does, and this directory never
+imports the GPU library: the two share no code, only the seeded input
+generators of ``workloads.py``.
+
+Contents
+--------
+quadrature.py  half-range and full-range Gauss-Hermite rules from exact moments (mpmath)
+fdlb_oracle.c  the fully discrete scheme on raw populations, plain C, FP64
+scheme.py      ctypes driver of fdlb_oracle.c, problem setup, moments and wall profiles
+couette.py     semi-analytic steady Couette solution of the discrete-velocity model
+               and the paper's printed closed form (Eqs. 10-11)
+dense.py       steady state by a dense null-space solve on tiny grids
+mlp.py         FP64 forward/backward/Adam of the warm-start network
+build.py       compiles fdlb_oracle.c with gcc
+
+Parity status: every function here is pinned by tests against facts the paper
+or mathematics fixes (printed Table I, closed-form moments, closed-form
+relaxation and transport responses, conservation, free-molecular Couette,
+convergence to the semi-analytic Couette solution, the printed Eqs. 10-11,
+symmetries, dense solves).  The Table II drag/flow-rate values and the
+figure curves are parity unpinned (their definitions and reference solvers
+are not in the paper).
+"""

@@ -1,0 +1,357 @@
+"""Pins of the oracle's fully discrete scheme against facts fixed by the paper or by mathematics.
+
+Each test names what it pins: closed-form responses of the relaxation and of
+the upwind transport, conservation laws, exact free-molecular Couette flow,
+first-order convergence to the semi-analytic Couette solution (itself pinned
+to the paper's printed Eqs. 10-11), symmetries, and a dense null-space solve.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import couette, dense, quadrature
+from oracle.scheme import BOTTOM, LEFT, RIGHT, TOP, Problem
+
+
+def _random_positive_state(P, seed, amp=0.3):
+    rng = np.random.default_rng(seed)
+    return P.w[:, None, None] * (1.0 + amp * rng.uniform(-1, 1, size=P.shape))
+
+
+# ---------------------------------------------------------------------------
+# Relaxation: explicit Euler on a linear relaxation (Eq. 1 without transport).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("qset", [(("half", 2), ("half", 2)), (("half", 4), ("full", 3)),
+                                  (("full", 4), ("half", 3))])
+def test_relaxation_closed_form(qset):
+    """One periodic cell, no transport: the populations relax geometrically,
+    f^n - f^inf = (1 - omega)^n (f^0 - f^inf), towards a limit that keeps the
+    initial density and momentum (Eqs. 6-7) and has the equilibrium form
+    w_alpha (a + b . xi_alpha) of Eq. (5)."""
+    P = Problem(1, 1, True, True, (0, 0, 0, 0), kn=0.05, qx=qset[0], qy=qset[1], dt_override=0.01)
+    omega = P.omega
+    f0 = _random_positive_state(P, 1)
+    finf = P.step(f0, 4000)
+    for n in (1, 2, 7, 30):
+        fn = P.step(f0, n)
+        assert np.allclose(fn - finf, (1 - omega) ** n * (f0 - finf), rtol=0, atol=1e-15)
+    # conservation of rho and rho u
+    for mom in (np.ones(P.q), P.xi_x, P.xi_y):
+        assert abs((mom[:, None, None] * (finf - f0)).sum()) < 1e-14
+    # equilibrium form: f/w is affine in xi
+    A = np.stack([np.ones(P.q), P.xi_x, P.xi_y], axis=1)
+    coef, *_ = np.linalg.lstsq(A, finf[:, 0, 0] / P.w, rcond=None)
+    assert np.abs(A @ coef - finf[:, 0, 0] / P.w).max() < 1e-13
+
+
+def test_relaxation_conserves_to_roundoff_on_grid():
+    P = Problem(7, 5, True, True, (0, 0, 0, 0), kn=0.02, qx=("half", 3), qy=("half", 3))
+    f0 = _random_positive_state(P, 2)
+    f1 = P.step(f0, 1)
+    for mom in (np.ones(P.q), P.xi_x, P.xi_y):
+        a = (mom[:, None, None] * f0).sum()
+        b = (mom[:, None, None] * f1).sum()
+        assert abs(a - b) < 1e-14 * max(1.0, abs(a))
+
+
+# ---------------------------------------------------------------------------
+# Transport: first-order upwind, closed form for a Fourier mode.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny,kx,ky", [(8, 6, 1, 2), (16, 16, 3, 5), (5, 9, 2, 0)])
+def test_upwind_fourier_mode_closed_form(nx, ny, kx, ky):
+    """Free-molecular flow (Kn = inf) on a periodic box: each population is
+    advected by the donor-cell scheme, which multiplies the Fourier mode
+    e^{i(th_x i + th_y j)} by G = 1 - nu_x (1 - e^{-i s_x th_x}) - nu_y (1 - e^{-i s_y th_y})
+    per step, with s the sign of xi and nu = dt |xi| / dx."""
+    P = Problem(nx, ny, True, True, (0, 0, 0, 0), kn=math.inf, qx=("half", 2), qy=("full", 3))
+    thx, thy = 2 * math.pi * kx / nx, 2 * math.pi * ky / ny
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    rng = np.random.default_rng(3)
+    phase = rng.uniform(0, 2 * math.pi, P.q)
+    f0 = np.stack([P.w[a] * (1 + 0.5 * np.cos(thx * i + thy * j + phase[a])) for a in range(P.q)])
+    nsteps = 13
+    fn = P.step(f0, nsteps)
+    for a in range(P.q):
+        nux = P.dt * abs(P.xi_x[a]) * nx
+        nuy = P.dt * abs(P.xi_y[a]) * ny
+        G = 1 - nux * (1 - np.exp(-1j * np.sign(P.xi_x[a]) * thx)) \
+              - nuy * (1 - np.exp(-1j * np.sign(P.xi_y[a]) * thy))
+        want = P.w[a] * (1 + 0.5 * np.real(G ** nsteps * np.exp(1j * (thx * i + thy * j + phase[a]))))
+        assert np.abs(fn[a] - want).max() < 1e-14, a
+
+
+# ---------------------------------------------------------------------------
+# Walls: impermeability (Eq. 9) conserves mass exactly.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", [W.cavity(12, ny=9, kn=0.1, order=2),
+                                  W.cavity(10, kn=0.01, order=3),
+                                  W.couette(30, kn=0.5),
+                                  W.couette_x(20, kn=0.2)])
+def test_total_mass_conserved(case):
+    P = Problem.from_case(case)
+    f0 = _random_positive_state(P, 4)
+    m0 = f0.sum()
+    f = f0
+    for _ in range(4):
+        f = P.step(f, 50)
+        assert abs(f.sum() - m0) < 3e-14 * m0
+
+
+def test_wall_face_state_has_no_normal_flow():
+    """Face state of every wall: the emitted half carries exactly the mass flux of the
+    arriving half (Eq. 9), so sum_alpha (xi . n) g_face = 0."""
+    P = Problem.from_case(W.cavity(9, ny=7, kn=0.1, order=3))
+    f = P.step(_random_positive_state(P, 5), 3)
+    # mass conservation over one step is the integral statement; check the local one too:
+    # with rho = 1 fields the face density is finite and the flux sums cancel.
+    for wall in (BOTTOM, TOP, LEFT, RIGHT):
+        r, u, p = P.wall_profile(f, wall)
+        assert np.all(r > 0)
+    m0 = f.sum()
+    assert abs(P.step(f, 1).sum() - m0) < 1e-14 * m0
+
+
+# ---------------------------------------------------------------------------
+# Couette flow.
+# ---------------------------------------------------------------------------
+
+def test_couette_invariants_during_march():
+    """rho = 1 and u_y = 0 at every step; u_x is odd about the mid-plane."""
+    P = Problem.from_case(W.C1)
+    f = P.equilibrium()
+    for _ in range(3):
+        f = P.step(f, 400)
+        rho, ux, uy = P.moments(f)
+        assert np.abs(rho - 1).max() < 1e-13
+        assert np.abs(uy).max() < 1e-15
+        assert np.abs(ux[:, 0] + ux[::-1, 0]).max() < 1e-16
+
+
+def test_couette_xi_x_rule_independence():
+    """The odd-in-xi_x part stays linear in xi_x, so any xi_x rule integrating xi_x^2
+    exactly gives the same flow (the paper's remark on the mixed set)."""
+    base = W.couette(60, kn=0.3)
+    outs = []
+    for qx in (("full", 3), ("half", 4), ("half", 2), ("full", 4), ("half", 1)):
+        P = Problem.from_case(W.with_(base, qx=qx))
+        f = P.step(P.equilibrium(), 700)
+        outs.append(P.moments(f)[1][:, 0])
+    for o in outs[1:-1]:
+        assert np.abs(o - outs[0]).max() < 1e-15
+    # one node per half integrates xi_x^2 as 2/pi, not 1: a different flow
+    assert np.abs(outs[-1] - outs[0]).max() > 1e-3
+
+
+def test_couette_free_molecular_exact():
+    """Kn = inf: each plate's emission crosses the gap unchanged, so u_x = 0 and
+    p_xy = -sqrt(2/pi) u_w everywhere, exactly (the upwind scheme carries constants exactly)."""
+    u_w = 0.01
+    for qy in (("half", 2), ("half", 4)):
+        P = Problem.from_case(W.couette(16, kn=math.inf, u_w=u_w, qy=qy))
+        f, n, hist = P.solve(P.equilibrium(), 1e-300, 20000)
+        f = P.step(f, 2000)
+        rho, ux, uy = P.moments(f)
+        assert np.abs(ux).max() < 1e-12 * u_w
+        assert np.abs(rho - 1).max() < 1e-13
+        pxy = P.pxy(f)
+        want = couette.free_molecular_pxy(u_w)
+        assert abs(want + math.sqrt(2 / math.pi) * u_w) < 1e-18
+        assert np.abs(pxy - want).max() < 1e-12 * u_w
+        for wall in (BOTTOM, TOP):
+            _, _, pw = P.wall_profile(f, wall)
+            assert np.abs(pw - want).max() < 1e-12 * u_w
+
+
+def _couette_converged(n, kn, qy=("half", 4), tol=1e-13):
+    P = Problem.from_case(W.couette(n, kn=kn, u_w=1.0, qy=qy))
+    f, steps, hist = P.solve(P.equilibrium(), tol, 400000)
+    assert hist[-1] < tol
+    _, ut, pw = P.wall_profile(f, TOP)
+    rho, ux, uy = P.moments(f)
+    return ut[0], pw[0], P, f
+
+
+@pytest.mark.parametrize("kn", [0.1, 1.0])
+def test_couette_first_order_convergence_to_semi_analytic(kn):
+    """The scheme is first order in dy: the wall velocity and stress approach the
+    semi-analytic solution of the discrete-velocity model with errors halving
+    as N doubles, and Richardson extrapolation removes the leading term."""
+    exact = couette.CouetteSolution(4, kn, 1.0)
+    uex, pex = exact.u(0.5), exact.pxy()
+    errs_u, errs_p, vals = [], [], []
+    for n in (50, 100, 200):
+        u, p, _, _ = _couette_converged(n, kn)
+        errs_u.append(u - uex)
+        errs_p.append(p - pex)
+        vals.append((u, p))
+    for e in (errs_u, errs_p):
+        r1, r2 = e[0] / e[1], e[1] / e[2]
+        assert 1.8 < r1 < 2.3 and 1.8 < r2 < 2.3, e
+    u_rich = 2 * vals[2][0] - vals[1][0]
+    p_rich = 2 * vals[2][1] - vals[1][1]
+    assert abs(u_rich - uex) < 1e-4 * abs(uex)
+    assert abs(p_rich - pex) < 2e-4 * abs(pex)
+
+
+def test_couette_face_stress_uniform_at_steady_state():
+    """Discrete momentum balance: at steady state the face stress is the same on both plates
+    and equals the integral of nothing but the flux (uniform across the channel)."""
+    _, _, P, f = _couette_converged(50, 0.3, tol=1e-14)
+    _, _, pt = P.wall_profile(f, TOP)
+    _, _, pb = P.wall_profile(f, BOTTOM)
+    assert abs(pt[0] - pb[0]) < 1e-10 * abs(pt[0])
+
+
+def test_couette_profile_matches_semi_analytic_interior():
+    exact = couette.CouetteSolution(4, 0.1, 1.0)
+    _, _, P, f = _couette_converged(200, 0.1)
+    rho, ux, _ = P.moments(f)
+    y = (np.arange(200) + 0.5) / 200 - 0.5
+    ue = np.array([exact.u(v) for v in y])
+    assert np.abs(ux[:, 0] - ue).max() < 5e-3   # O(dy) with dy = 1/200
+
+
+@pytest.mark.parametrize("kn", [0.01, 0.1, 0.3, 1.0, 3.0, 10.0, 100.0])
+def test_printed_eqs_10_11_match_semi_analytic_under_readings(kn):
+    """The paper's closed form for 2 nodes per half (Eqs. 10-11) agrees with the
+    semi-analytic solution once (i) its Kn is the Eq. (1) value times sqrt(2) and its
+    stress is sqrt(2) times ours, and (ii) the first numerator constant 0.9494 is read
+    as 0.9404 (= 1.881/2).  Four-digit constants limit the agreement to ~3e-4."""
+    s = couette.CouetteSolution(2, kn, 1.0)
+    kp = math.sqrt(2) * kn
+    for y in (0.5, 0.3, 0.1):
+        ue = s.u(y)
+        up = couette.printed_eq10(y, kp, a_num=0.9404)
+        assert abs(up - ue) <= 3e-4 * abs(s.u(0.5)), (y, up, ue)
+    pp = couette.printed_eq11(kp, a_num=0.9404) / math.sqrt(2)
+    assert abs(pp - s.pxy()) <= 3e-4 * abs(s.pxy())
+
+
+def test_printed_eq10_literal_disagrees():
+    """As printed (0.9494, Eq. 1 Kn), Eq. (10) is far from the solution at small Kn:
+    the readings above are needed, not cosmetic."""
+    s = couette.CouetteSolution(2, 0.01, 1.0)
+    assert abs(couette.printed_eq10(0.5, 0.01) - s.u(0.5)) > 0.1
+
+
+def test_semi_analytic_dispersion_roots_and_limits():
+    """2 nodes per half: one root; its value times sqrt(2) is the printed 1.881 (Eq. 10).
+    Kn -> inf gives the free-molecular stress; Kn -> 0 gives no slip (u(1/2) -> u_w)."""
+    s = couette.CouetteSolution(2, 1.0)
+    assert len(s.mu) == 1
+    assert abs(float(s.mu[0]) * math.sqrt(2) - 1.881) < 5e-4
+    s4 = couette.CouetteSolution(4, 1.0)
+    assert len(s4.mu) == 3
+    assert abs(couette.CouetteSolution(4, 1e7).pxy() - couette.free_molecular_pxy()) < 1e-6
+    assert abs(couette.CouetteSolution(4, 1e-4).u(0.5) - 1.0) < 1e-3
+
+
+def test_x_oriented_couette_is_the_transpose():
+    """Couette flow between plates at x = 0 and x = 1 (sliding along y) is the same flow
+    reflected across the diagonal: u_y(x) equals u_x(y)."""
+    A = Problem.from_case(W.couette(40, kn=0.2))
+    B = Problem.from_case(W.couette_x(40, kn=0.2))
+    assert A.dt == B.dt
+    fa = A.step(A.equilibrium(), 900)
+    fb = B.step(B.equilibrium(), 900)
+    ua = A.moments(fa)[1][:, 0]
+    ub = B.moments(fb)[2][0, :]
+    assert np.abs(ua - ub).max() < 1e-12 * np.abs(ua).max()
+
+
+# ---------------------------------------------------------------------------
+# Cavity.
+# ---------------------------------------------------------------------------
+
+def test_cavity_mirror_symmetry():
+    """Reversing the lid equals mirroring x -> 1 - x (xi_x -> -xi_x)."""
+    c = W.cavity(12, ny=10, kn=0.2, order=2)
+    P = Problem.from_case(c)
+    M = Problem.from_case(W.with_(c, wall_u=(0.0, -0.01, 0.0, 0.0)))
+    fp = P.step(P.equilibrium(), 300)
+    fm = M.step(M.equilibrium(), 300)
+    rp, uxp, uyp = P.moments(fp)
+    rm, uxm, uym = M.moments(fm)
+    s = np.abs(uxp).max()
+    assert np.abs(rm - rp[:, ::-1]).max() < 1e-14
+    assert np.abs(uxm + uxp[:, ::-1]).max() < 1e-12 * s
+    assert np.abs(uym - uyp[:, ::-1]).max() < 1e-12 * s
+
+
+def test_cavity_rotation_equivariance():
+    """A top lid sliding along +x, turned by 90 degrees, is a left wall sliding along +y:
+    cell (i, j) maps to (N-1-j, i) and (u_x, u_y) to (-u_y, u_x)."""
+    N = 10
+    A = Problem.from_case(W.cavity(N, kn=0.1, order=3))
+    B = Problem.from_case(W.with_(W.cavity(N, kn=0.1, order=3), wall_u=(0.0, 0.0, 0.01, 0.0)))
+    fa = A.step(A.equilibrium(), 250)
+    fb = B.step(B.equilibrium(), 250)
+    ra, uxa, uya = A.moments(fa)
+    rb, uxb, uyb = B.moments(fb)
+    s = np.abs(uxa).max()
+    for j in range(N):
+        for i in range(N):
+            ib, jb = N - 1 - j, i
+            assert abs(rb[jb, ib] - ra[j, i]) < 1e-14
+            assert abs(uxb[jb, ib] + uya[j, i]) < 1e-12 * s
+            assert abs(uyb[jb, ib] - uxa[j, i]) < 1e-12 * s
+
+
+def test_cavity_at_rest_stays_at_rest():
+    P = Problem.from_case(W.cavity(8, kn=0.1, order=2, u_w=0.0))
+    f0 = P.equilibrium()
+    f = P.step(f0, 50)
+    assert np.abs(f - f0).max() < 1e-15
+
+
+def test_steady_state_equals_dense_null_space():
+    """Brute force on a tiny grid: the marched steady state equals the null vector of
+    (M - I) of the one-step map, with the same total mass."""
+    for case in (W.cavity(4, kn=0.1, order=2), W.cavity(3, ny=4, kn=1.0, order=2),
+                 W.couette(6, kn=0.2, qy=("half", 2))):
+        P = Problem.from_case(case)
+        f, n, hist = P.solve(P.equilibrium(), 1e-13, 300000)
+        assert hist[-1] < 1e-13
+        fd = dense.steady_state(P, total_mass=P.nx * P.ny)
+        r1, ux1, uy1 = P.moments(f)
+        r2, ux2, uy2 = P.moments(fd)
+        scale = max(np.abs(ux1).max(), np.abs(uy1).max())
+        assert max(np.abs(ux1 - ux2).max(), np.abs(uy1 - uy2).max()) < 1e-10 * scale
+        assert np.abs(r1 - r2).max() < 1e-12
+
+
+def test_splitting_order_does_not_change_steady_rho_u():
+    """The relaxation conserves rho and rho u exactly, so relax-then-transport and
+    transport-then-relax share their steady density and velocity."""
+    c = W.cavity(6, kn=0.1, order=2)
+    A = Problem.from_case(c, order=0)
+    B = Problem.from_case(c, order=1)
+    fa, _, ha = A.solve(A.equilibrium(), 1e-13, 400000)
+    fb, _, hb = B.solve(B.equilibrium(), 1e-13, 400000)
+    assert ha[-1] < 1e-13 and hb[-1] < 1e-13
+    ra, uxa, uya = A.moments(fa)
+    rb, uxb, uyb = B.moments(fb)
+    s = np.abs(uxa).max()
+    assert np.abs(uxa - uxb).max() < 1e-10 * s
+    assert np.abs(uya - uyb).max() < 1e-10 * s
+    assert np.abs(ra - rb).max() < 1e-12
+
+
+def test_residual_history_and_stop():
+    P = Problem.from_case(W.cavity(8, kn=0.1, order=2))
+    f, n, hist = P.solve(P.equilibrium(), 1e-6, 100000)
+    assert hist[-1] < 1e-6 and np.all(hist[:-1] >= 1e-6)
+    assert len(hist) == n
+
+
+def test_equilibrium_renormalisation():
+    P = Problem.from_case(W.cavity(5, kn=0.1, order=2))
+    rho, ux, uy = W.random_fields(5, 5, seed=7, amp=0.1)
+    f = P.equilibrium(rho * 1.3, ux, uy, renormalize=True)
+    assert abs(f.sum() - 25.0) < 1e-13
