@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the finite-difference lattice Boltzmann hot path on one MI355X.
+
+One benchmark step is one full time step of the method on the large cavity
+(1024 x 1024 cells, 16 x 16 = 256 half-range velocities, Kn = 1, lid 0.01,
+FP32 deviation storage with FP64 wall and residual sums): relaxation, wall
+emission, upwind transport, moments, wall fluxes and the residual reduction.
+The state is resident in HBM before timing starts.
+
+Output: one JSON line on stdout (progress on stderr).  `value` is cell-velocity
+updates per second.  `roofline` prices the fused step kernel against the HBM
+peak using its algorithmic bytes (every population read once and written once,
+plus the per-cell moments) and its own average duration from HIP events on the
+library's stream.  Extra fields: the time to residual 1e-8 of the 128 x 128
+cavity in FP32 versus plain FP64, the Couette time to 1e-10 in FP64, and the
+measured copy bandwidth.  `cpu_baseline` times the FP64 CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "cell·velocity updates/s (GB/s vs HBM peak); time to residual 1e-8 vs plain FP64"
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "step_kernel_cavity1024_q256_fp32_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1308_0692_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(per_launch_bytes_alg: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; otherwise None."""
+    try:
+        d = json.load(open(PROFILE_TRAFFIC))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_to_residual(F, W):
+    """Plain FP64 and FP32 solves of the 128^2 cavity to R < 1e-8 and the Couette case to 1e-10."""
+    out = {}
+    c2 = W.C2
+    for prec, graph in (("fp32", True), ("fp64", True), ("fp64", False)):
+        p = F.Problem(c2, precision=prec)
+        p.init_equilibrium()
+        p.solve(1e-8, 400, check_every=200, use_graph=graph)  # warm-up (graph capture)
+        p.init_equilibrium()
+        rep = p.solve(1e-8, 200000, check_every=200, use_graph=graph)
+        key = f"cavity128_q64_{prec}{'_graph' if graph else ''}"
+        out[key] = {"wall_s": round(rep["wall_s"], 4), "steps": rep["steps"],
+                    "first_below": rep["first_below"], "updates_per_s": rep["updates_per_s"]}
+        log(f"  {key}: {rep['wall_s']:.3f} s, {rep['steps']} steps")
+        p.close()
+    p = F.Problem(W.C1, precision="fp64")
+    p.init_equilibrium()
+    p.solve(1e-10, 200, check_every=100)
+    p.init_equilibrium()
+    rep = p.solve(1e-10, 200000, check_every=100)
+    out["couette200_q24_fp64_graph"] = {"wall_s": round(rep["wall_s"], 4), "steps": rep["steps"],
+                                        "first_below": rep["first_below"]}
+    log(f"  couette: {rep['wall_s']:.3f} s, {rep['steps']} steps")
+    p.close()
+    return out
+
+
+def copy_ceiling(F, torch, nbytes=4 << 30, reps=10):
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    F.stream_copy(dst, src, nbytes, s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        F.stream_copy(dst, src, nbytes, s)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(case, target_s: float = 15.0):
+    """The FP64 oracle on the same workload, a bounded number of steps."""
+    from oracle import scheme
+    P = scheme.Problem.from_case(case)
+    f = P.equilibrium()
+    t0 = time.perf_counter()
+    f = P.step(f, 1)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(50, int(target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    f = P.step(f, n)
+    dt = time.perf_counter() - t0
+    ups = case.nx * case.ny * P.q * n / dt
+    return {"value": ups, "unit": "cell-velocity updates/s", "cores": scheme.threads(), "kind": "oracle",
+            "sample": f"{n} FP64 steps of the {case.nx}x{case.ny} cavity with {P.q} velocities "
+                      f"(after 1 untimed step), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--tile", type=int, default=-2, help="-2 autotune, -1 heuristic, >=0 a tile index")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual runs")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU, "
+              "see the sharding design notes", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1308_0692_amd as F
+    import workloads as W
+
+    case = W.C4
+    log(f"[bench] workload {case.name}: {case.nx}x{case.ny} cells, Q={case.q}, Kn={case.kn}")
+    p = F.Problem(case, precision="fp32")
+    if args.tile == -2:
+        ms = p.autotune(steps=5)
+        log(f"[bench] autotuned tile {p.tile} ({F.tile_describe('fp32', p.tile)}): {ms:.3f} ms/step")
+    elif args.tile >= 0:
+        p.set_tile(args.tile)
+    tile_desc = F.tile_describe("fp32", p.tile)
+    p.init_equilibrium()
+    p.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"[bench] warm-up {args.warmup} steps done; timing {args.steps}")
+
+    s = p.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s)
+    ms_step_k, ms_red_k = p.step_timed(args.steps)
+    e1.record(s)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    R, nsteps = p.last_residual()
+    log(f"[bench] {args.steps} steps: {ms_total:.2f} ms events, {wall*1e3:.2f} ms wall; "
+        f"step kernels {ms_step_k:.2f} ms, reductions {ms_red_k:.2f} ms; R={R:.3e}")
+
+    cells = case.nx * case.ny
+    q = p.q
+    updates_per_step = cells * q
+    ms_per_step = ms_total / args.steps
+    value = updates_per_step * args.steps / (ms_total * 1e-3)
+    # algorithmic bytes of one step-kernel launch: populations read + written (4 B each),
+    # per-cell moments read + written (3 + 3 floats), wall fluxes (4 walls x N doubles, in + out)
+    alg_bytes = updates_per_step * 8 + cells * 6 * 4 + 2 * 4 * max(case.nx, case.ny) * 8
+    avg_kernel_s = ms_step_k * 1e-3 / args.steps
+    achieved = alg_bytes / avg_kernel_s / 1e9
+    traffic = measured_traffic(alg_bytes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "step_kernel", "alg_bytes_per_launch": alg_bytes,
+                "avg_kernel_ms": round(avg_kernel_s * 1e3, 5)}
+    log(f"[bench] {value:.4e} updates/s; step kernel {achieved:.0f} GB/s = {achieved/HBM_PEAK_GBPS:.3f} of peak")
+
+    extra = {}
+    if not args.no_copy:
+        extra["copy_GBps"] = round(copy_ceiling(F, torch), 1)
+        log(f"[bench] streaming copy: {extra['copy_GBps']} GB/s")
+    if not args.no_ttr:
+        log("[bench] time to residual:")
+        extra["time_to_residual"] = time_to_residual(F, W)
+    p.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(case)
+        log(f"[bench] oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
+
+    line = {"metric": METRIC, "value": value, "unit": "cell-velocity updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": case.name, "nx": case.nx, "ny": case.ny, "q": q, "kn": case.kn,
+                       "lid_u": case.wall_u[1], "velocities": "half-range Gauss-Hermite 8 per half, tensor",
+                       "tile": tile_desc},
+            "roofline": roofline, "cpu_baseline": cpu, **extra}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,265 @@
+/*
+ * fdlb.h -- C ABI of libfdlb, an MI355X (gfx950) implementation of the
+ * finite-difference lattice Boltzmann method of Ghiroldi & Gibelli,
+ * "A finite-difference lattice Boltzmann approach for gas microflows"
+ * (arXiv 1308.0692).
+ *
+ * The method: discrete velocities xi_alpha and weights w_alpha from a
+ * half-range (or full-range) Gauss-Hermite rule (Table I, tensor product in
+ * two dimensions); weighted populations f_alpha (Eq. 2) obey the linearised
+ * BGKW model of Eq. (1) with the isothermal equilibrium of Eq. (5); density
+ * and momentum are the sums of Eqs. (6)-(7); solid walls re-emit the
+ * populations that leave them with the diffuse Maxwell condition of Eq. (8),
+ * whose wall density comes from the impermeability sum of Eq. (9).  One time
+ * step relaxes with an explicit Euler step and then transports with a
+ * first-order upwind difference (the paragraph that introduces the fully
+ * discrete scheme, before the Couette problem).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Geometry: the unit square, N_x x N_y cell-centred cells (dx = 1/N_x,
+ *    dy = 1/N_y); walls lie on the outer cell faces.  An axis is either
+ *    bounded by two walls or periodic; a periodic axis must have exactly one
+ *    cell (the paper's planar Couette flow), so transport along it vanishes.
+ *  - Walls: index 0 bottom (y = 0), 1 top (y = 1), 2 left (x = 0), 3 right
+ *    (x = 1).  wall_u[i] is the wall's tangential speed: along +x for the
+ *    bottom/top walls, along +y for the left/right walls.
+ *  - Velocity order: alpha = j * Q_x + i, i indexing the x rule and j the y
+ *    rule, both rules with nodes ascending.
+ *  - Host arrays of cell fields are row-major [y][x] (N_x fastest), doubles.
+ *    Population arrays are [alpha][y][x], doubles, raw f_alpha (not deviations).
+ *  - Device memory is owned by the caller: the library never allocates,
+ *    frees or keeps device memory beyond what fdlb_bind hands it.  Host
+ *    buffers passed in are owned by the caller and not retained after return.
+ *  - Streams: `stream` arguments are hipStream_t values passed as void*;
+ *    NULL means the default stream.  Every call that launches work enqueues
+ *    it on the bound stream.  Calls documented as synchronous wait for that
+ *    stream; all others return without waiting.
+ *  - Errors: every int-returning function returns FDLB_OK (0), a negative
+ *    error code, or a positive warning.  fdlb_last_error() gives a message
+ *    for the calling thread.  No C++ exception crosses this interface.  A
+ *    handle must not be used from two threads at once; distinct handles are
+ *    independent.
+ */
+#ifndef FDLB_H
+#define FDLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FDLB_OK 0
+#define FDLB_ENOTCONVERGED 1 /* warning: max_steps reached above the tolerance */
+#define FDLB_EINVAL (-1)     /* invalid argument */
+#define FDLB_EUNSTABLE (-2)  /* CFL > 1 or dt/Kn > 1 without allow_unstable */
+#define FDLB_EHIP (-3)       /* a HIP runtime call failed (message has the HIP error) */
+#define FDLB_EDIVERGED (-4)  /* non-finite residual or |u| > 0.5 during a solve */
+#define FDLB_ESTATE (-5)     /* call out of order (e.g. not bound) */
+#define FDLB_ENOMEM (-6)     /* host allocation failed */
+
+/* ---- enumerations -------------------------------------------------------- */
+#define FDLB_HALF 0 /* half-range Gauss-Hermite rule, n nodes per half-line */
+#define FDLB_FULL 1 /* full-range Gauss-Hermite rule, n nodes */
+#define FDLB_FP64 0 /* populations stored and updated in double */
+#define FDLB_FP32 1 /* deviations f_alpha - w_alpha stored and updated in float;
+                       wall densities and the residual in double */
+#define FDLB_WALL_BOTTOM 0
+#define FDLB_WALL_TOP 1
+#define FDLB_WALL_LEFT 2
+#define FDLB_WALL_RIGHT 3
+
+/* ---- quadrature (Eq. 4, Table I, tensor product after Table I) ----------- */
+
+/*
+ * Half-range rule for the weight (2 pi)^(-1/2) exp(-xi^2/2) on [0, inf),
+ * mirrored onto (-inf, 0]: the n-point Gauss rule of each half-line.  Writes
+ * 2n nodes in ascending order and their weights (summing to 1) into
+ * caller-owned arrays of 2n doubles.  n in 1..16, else FDLB_EINVAL.
+ * Host only; needs no GPU.
+ */
+int fdlb_quad_half_range(int n_per_half, double *nodes, double *weights);
+
+/*
+ * Full-range Gauss-Hermite rule for the same weight on the whole line
+ * (probabilists' Hermite roots): n nodes ascending and weights summing to 1.
+ * n in 1..32, else FDLB_EINVAL.  Host only.
+ */
+int fdlb_quad_full_range(int n, double *nodes, double *weights);
+
+/* ---- problem description --------------------------------------------------- */
+
+typedef struct fdlb_problem_desc {
+    int32_t nx, ny;                 /* cells; >= 1 */
+    int32_t periodic_x, periodic_y; /* 1: periodic axis (then that N must be 1) */
+    double wall_u[4];               /* tangential wall speeds (see conventions) */
+    double kn;                      /* Knudsen number of Eq. (1); INFINITY allowed */
+    double cfl;                     /* Courant number in (0, 1]; 0.9 is customary */
+    int32_t qx_kind, qx_n;          /* FDLB_HALF (n per half) or FDLB_FULL (n total) */
+    int32_t qy_kind, qy_n;
+    int32_t precision;              /* FDLB_FP64 or FDLB_FP32 */
+    int32_t allow_unstable;         /* 1: accept CFL > 1 or dt/Kn > 1 (tests only) */
+} fdlb_problem_desc;
+
+typedef struct fdlb_problem fdlb_problem; /* opaque host handle */
+
+/*
+ * Validate a description and build the velocity set, the time step
+ * dt = cfl / max_alpha(|xi_x| N_x [x bounded] + |xi_y| N_y [y bounded]) and
+ * omega = dt / Kn (0 for Kn = INFINITY).  Host only (no GPU call); the
+ * handle owns only host memory.  FDLB_EINVAL for bad sizes or rules,
+ * FDLB_EUNSTABLE if cfl > 1 or omega > 1 and allow_unstable is 0.
+ */
+int fdlb_problem_create(const fdlb_problem_desc *desc, fdlb_problem **out);
+void fdlb_problem_destroy(fdlb_problem *p); /* NULL is a no-op; no GPU call */
+
+int fdlb_problem_q(const fdlb_problem *p);         /* number of velocities, or < 0 */
+double fdlb_problem_dt(const fdlb_problem *p);     /* time step (NaN for NULL) */
+double fdlb_problem_omega(const fdlb_problem *p);  /* dt / Kn */
+/* Copy the velocity set (Q entries each, velocity order above) into caller arrays. */
+int fdlb_problem_velocities(const fdlb_problem *p, double *xi_x, double *xi_y, double *w);
+
+/*
+ * Device memory the caller must provide: the state (two population buffers
+ * of Q N_x N_y values each, in the problem's precision) and a workspace
+ * (moments, wall fluxes, residual partials, tables, outputs).  Both sizes
+ * are in bytes; base addresses must be 256-byte aligned.
+ */
+size_t fdlb_state_bytes(const fdlb_problem *p);
+size_t fdlb_workspace_bytes(const fdlb_problem *p);
+
+/*
+ * Hand the library device buffers of at least the sizes above and the stream
+ * to use.  Uploads the velocity tables (asynchronously, on the stream).  The
+ * buffers stay owned by the caller and must outlive the binding; binding
+ * again replaces the previous binding.  The state is undefined until one of
+ * the init/upload calls below.
+ */
+int fdlb_bind(fdlb_problem *p, void *d_state, void *d_workspace, void *stream);
+
+/* ---- initial state --------------------------------------------------------- */
+
+/*
+ * Seed every cell at equilibrium, f_alpha = w_alpha rho (1 + xi_alpha . u)
+ * (Eqs. 3, 5), from host arrays of N_x N_y doubles ([y][x]).  NULL rho means
+ * rho = 1, NULL ux/uy mean zero.  With renormalize_mass, rho is first scaled
+ * so that its sum over cells is N_x N_y (the steady state scales with the
+ * total mass, which the scheme conserves).  Resets the step counter.
+ */
+int fdlb_init_equilibrium(fdlb_problem *p, const double *rho, const double *ux, const double *uy,
+                          int renormalize_mass);
+
+/*
+ * Same from device arrays of N_x N_y floats each (e.g. a network's output),
+ * laid out [y][x]; none may be NULL.  Renormalisation as above, on device.
+ */
+int fdlb_init_equilibrium_dev(fdlb_problem *p, const float *d_rho, const float *d_ux, const float *d_uy,
+                              int renormalize_mass);
+
+/*
+ * Replace the state by raw populations from a host array of Q N_x N_y doubles
+ * ([alpha][y][x]); the FP32 path stores f - w rounded to float.  With
+ * fdlb_state_download this is checkpoint/resume.  Synchronous.
+ */
+int fdlb_state_upload(fdlb_problem *p, const double *f_host);
+int fdlb_state_download(fdlb_problem *p, double *f_host); /* synchronous */
+
+/* ---- time marching ------------------------------------------------------------ */
+
+/*
+ * Advance nsteps time steps (relaxation, wall emission, upwind transport,
+ * moments and residual of every step), asynchronously on the bound stream.
+ */
+int fdlb_step(fdlb_problem *p, int64_t nsteps);
+
+/*
+ * Advance nsteps steps exactly as fdlb_step does, with HIP events recorded on
+ * the bound stream around every kernel launch; returns the summed device
+ * time of the fused step kernels and of the residual-reduction kernels, in
+ * milliseconds (either pointer may be NULL).  Synchronous.
+ */
+int fdlb_step_timed(fdlb_problem *p, int64_t nsteps, double *ms_step_kernels, double *ms_reduce_kernels);
+
+/*
+ * Residual of the most recent step, R = ||u^{n+1} - u^n||_2 / ||u^{n+1}||_2
+ * over all cells (both velocity components), and the number of steps since
+ * the last init.  Synchronous.
+ */
+int fdlb_last_residual(fdlb_problem *p, double *residual, int64_t *steps);
+
+typedef struct fdlb_report {
+    int64_t steps;          /* steps taken by the call */
+    int64_t first_below;    /* step count at which R first fell below tol, or -1 */
+    double residual;        /* residual of the last step */
+    double wall_s;          /* wall time of the call (host clock, after sync) */
+    double updates_per_s;   /* N_x N_y Q steps / wall_s */
+    double bytes_per_s;     /* algorithmic bytes (2 x population size per update) / wall_s */
+    int32_t status;         /* same as the return value */
+    int32_t history_len;    /* entries written to history */
+    int32_t history_cap;    /* capacity of history (set by the caller) */
+    int32_t pad_;
+    double *history;        /* caller-owned, may be NULL: residual at every check */
+} fdlb_report;
+
+/*
+ * March until the residual of a step falls below tol or max_steps steps have
+ * been taken; the host reads the residual every check_every steps (the only
+ * device-to-host synchronisation in the loop), so up to check_every - 1 steps
+ * may run past the first one below tol (report.first_below says where).
+ * use_graph = 1 replays check_every steps as one captured HIP graph.
+ * Synchronous.  Returns FDLB_OK, FDLB_ENOTCONVERGED or FDLB_EDIVERGED.
+ */
+int fdlb_solve_steady(fdlb_problem *p, double tol, int64_t max_steps, int32_t check_every,
+                      int32_t use_graph, fdlb_report *report);
+
+/* ---- outputs ---------------------------------------------------------------------- */
+
+/*
+ * Cell fields of the current state into host arrays of N_x N_y doubles
+ * ([y][x]; any pointer may be NULL): density (Eq. 6), velocity (Eq. 7) and
+ * the xy stress sum_alpha xi_x xi_y g_alpha of the post-relaxation state.
+ * Synchronous.
+ */
+int fdlb_moments(fdlb_problem *p, double *rho, double *ux, double *uy, double *pxy);
+
+/*
+ * Face state along one wall after relaxation: arriving and grazing
+ * populations carry the wall cell's value, leaving ones the emission of
+ * Eq. (8) with rho_w of Eq. (9).  Per face (N_x faces for bottom/top, N_y
+ * for left/right; pointers may be NULL): density, tangential velocity and
+ * xy stress.  FDLB_EINVAL for a wall of a periodic axis.  Synchronous.
+ */
+int fdlb_wall_profile(fdlb_problem *p, int wall, double *rho, double *u_t, double *pxy);
+
+/* ---- tuning --------------------------------------------------------------------- */
+
+/*
+ * Tile shapes of the step kernel.  fdlb_tile_count() gives the number of
+ * compiled shapes; fdlb_tile_describe writes "VXxLX/KxW" style text.
+ * fdlb_problem_set_tile selects one (-1: the built-in heuristic); shapes that
+ * do not fit the problem give FDLB_EINVAL.  fdlb_autotune times every
+ * fitting shape for `steps` steps on the bound buffers (the state is
+ * re-seeded at rest afterwards) and keeps the fastest; synchronous.
+ */
+int fdlb_tile_count(int precision);
+int fdlb_tile_describe(int precision, int tile, char *buf, size_t len);
+int fdlb_problem_set_tile(fdlb_problem *p, int tile);
+int fdlb_problem_get_tile(const fdlb_problem *p);
+int fdlb_autotune(fdlb_problem *p, int steps, double *best_ms_per_step);
+
+/* ---- measurement helpers ------------------------------------------------------------ */
+
+/* Copy `bytes` bytes device-to-device with the library's streaming copy kernel
+ * (for the achievable-bandwidth ceiling); asynchronous on the stream. */
+int fdlb_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *stream);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char *fdlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDLB_H */

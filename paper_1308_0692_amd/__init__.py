@@ -1,0 +1,182 @@
+"""fdlb on MI355X: the finite-difference lattice Boltzmann method with half-range
+Gauss-Hermite velocities (Ghiroldi & Gibelli, arXiv 1308.0692), as hand-written
+HIP kernels for gfx950 behind the C ABI of include/fdlb.h.
+
+Python layer: argument marshalling over ctypes; PyTorch provides device memory
+and the stream.  Importing this package requires the built libfdlb.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BOTTOM, LEFT, RIGHT, TOP, FdlbError, check, desc_from_case, make_desc,
+                   quad_full_range, quad_half_range, tile_count, tile_describe)
+
+__all__ = ["Problem", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
+           "RIGHT", "tile_count", "tile_describe", "stream_copy"]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libfdlb needs a GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _alloc(nbytes: int, device):
+    torch = _torch()
+    t = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t, t.data_ptr() + off
+
+
+class Problem:
+    """One boundary-value problem bound to device memory on `device` (default cuda:0)."""
+
+    def __init__(self, case=None, *, precision: Optional[str] = None, allow_unstable: bool = False,
+                 device="cuda:0", stream=None, bind: bool = True, desc: Optional[_lib.ProblemDesc] = None):
+        self.desc = desc if desc is not None else desc_from_case(case, precision, allow_unstable)
+        self.precision = "fp32" if self.desc.precision == _lib.FP32 else "fp64"
+        h = C.c_void_p()
+        check(_lib.lib.fdlb_problem_create(C.byref(self.desc), C.byref(h)))
+        self._h = h
+        self.nx, self.ny = self.desc.nx, self.desc.ny
+        self.q = _lib.lib.fdlb_problem_q(h)
+        self.dt = _lib.lib.fdlb_problem_dt(h)
+        self.omega = _lib.lib.fdlb_problem_omega(h)
+        self.state_bytes = _lib.lib.fdlb_state_bytes(h)
+        self.workspace_bytes = _lib.lib.fdlb_workspace_bytes(h)
+        self.device = device
+        self._stream = stream
+        if bind:
+            self.bind()
+
+    # -- memory ----------------------------------------------------------------
+    def bind(self):
+        torch = _torch()
+        # A stream of its own (default priority) so that step chunks can be graph-captured.
+        s = self._stream if self._stream is not None else torch.cuda.Stream(device=self.device)
+        self._stream = s
+        self._state_t, self._state = _alloc(self.state_bytes, self.device)
+        self._work_t, self._work = _alloc(self.workspace_bytes, self.device)
+        check(_lib.lib.fdlb_bind(self._h, C.c_void_p(self._state), C.c_void_p(self._work),
+                                 C.c_void_p(s.cuda_stream)))
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def velocities(self):
+        x, y, w = np.empty(self.q), np.empty(self.q), np.empty(self.q)
+        check(_lib.lib.fdlb_problem_velocities(self._h, _lib._dp(x), _lib._dp(y), _lib._dp(w)))
+        return x, y, w
+
+    # -- initial state -----------------------------------------------------------
+    def init_equilibrium(self, rho=None, ux=None, uy=None, renormalize: bool = False):
+        arr = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny, self.nx)
+               for a in (rho, ux, uy)]
+        check(_lib.lib.fdlb_init_equilibrium(self._h, *[_lib._dp(a) for a in arr], int(renormalize)))
+
+    def init_equilibrium_dev(self, rho, ux, uy, renormalize: bool = True):
+        """Seed from device float32 tensors of shape (ny, nx) (e.g. a network's prediction)."""
+        torch = _torch()
+        ts = [t.contiguous().to(torch.float32) for t in (rho, ux, uy)]
+        for t in ts:
+            assert t.numel() == self.nx * self.ny and t.is_cuda
+        self._stream.wait_stream(torch.cuda.current_stream(self.device))
+        ptrs = [C.cast(C.c_void_p(t.data_ptr()), C.POINTER(C.c_float)) for t in ts]
+        check(_lib.lib.fdlb_init_equilibrium_dev(self._h, *ptrs, int(renormalize)))
+        self._keep = ts
+
+    def upload(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (self.q, self.ny, self.nx)
+        check(_lib.lib.fdlb_state_upload(self._h, _lib._dp(f)))
+
+    def download(self) -> np.ndarray:
+        f = np.empty((self.q, self.ny, self.nx))
+        check(_lib.lib.fdlb_state_download(self._h, _lib._dp(f)))
+        return f
+
+    # -- marching ------------------------------------------------------------------
+    def step(self, n: int = 1):
+        check(_lib.lib.fdlb_step(self._h, int(n)))
+
+    def step_timed(self, n: int):
+        """Advance n steps; returns (ms in fused step kernels, ms in reduction kernels) from HIP events."""
+        a, b = C.c_double(), C.c_double()
+        check(_lib.lib.fdlb_step_timed(self._h, int(n), C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def last_residual(self):
+        r, s = C.c_double(), C.c_int64()
+        check(_lib.lib.fdlb_last_residual(self._h, C.byref(r), C.byref(s)))
+        return r.value, s.value
+
+    def solve(self, tol: float, max_steps: int, check_every: int = 100, use_graph: bool = True,
+              history_cap: int = 0, raise_on_diverge: bool = True) -> dict:
+        rep = _lib.Report()
+        hist = np.zeros(max(history_cap, 1))
+        rep.history_cap = history_cap
+        rep.history = _lib._dp(hist) if history_cap else None
+        code = _lib.lib.fdlb_solve_steady(self._h, float(tol), int(max_steps), int(check_every),
+                                          int(use_graph), C.byref(rep))
+        if code == _lib.EDIVERGED and not raise_on_diverge:
+            pass
+        else:
+            check(code, allow=(_lib.OK, _lib.ENOTCONVERGED))
+        return dict(status=code, steps=rep.steps, first_below=rep.first_below, residual=rep.residual,
+                    wall_s=rep.wall_s, updates_per_s=rep.updates_per_s, bytes_per_s=rep.bytes_per_s,
+                    history=hist[:rep.history_len].copy())
+
+    # -- outputs ----------------------------------------------------------------------
+    def moments(self):
+        """(rho, ux, uy, pxy), float64 arrays of shape (ny, nx)."""
+        out = [np.empty((self.ny, self.nx)) for _ in range(4)]
+        check(_lib.lib.fdlb_moments(self._h, *[_lib._dp(a) for a in out]))
+        return tuple(out)
+
+    def wall_profile(self, wall: int):
+        n = self.nx if wall in (BOTTOM, TOP) else self.ny
+        out = [np.empty(n) for _ in range(3)]
+        check(_lib.lib.fdlb_wall_profile(self._h, int(wall), *[_lib._dp(a) for a in out]))
+        return tuple(out)
+
+    # -- tiles ------------------------------------------------------------------------
+    @property
+    def tile(self) -> int:
+        return _lib.lib.fdlb_problem_get_tile(self._h)
+
+    def set_tile(self, tile: int):
+        check(_lib.lib.fdlb_problem_set_tile(self._h, int(tile)))
+
+    def autotune(self, steps: int = 10) -> float:
+        ms = C.c_double()
+        check(_lib.lib.fdlb_autotune(self._h, int(steps), C.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            # Work queued on the library's stream must finish before torch may recycle the buffers.
+            if getattr(self, "_state_t", None) is not None and self._stream is not None:
+                self._stream.synchronize()
+            _lib.lib.fdlb_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stream_copy(dst, src, nbytes: int, stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    check(_lib.lib.fdlb_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
+                                    int(nbytes), C.c_void_p(s.cuda_stream)))

@@ -1,0 +1,151 @@
+"""ctypes binding of libfdlb (include/fdlb.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.  PyTorch is used
+for device memory and streams.  If the library is missing, importing this
+module raises: there is no CPU fallback."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdlb.so")
+
+OK, ENOTCONVERGED, EINVAL, EUNSTABLE, EHIP, EDIVERGED, ESTATE, ENOMEM = 0, 1, -1, -2, -3, -4, -5, -6
+HALF, FULL = 0, 1
+FP64, FP32 = 0, 1
+BOTTOM, TOP, LEFT, RIGHT = 0, 1, 2, 3
+
+
+class FdlbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfdlb error {code}: {msg}")
+        self.code = code
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
+        ("wall_u", C.c_double * 4),
+        ("kn", C.c_double), ("cfl", C.c_double),
+        ("qx_kind", C.c_int32), ("qx_n", C.c_int32),
+        ("qy_kind", C.c_int32), ("qy_n", C.c_int32),
+        ("precision", C.c_int32), ("allow_unstable", C.c_int32),
+    ]
+
+
+class Report(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int64), ("first_below", C.c_int64),
+        ("residual", C.c_double), ("wall_s", C.c_double),
+        ("updates_per_s", C.c_double), ("bytes_per_s", C.c_double),
+        ("status", C.c_int32), ("history_len", C.c_int32), ("history_cap", C.c_int32),
+        ("pad_", C.c_int32), ("history", C.POINTER(C.c_double)),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    dp, vp, i64, i32 = C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_int32
+    fp = C.POINTER(C.c_float)
+    sig = {
+        "fdlb_quad_half_range": (C.c_int, [C.c_int, dp, dp]),
+        "fdlb_quad_full_range": (C.c_int, [C.c_int, dp, dp]),
+        "fdlb_problem_create": (C.c_int, [C.POINTER(ProblemDesc), C.POINTER(vp)]),
+        "fdlb_problem_destroy": (None, [vp]),
+        "fdlb_problem_q": (C.c_int, [vp]),
+        "fdlb_problem_dt": (C.c_double, [vp]),
+        "fdlb_problem_omega": (C.c_double, [vp]),
+        "fdlb_problem_velocities": (C.c_int, [vp, dp, dp, dp]),
+        "fdlb_state_bytes": (C.c_size_t, [vp]),
+        "fdlb_workspace_bytes": (C.c_size_t, [vp]),
+        "fdlb_bind": (C.c_int, [vp, vp, vp, vp]),
+        "fdlb_init_equilibrium": (C.c_int, [vp, dp, dp, dp, C.c_int]),
+        "fdlb_init_equilibrium_dev": (C.c_int, [vp, fp, fp, fp, C.c_int]),
+        "fdlb_state_upload": (C.c_int, [vp, dp]),
+        "fdlb_state_download": (C.c_int, [vp, dp]),
+        "fdlb_step": (C.c_int, [vp, i64]),
+        "fdlb_step_timed": (C.c_int, [vp, i64, dp, dp]),
+        "fdlb_last_residual": (C.c_int, [vp, dp, C.POINTER(i64)]),
+        "fdlb_solve_steady": (C.c_int, [vp, C.c_double, i64, i32, i32, C.POINTER(Report)]),
+        "fdlb_moments": (C.c_int, [vp, dp, dp, dp, dp]),
+        "fdlb_wall_profile": (C.c_int, [vp, C.c_int, dp, dp, dp]),
+        "fdlb_tile_count": (C.c_int, [C.c_int]),
+        "fdlb_tile_describe": (C.c_int, [C.c_int, C.c_int, C.c_char_p, C.c_size_t]),
+        "fdlb_problem_set_tile": (C.c_int, [vp, C.c_int]),
+        "fdlb_problem_get_tile": (C.c_int, [vp]),
+        "fdlb_autotune": (C.c_int, [vp, C.c_int, dp]),
+        "fdlb_stream_copy": (C.c_int, [vp, vp, C.c_size_t, vp]),
+        "fdlb_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def check(code: int, allow=(OK,)) -> int:
+    if code in allow:
+        return code
+    raise FdlbError(code, lib.fdlb_last_error().decode())
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def quad_half_range(n: int):
+    x, w = np.empty(2 * n), np.empty(2 * n)
+    check(lib.fdlb_quad_half_range(n, _dp(x), _dp(w)))
+    return x, w
+
+
+def quad_full_range(n: int):
+    x, w = np.empty(n), np.empty(n)
+    check(lib.fdlb_quad_full_range(n, _dp(x), _dp(w)))
+    return x, w
+
+
+def make_desc(nx, ny, periodic_x, periodic_y, wall_u, kn, qx, qy, cfl=0.9, precision="fp32",
+              allow_unstable=False) -> ProblemDesc:
+    kinds = {"half": HALF, "full": FULL}
+    d = ProblemDesc()
+    d.nx, d.ny = int(nx), int(ny)
+    d.periodic_x, d.periodic_y = int(bool(periodic_x)), int(bool(periodic_y))
+    d.wall_u = (C.c_double * 4)(*[float(v) for v in wall_u])
+    d.kn = float(kn)
+    d.cfl = float(cfl)
+    d.qx_kind, d.qx_n = kinds[qx[0]], int(qx[1])
+    d.qy_kind, d.qy_n = kinds[qy[0]], int(qy[1])
+    d.precision = FP32 if precision == "fp32" else FP64
+    d.allow_unstable = int(bool(allow_unstable))
+    return d
+
+
+def desc_from_case(case, precision: Optional[str] = None, allow_unstable=False) -> ProblemDesc:
+    return make_desc(case.nx, case.ny, case.periodic_x, case.periodic_y, case.wall_u, case.kn,
+                     case.qx, case.qy, case.cfl, precision or case.precision, allow_unstable)
+
+
+def tile_count(precision: str) -> int:
+    return check(lib.fdlb_tile_count(FP32 if precision == "fp32" else FP64), allow=range(0, 1 << 20))
+
+
+def tile_describe(precision: str, tile: int) -> str:
+    buf = C.create_string_buffer(128)
+    check(lib.fdlb_tile_describe(FP32 if precision == "fp32" else FP64, tile, buf, 128))
+    return buf.value.decode()

@@ -1,0 +1,160 @@
+// Internal declarations of libfdlb (host structures, device argument blocks,
+// kernel launchers).  Not part of the public ABI (include/fdlb.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <tuple>
+#include <string>
+#include <vector>
+
+#include "../../include/fdlb.h"
+
+namespace fdlb {
+
+struct Error {
+    int code;
+    std::string msg;
+    Error(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+void hip_check(hipError_t e, const char* what);
+#define FDLB_HIP(call) ::fdlb::hip_check((call), #call)
+
+void quad_half_range(int n, double* nodes, double* weights);
+void quad_full_range(int n, double* nodes, double* weights);
+
+enum { BOTTOM = 0, TOP = 1, LEFT = 2, RIGHT = 3 };
+
+// Per-velocity constants, grouped by quadrant (sign of xi_x, sign of xi_y).
+// ow* = omega * w-terms (relaxation), w* = w-terms (wall emission).
+template <class T>
+struct VelEntry {
+    T ow, owx, owy;   // omega w, omega w xi_x, omega w xi_y
+    T w, wx, wy;      // w, w xi_x, w xi_y
+    T xx, xy;         // xi_x, xi_y
+    T nux, nuy;       // dt |xi_x| N_x, dt |xi_y| N_y (0 along a periodic single-cell axis)
+    int32_t alpha;    // plane index of this velocity in the state
+    int32_t pad[3];
+};
+
+// Per-wall constants of Eq. (9) in deviation form (double).  For the wall's
+// inward normal n and tangent t, over the arriving half (xi . n < 0):
+// A = sum |xi_n| w, Bn = sum |xi_n| w xi_n, Bt = sum |xi_n| w xi_t, and
+// c0 = sqrt(2 pi) A - 1 (zero in exact arithmetic).
+struct WallConst {
+    double A, Bn, Bt, c0, u;
+    int32_t active;
+    int32_t pad;
+};
+
+// Everything the step kernel needs, passed by value.
+template <class T>
+struct StepArgs {
+    const T* src;
+    T* dst;
+    const T* mom_in;      // [3][ny][nx]: sum h, sum xi_x h, sum xi_y h of src
+    T* mom_out;           // same for dst
+    const double* phi_in; // [4][L]: sum over arriving half of |xi_n| h at each wall cell of src
+    double* phi_out;
+    double* partials;     // [nblocks][3]: sum |du|^2, sum |u|^2, max |u|^2
+    const VelEntry<T>* vel;
+    int32_t quad_begin[5];
+    int32_t nx, ny, L;
+    int32_t tiles_x, tiles_y;
+    int32_t pad0;
+    int64_t plane;        // nx * ny
+    T c1;                 // 1 - omega
+    T pad1;
+    WallConst wall[4];
+};
+
+// A compiled tile shape of the step kernel.
+struct TileShape {
+    int vx;    // cells per lane along x (vector width)
+    int lx;    // lanes along x in a wave (64 / lx lanes along y)
+    int k;     // rows per lane
+    int wpb;   // waves per block (stacked along y)
+    int tile_w() const { return vx * lx; }
+    int tile_h() const { return (64 / lx) * k * wpb; }
+};
+
+const std::vector<TileShape>& tile_shapes(int precision);
+bool tile_fits(const TileShape& t, int nx, int ny, bool periodic_x, bool periodic_y);
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return immediately.
+template <class T>
+void launch_step(int tile, const StepArgs<T>& a, int nblocks, hipStream_t stream);
+void launch_reduce(const double* partials, int nblocks, double* ctrl, int64_t inc, hipStream_t stream);
+template <class T>
+void launch_seed(T* h, int q, int64_t plane, const VelEntry<double>* vel, const double* rho,
+                 const double* ux, const double* uy, const float* frho, const float* fux,
+                 const float* fuy, const double* mass_scale, hipStream_t stream);
+template <class T>
+void launch_moments(const T* h, T* mom, double* phi, const VelEntry<double>* vel, int q, int nx, int ny,
+                    int L, const WallConst* d_wall, hipStream_t stream);
+template <class T>
+void launch_post(const T* h, const VelEntry<double>* vel, int q, int nx, int ny, double omega,
+                 double* out /* [4][ny][nx] */, hipStream_t stream);
+template <class T>
+void launch_wall_profile(const T* h, const VelEntry<double>* vel, int q, int nx, int ny, int wall,
+                         const WallConst* host_wc, double omega, double* out /* [3][n] */,
+                         hipStream_t stream);
+// Planes [a0, a1) of the state <-> raw populations f = w + h in a compact double buffer.
+template <class T>
+void launch_to_raw(const T* h, const double* w_nat, int a0, int a1, int64_t plane, double* f,
+                   hipStream_t stream);
+template <class T>
+void launch_from_raw(const double* f, const double* w_nat, int a0, int a1, int64_t plane, T* h,
+                     hipStream_t stream);
+void launch_mass_scale(const float* frho, int64_t cells, double* scale_out, hipStream_t stream);
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+// Control block layout (doubles) written by the reduce kernel.
+enum CtrlSlot {
+    CTRL_STEP = 0,        // steps since init (stored as double, exact below 2^53)
+    CTRL_LAST_R = 1,      // residual of the last reduced step
+    CTRL_FIRST_BELOW = 2, // step count when R first fell below tol, -1 if never
+    CTRL_DIVERGED = 3,    // step count of the first non-finite / runaway step, -1 if none
+    CTRL_MAXU = 4,        // max |u| of the last step
+    CTRL_TOL = 5,         // tolerance the reduce kernel compares against
+    CTRL_RING = 8,        // ring of residuals, CTRL_RING_LEN entries
+};
+constexpr int CTRL_RING_LEN = 4096;
+constexpr int CTRL_DOUBLES = CTRL_RING + CTRL_RING_LEN;
+
+}  // namespace fdlb
+
+// ---- the opaque handles -------------------------------------------------------
+struct fdlb_problem {
+    fdlb_problem_desc d{};
+    int q = 0;
+    std::vector<double> xi_x, xi_y, w;     // velocity order of the ABI
+    double dt = 0, omega = 0;
+    double nux_scale = 0, nuy_scale = 0;   // N along a bounded axis, 0 along a periodic single-cell one
+    fdlb::WallConst wall[4]{};
+    int32_t quad_begin[5]{};
+    std::vector<int> quad_order;           // velocity index of each table entry (quadrant-grouped)
+    int L = 0;                             // max(nx, ny): stride of the per-wall arrays
+    int64_t plane = 0;                     // nx * ny
+    size_t elem = 0;                       // bytes per stored population (4 or 8)
+    // layout (byte offsets into the state / workspace)
+    size_t pop_bytes = 0, state_bytes = 0, work_bytes = 0;
+    size_t off_mom = 0, mom_bytes = 0, off_phi = 0, phi_bytes = 0, off_part = 0, off_ctrl = 0,
+           off_vel = 0, off_vel64 = 0, off_wall = 0, off_wnat = 0, off_io = 0, io_bytes = 0;
+    int max_blocks = 0;
+    int tile = -1;                         // tile shape in use
+    // binding
+    char* d_state = nullptr;
+    char* d_work = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    bool seeded = false;
+    int parity = 0;                        // population buffer holding the current state
+    double* pinned = nullptr;              // small pinned host buffer for control reads
+    // captured graphs keyed by (steps per replay, tile, starting parity)
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+    ~fdlb_problem();
+};

@@ -1,0 +1,817 @@
+// Device kernels of libfdlb for gfx950 (CDNA4, wave64).
+//
+// State: populations in structure-of-arrays planes h[alpha][y][x].  The FP64
+// path stores h = f_alpha - w_alpha in double, the FP32 path in float; the
+// change of variable is exact because the scheme is linear and the rest
+// state f_alpha = w_alpha is a fixed point of it (Eqs. 1, 5, 8-9).
+//
+// One time step (the fully discrete scheme: explicit-Euler relaxation, then
+// first-order upwind transport) is ONE pass of step_kernel over the state:
+// every population is read once and written once.  The relaxation needs the
+// density and momentum of each cell over all velocities (Eqs. 6-7), and the
+// wall emission needs the impermeability sum of Eq. (9) over the arriving
+// half of the wall cell's relaxed populations; both are accumulated while
+// the previous step writes its output and read back at the start of the
+// next, so no second pass over the state is needed:
+//   sum over arriving xi of |xi_n| g = (1-omega) Phi + omega (rho_h A + j_n Bn + j_t Bt)
+// with Phi the same sum over h (kept in double) and A, Bn, Bt constants of
+// the velocity set.
+//
+// Work decomposition: a wave owns a tile of (LX*VX) x (LY*K) cells (LX lanes
+// along x, LY = 64/LX along y, each lane VX consecutive cells of K rows) and
+// loops over all velocities, quadrant by quadrant (signs of xi_x, xi_y are
+// then compile-time constants).  The upwind neighbour of a cell is in the
+// same lane's registers, in a neighbouring lane (cross-lane shuffle of the
+// relaxed value), in a halo cell outside the wave (loaded and relaxed by the
+// edge lane), or the wall emission of Eq. (8).  Blocks are mapped to tiles
+// so that each of the 8 XCDs owns a contiguous band of tile rows (its own
+// L2 then serves the halo rows shared between vertically adjacent tiles).
+#include <type_traits>
+
+#include "fdlb_internal.h"
+
+namespace fdlb {
+
+namespace {
+
+constexpr double SQRT_2PI = 2.50662827463100050241576528481104525;
+constexpr int NUM_XCD = 8;
+
+enum : int { MODE_SHUF = 0, MODE_LOAD = 1, MODE_WALL = 2 };
+
+// Tile index of a block so that XCD k (blocks b with b % 8 == k) owns tiles
+// [start_k, start_k + count_k): hardware dispatches blocks round-robin over XCDs.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int k = b % NUM_XCD, i = b / NUM_XCD;
+    const int q = nb / NUM_XCD, r = nb % NUM_XCD;
+    return k * q + (k < r ? k : r) + i;
+}
+
+template <int N, class T>
+__device__ __forceinline__ void vload(T (&dst)[N], const T* p) {
+    if constexpr (N == 1) {
+        dst[0] = p[0];
+    } else {
+        typedef T V __attribute__((ext_vector_type(N)));
+        const V v = *reinterpret_cast<const V*>(p);
+#pragma unroll
+        for (int i = 0; i < N; ++i) dst[i] = v[i];
+    }
+}
+
+template <int N, class T>
+__device__ __forceinline__ void vstore(T* p, const T (&src)[N]) {
+    if constexpr (N == 1) {
+        p[0] = src[0];
+    } else {
+        typedef T V __attribute__((ext_vector_type(N)));
+        V v;
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = src[i];
+        *reinterpret_cast<V*>(p) = v;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The fused time step.
+// ---------------------------------------------------------------------------
+template <class T, int VX, int K, int LX, int WPB>
+__global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
+    constexpr int LY = 64 / LX;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lx = lane % LX, ly = lane / LX;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
+    const int nx = A.nx, ny = A.ny, L = A.L;
+    const int64_t plane = A.plane;
+    const int x0 = tx * (LX * VX) + lx * VX;
+    const int y0 = ((ty * WPB + wave) * LY + ly) * K;
+    const bool xv = x0 < nx;
+    const T c1 = A.c1;
+
+    bool rv[K];  // row r of this lane is a cell of the grid
+#pragma unroll
+    for (int r = 0; r < K; ++r) rv[r] = xv && (y0 + r < ny);
+
+    // Density and momentum (deviation form) of this lane's cells, from the previous step.
+    T mr[K][VX], mx[K][VX], my[K][VX];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        if (rv[r]) {
+            const int64_t o = (int64_t)(y0 + r) * nx + x0;
+            vload<VX>(mr[r], A.mom_in + o);
+            vload<VX>(mx[r], A.mom_in + plane + o);
+            vload<VX>(my[r], A.mom_in + 2 * plane + o);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) mr[r][v] = mx[r][v] = my[r][v] = T(0);
+        }
+    }
+
+    // Wall emission parameters of this step (Eqs. 8-9): rho_w - 1 and u_w rho_w per wall face.
+    const double omega = 1.0 - (double)c1;
+    const bool on_left = xv && x0 == 0 && A.wall[LEFT].active;
+    const bool on_right = xv && (x0 + VX == nx) && A.wall[RIGHT].active;
+    const bool on_bot = xv && y0 == 0 && A.wall[BOTTOM].active;
+    const int r_top = ny - 1 - y0;
+    const bool on_top = xv && r_top >= 0 && r_top < K && A.wall[TOP].active;
+    const int xw = on_left ? LEFT : RIGHT;
+    const int yw = on_bot ? BOTTOM : TOP;
+
+    T Px[K], Qx[K];
+    double phx[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        Px[r] = Qx[r] = T(0);
+        phx[r] = 0.0;
+    }
+    if (on_left || on_right) {
+        const WallConst W = A.wall[xw];
+        const int vi = on_left ? 0 : VX - 1;
+        const double sn = on_left ? 1.0 : -1.0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (rv[r]) {
+                const double phi = A.phi_in[xw * L + y0 + r];
+                const double s = (1.0 - omega) * phi +
+                                 omega * ((double)mr[r][vi] * W.A + sn * (double)mx[r][vi] * W.Bn +
+                                          (double)my[r][vi] * W.Bt);
+                const double P = W.c0 + SQRT_2PI * s;
+                Px[r] = (T)P;
+                Qx[r] = (T)(W.u * (1.0 + P));
+            }
+        }
+    }
+    T Py[VX], Qy[VX];
+    double phy[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        Py[v] = Qy[v] = T(0);
+        phy[v] = 0.0;
+    }
+    if (on_bot || on_top) {
+        const WallConst W = A.wall[yw];
+        const double sn = on_bot ? 1.0 : -1.0;
+        const int rw = on_bot ? 0 : r_top;
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            T wr = T(0), wx = T(0), wy = T(0);
+#pragma unroll
+            for (int r = 0; r < K; ++r)
+                if (r == rw) {
+                    wr = mr[r][v];
+                    wx = mx[r][v];
+                    wy = my[r][v];
+                }
+            const double phi = A.phi_in[yw * L + x0 + v];
+            const double s = (1.0 - omega) * phi +
+                             omega * ((double)wr * W.A + sn * (double)wy * W.Bn + (double)wx * W.Bt);
+            const double P = W.c0 + SQRT_2PI * s;
+            Py[v] = (T)P;
+            Qy[v] = (T)(W.u * (1.0 + P));
+        }
+    }
+    const int r_top_in = (r_top >= 0 && r_top < K - 1) ? r_top : -1;
+
+    // Moments of the new state, accumulated over all velocities.
+    T ar[K][VX], ax[K][VX], ay[K][VX];
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int v = 0; v < VX; ++v) ar[r][v] = ax[r][v] = ay[r][v] = T(0);
+
+    auto quadrant = [&](auto sxc, auto syc, const int qb, const int qe) {
+        constexpr int SX = decltype(sxc)::value;
+        constexpr int SY = decltype(syc)::value;
+        // Where the lane-boundary cell's upwind neighbour comes from.
+        int xmode, xh;
+        if constexpr (SX > 0) {
+            xh = x0 - 1;
+            xmode = (x0 == 0) ? MODE_WALL : (lx > 0 ? MODE_SHUF : MODE_LOAD);
+        } else {
+            xh = x0 + VX;
+            xmode = (x0 + VX >= nx) ? MODE_WALL : (lx < LX - 1 ? MODE_SHUF : MODE_LOAD);
+        }
+        int ymode, yh;
+        if constexpr (SY > 0) {
+            yh = y0 - 1;
+            ymode = (y0 == 0) ? MODE_WALL : (ly > 0 ? MODE_SHUF : MODE_LOAD);
+        } else {
+            yh = y0 + K;
+            ymode = (y0 + K >= ny) ? MODE_WALL : (ly < LY - 1 ? MODE_SHUF : MODE_LOAD);
+        }
+        // A lane with no cell of the grid loads nothing (its halo may lie outside the grid).
+        if (!xv || y0 >= ny) xmode = ymode = MODE_WALL;
+        // Moments of the halo cells this lane relaxes itself.
+        T hxr[K], hxx[K], hxy[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            hxr[r] = hxx[r] = hxy[r] = T(0);
+            if (xmode == MODE_LOAD && rv[r]) {
+                const int64_t o = (int64_t)(y0 + r) * nx + xh;
+                hxr[r] = A.mom_in[o];
+                hxx[r] = A.mom_in[plane + o];
+                hxy[r] = A.mom_in[2 * plane + o];
+            }
+        }
+        T hyr[VX], hyx[VX], hyy[VX];
+        if (ymode == MODE_LOAD) {
+            const int64_t o = (int64_t)yh * nx + x0;
+            vload<VX>(hyr, A.mom_in + o);
+            vload<VX>(hyx, A.mom_in + plane + o);
+            vload<VX>(hyy, A.mom_in + 2 * plane + o);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) hyr[v] = hyx[v] = hyy[v] = T(0);
+        }
+
+        for (int e = qb; e < qe; ++e) {
+            const VelEntry<T> c = A.vel[e];
+            const T* __restrict__ s = A.src + (int64_t)c.alpha * plane;
+            T* __restrict__ d = A.dst + (int64_t)c.alpha * plane;
+
+            T g[K][VX];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                if (rv[r]) {
+                    vload<VX>(g[r], s + (int64_t)(y0 + r) * nx + x0);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) g[r][v] = T(0);
+                }
+            }
+            T gxh[K];
+#pragma unroll
+            for (int r = 0; r < K; ++r)
+                gxh[r] = (xmode == MODE_LOAD && rv[r]) ? s[(int64_t)(y0 + r) * nx + xh] : T(0);
+            T gyh[VX];
+            if (ymode == MODE_LOAD) {
+                vload<VX>(gyh, s + (int64_t)yh * nx + x0);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VX; ++v) gyh[v] = T(0);
+            }
+
+            // Relaxation (explicit Euler of Eq. 1 towards Eq. 5, deviation form).
+#pragma unroll
+            for (int r = 0; r < K; ++r)
+#pragma unroll
+                for (int v = 0; v < VX; ++v)
+                    g[r][v] = c1 * g[r][v] + (c.ow * mr[r][v] + c.owx * mx[r][v] + c.owy * my[r][v]);
+#pragma unroll
+            for (int r = 0; r < K; ++r) gxh[r] = c1 * gxh[r] + (c.ow * hxr[r] + c.owx * hxx[r] + c.owy * hxy[r]);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) gyh[v] = c1 * gyh[v] + (c.ow * hyr[v] + c.owx * hyx[v] + c.owy * hyy[v]);
+
+            // Upwind values across the lane boundary: neighbour lane, halo, or wall emission.
+            T xb[K];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const T sh = __shfl(g[r][SX > 0 ? VX - 1 : 0], lane - SX, 64);
+                const T em = c.w * Px[r] + c.wy * Qx[r];
+                xb[r] = xmode == MODE_SHUF ? sh : (xmode == MODE_LOAD ? gxh[r] : em);
+            }
+            T yb[VX];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const T sh = __shfl(g[SY > 0 ? K - 1 : 0][v], lane - SY * LX, 64);
+                const T em = c.w * Py[v] + c.wx * Qy[v];
+                yb[v] = ymode == MODE_SHUF ? sh : (ymode == MODE_LOAD ? gyh[v] : em);
+            }
+
+            // First-order upwind transport.
+            T fn[K][VX];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    const T gc = g[r][v];
+                    T gx, gy;
+                    if constexpr (SX > 0) gx = (v > 0) ? g[r][v - 1] : xb[r];
+                    else gx = (v < VX - 1) ? g[r][v + 1] : xb[r];
+                    if constexpr (SY > 0) {
+                        gy = (r > 0) ? g[r - 1][v] : yb[v];
+                    } else {
+                        gy = (r < K - 1) ? g[r + 1][v] : yb[v];
+                        if (r == r_top_in) gy = c.w * Py[v] + c.wx * Qy[v];
+                    }
+                    fn[r][v] = gc - c.nux * (gc - gx) - c.nuy * (gc - gy);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < K; ++r)
+                if (rv[r]) vstore<VX>(d + (int64_t)(y0 + r) * nx + x0, fn[r]);
+
+            // Moments (Eqs. 6-7) and wall fluxes of the new state.
+#pragma unroll
+            for (int r = 0; r < K; ++r)
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    ar[r][v] += fn[r][v];
+                    ax[r][v] += c.xx * fn[r][v];
+                    ay[r][v] += c.xy * fn[r][v];
+                }
+            if constexpr (SX < 0) {
+                if (on_left) {
+#pragma unroll
+                    for (int r = 0; r < K; ++r) phx[r] += -(double)c.xx * (double)fn[r][0];
+                }
+            } else {
+                if (on_right) {
+#pragma unroll
+                    for (int r = 0; r < K; ++r) phx[r] += (double)c.xx * (double)fn[r][VX - 1];
+                }
+            }
+            if constexpr (SY < 0) {
+                if (on_bot) {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) phy[v] += -(double)c.xy * (double)fn[0][v];
+                }
+            } else {
+                if (on_top) {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        T t = T(0);
+#pragma unroll
+                        for (int r = 0; r < K; ++r)
+                            if (r == r_top) t = fn[r][v];
+                        phy[v] += (double)c.xy * (double)t;
+                    }
+                }
+            }
+        }
+    };
+
+    quadrant(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{}, A.quad_begin[0],
+             A.quad_begin[1]);
+    quadrant(std::integral_constant<int, -1>{}, std::integral_constant<int, 1>{}, A.quad_begin[1],
+             A.quad_begin[2]);
+    quadrant(std::integral_constant<int, 1>{}, std::integral_constant<int, -1>{}, A.quad_begin[2],
+             A.quad_begin[3]);
+    quadrant(std::integral_constant<int, -1>{}, std::integral_constant<int, -1>{}, A.quad_begin[3],
+             A.quad_begin[4]);
+
+    // Outputs for the next step.
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        if (rv[r]) {
+            const int64_t o = (int64_t)(y0 + r) * nx + x0;
+            vstore<VX>(A.mom_out + o, ar[r]);
+            vstore<VX>(A.mom_out + plane + o, ax[r]);
+            vstore<VX>(A.mom_out + 2 * plane + o, ay[r]);
+        }
+    }
+    if (on_left || on_right) {
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            if (rv[r]) A.phi_out[xw * L + y0 + r] = phx[r];
+    }
+    if (on_bot || on_top) {
+#pragma unroll
+        for (int v = 0; v < VX; ++v) A.phi_out[yw * L + x0 + v] = phy[v];
+    }
+
+    // Residual partials: sum |u_new - u_old|^2, sum |u_new|^2, max |u_new|^2.
+    double num = 0.0, den = 0.0, umax = 0.0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        if (rv[r]) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const double r0 = 1.0 + (double)mr[r][v];
+                const double ux0 = (double)mx[r][v] / r0, uy0 = (double)my[r][v] / r0;
+                const double r1 = 1.0 + (double)ar[r][v];
+                const double ux1 = (double)ax[r][v] / r1, uy1 = (double)ay[r][v] / r1;
+                const double dx = ux1 - ux0, dy = uy1 - uy0;
+                const double u2 = ux1 * ux1 + uy1 * uy1;
+                num += dx * dx + dy * dy;
+                den += u2;
+                umax = fmax(umax, u2);
+            }
+        }
+    }
+    num = wave_sum(num);
+    den = wave_sum(den);
+    umax = wave_max(umax);
+    __shared__ double red[WPB][3];
+    if (lane == 0) {
+        red[wave][0] = num;
+        red[wave][1] = den;
+        red[wave][2] = umax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0, m = 0;
+#pragma unroll
+        for (int w = 0; w < WPB; ++w) {
+            a += red[w][0];
+            b += red[w][1];
+            m = fmax(m, red[w][2]);
+        }
+        A.partials[3 * blockIdx.x + 0] = a;
+        A.partials[3 * blockIdx.x + 1] = b;
+        A.partials[3 * blockIdx.x + 2] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Residual: second stage of the reduction, and the step bookkeeping.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ partials, int nblocks,
+                                                     double* __restrict__ ctrl, int64_t inc) {
+    __shared__ double s[3][256];
+    double a = 0, b = 0, m = 0;
+    for (int i = threadIdx.x; i < nblocks; i += 256) {
+        a += partials[3 * i];
+        b += partials[3 * i + 1];
+        m = fmax(m, partials[3 * i + 2]);
+    }
+    s[0][threadIdx.x] = a;
+    s[1][threadIdx.x] = b;
+    s[2][threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + o];
+            s[1][threadIdx.x] += s[1][threadIdx.x + o];
+            s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double num = s[0][0], den = s[1][0], umax2 = s[2][0];
+        double R;
+        if (den > 0.0) R = sqrt(num / den);
+        else R = (num > 0.0) ? __builtin_huge_val() : 0.0;
+        const double step = ctrl[CTRL_STEP] + (double)inc;
+        ctrl[CTRL_STEP] = step;
+        ctrl[CTRL_LAST_R] = R;
+        ctrl[CTRL_MAXU] = sqrt(umax2);
+        ctrl[CTRL_RING + ((int64_t)step - 1) % CTRL_RING_LEN] = R;
+        if (R < ctrl[CTRL_TOL] && ctrl[CTRL_FIRST_BELOW] < 0.0) ctrl[CTRL_FIRST_BELOW] = step;
+        const bool bad = !(R <= 1e300) || !(umax2 <= 0.25);
+        if (bad && ctrl[CTRL_DIVERGED] < 0.0) ctrl[CTRL_DIVERGED] = step;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Seeding at equilibrium: h_alpha = w_alpha (rho - 1 + xi_alpha . rho u) (Eqs. 3, 5).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) seed_kernel(T* __restrict__ h, int q, int64_t plane,
+                                                   const VelEntry<double>* __restrict__ vel,
+                                                   const double* rho, const double* ux, const double* uy,
+                                                   const float* frho, const float* fux, const float* fuy,
+                                                   const double* mass_scale) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= plane) return;
+    double r = 1.0, u = 0.0, w = 0.0;
+    if (rho) r = rho[c];
+    else if (frho) r = (double)frho[c];
+    if (ux) u = ux[c];
+    else if (fux) u = (double)fux[c];
+    if (uy) w = uy[c];
+    else if (fuy) w = (double)fuy[c];
+    if (mass_scale) r *= *mass_scale;
+    const double jx = r * u, jy = r * w, rh = r - 1.0;
+    for (int e = 0; e < q; ++e) {
+        const VelEntry<double> v = vel[e];
+        h[(int64_t)v.alpha * plane + c] = (T)(v.w * rh + v.wx * jx + v.wy * jy);
+    }
+}
+
+// Sum of a float array of cells, and the factor that brings it to `cells`.
+__global__ void __launch_bounds__(1024) mass_scale_kernel(const float* __restrict__ rho, int64_t cells,
+                                                          double* __restrict__ out) {
+    __shared__ double s[1024];
+    double a = 0;
+    for (int64_t i = threadIdx.x; i < cells; i += 1024) a += (double)rho[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = (double)cells / s[0];
+}
+
+// ---------------------------------------------------------------------------
+// Moments and wall fluxes of a state (after seeding or upload).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) moments_kernel(const T* __restrict__ h, T* __restrict__ mom,
+                                                      double* __restrict__ phi,
+                                                      const VelEntry<double>* __restrict__ vel, int q,
+                                                      int nx, int ny, int L, const WallConst* wall) {
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= plane) return;
+    const int x = (int)(c % nx), y = (int)(c / nx);
+    double r = 0, jx = 0, jy = 0, pb = 0, pt = 0, pl = 0, pr = 0;
+    for (int e = 0; e < q; ++e) {
+        const VelEntry<double> v = vel[e];
+        const double f = (double)h[(int64_t)v.alpha * plane + c];
+        r += f;
+        jx += v.xx * f;
+        jy += v.xy * f;
+        if (v.xy < 0) pb += -v.xy * f;
+        if (v.xy > 0) pt += v.xy * f;
+        if (v.xx < 0) pl += -v.xx * f;
+        if (v.xx > 0) pr += v.xx * f;
+    }
+    mom[c] = (T)r;
+    mom[plane + c] = (T)jx;
+    mom[2 * plane + c] = (T)jy;
+    if (wall[BOTTOM].active && y == 0) phi[BOTTOM * L + x] = pb;
+    if (wall[TOP].active && y == ny - 1) phi[TOP * L + x] = pt;
+    if (wall[LEFT].active && x == 0) phi[LEFT * L + y] = pl;
+    if (wall[RIGHT].active && x == nx - 1) phi[RIGHT * L + y] = pr;
+}
+
+// ---------------------------------------------------------------------------
+// Output fields: rho, u (Eqs. 6-7) and the xy stress of the relaxed state.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) post_kernel(const T* __restrict__ h,
+                                                   const VelEntry<double>* __restrict__ vel, int q,
+                                                   int nx, int ny, double omega, double* __restrict__ out) {
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= plane) return;
+    double r = 0, jx = 0, jy = 0;
+    for (int e = 0; e < q; ++e) {
+        const VelEntry<double> v = vel[e];
+        const double f = (double)h[(int64_t)v.alpha * plane + c];
+        r += f;
+        jx += v.xx * f;
+        jy += v.xy * f;
+    }
+    double pxy = 0;
+    for (int e = 0; e < q; ++e) {
+        const VelEntry<double> v = vel[e];
+        const double f = (double)h[(int64_t)v.alpha * plane + c];
+        const double g = (1.0 - omega) * f + omega * (v.w * r + v.wx * jx + v.wy * jy);
+        pxy += v.xx * v.xy * g;
+    }
+    const double rho = 1.0 + r;
+    out[c] = rho;
+    out[plane + c] = jx / rho;
+    out[2 * plane + c] = jy / rho;
+    out[3 * plane + c] = pxy;
+}
+
+// Face state along a wall: arriving/grazing populations from the wall cell's relaxed
+// values, leaving ones from the emission of Eq. (8) with rho_w of Eq. (9).
+template <class T>
+__global__ void __launch_bounds__(256) wall_profile_kernel(const T* __restrict__ h,
+                                                           const VelEntry<double>* __restrict__ vel, int q,
+                                                           int nx, int ny, int wall, WallConst wc,
+                                                           double omega, double* __restrict__ out) {
+    const int64_t plane = (int64_t)nx * ny;
+    const int n = (wall == BOTTOM || wall == TOP) ? nx : ny;
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= n) return;
+    int x, y;
+    if (wall == BOTTOM) { x = pos; y = 0; }
+    else if (wall == TOP) { x = pos; y = ny - 1; }
+    else if (wall == LEFT) { x = 0; y = pos; }
+    else { x = nx - 1; y = pos; }
+    const int64_t c = (int64_t)y * nx + x;
+    double r = 0, jx = 0, jy = 0;
+    for (int e = 0; e < q; ++e) {
+        const VelEntry<double> v = vel[e];
+        const double f = (double)h[(int64_t)v.alpha * plane + c];
+        r += f;
+        jx += v.xx * f;
+        jy += v.xy * f;
+    }
+    auto xn = [&](const VelEntry<double>& v) {
+        return wall == BOTTOM ? v.xy : wall == TOP ? -v.xy : wall == LEFT ? v.xx : -v.xx;
+    };
+    auto xt = [&](const VelEntry<double>& v) { return (wall == BOTTOM || wall == TOP) ? v.xx : v.xy; };
+    double s = 0;
+    for (int e = 0; e < q; ++e) {
+        const VelEntry<double> v = vel[e];
+        const double n_ = xn(v);
+        if (n_ < 0) {
+            const double f = (double)h[(int64_t)v.alpha * plane + c];
+            s += -n_ * ((1.0 - omega) * f + omega * (v.w * r + v.wx * jx + v.wy * jy));
+        }
+    }
+    const double P = wc.c0 + SQRT_2PI * s;  // rho_w - 1
+    double fr = 0, ft = 0, fp = 0;
+    for (int e = 0; e < q; ++e) {
+        const VelEntry<double> v = vel[e];
+        double graw;
+        if (xn(v) > 0) {
+            graw = v.w * (1.0 + P) * (1.0 + xt(v) * wc.u);
+        } else {
+            const double f = (double)h[(int64_t)v.alpha * plane + c];
+            graw = v.w + (1.0 - omega) * f + omega * (v.w * r + v.wx * jx + v.wy * jy);
+        }
+        fr += graw;
+        ft += xt(v) * graw;
+        fp += v.xx * v.xy * graw;
+    }
+    out[pos] = fr;
+    out[n + pos] = ft / fr;
+    out[2 * n + pos] = fp;
+}
+
+// Raw populations <-> stored deviations, for planes [a0, a1) through a compact buffer.
+template <class T>
+__global__ void __launch_bounds__(256) to_raw_kernel(const T* __restrict__ h, const double* __restrict__ w_nat,
+                                                     int a0, int a1, int64_t plane, double* __restrict__ f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= plane * (a1 - a0)) return;
+    const int a = a0 + (int)(i / plane);
+    f[i] = w_nat[a] + (double)h[(int64_t)a * plane + i % plane];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) from_raw_kernel(const double* __restrict__ f,
+                                                       const double* __restrict__ w_nat, int a0, int a1,
+                                                       int64_t plane, T* __restrict__ h) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= plane * (a1 - a0)) return;
+    const int a = a0 + (int)(i / plane);
+    h[(int64_t)a * plane + i % plane] = (T)(f[i] - w_nat[a]);
+}
+
+// Streaming copy (16-byte vectors, grid-stride) for the bandwidth ceiling.
+__global__ void __launch_bounds__(256) copy_kernel(float4* __restrict__ dst, const float4* __restrict__ src,
+                                                   int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+__global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict__ src, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Tile shapes and launchers.
+// ---------------------------------------------------------------------------
+#define FDLB_TILES_FP32(X)   \
+    X(0, float, 4, 2, 64, 4) \
+    X(1, float, 4, 2, 16, 4) \
+    X(2, float, 4, 2, 32, 4) \
+    X(3, float, 4, 1, 64, 4) \
+    X(4, float, 4, 4, 16, 2) \
+    X(5, float, 2, 4, 64, 4) \
+    X(6, float, 1, 4, 64, 4) \
+    X(7, float, 1, 4, 1, 1)  \
+    X(8, float, 1, 2, 16, 1) \
+    X(9, float, 4, 1, 16, 4) \
+    X(10, float, 1, 1, 16, 1)
+
+#define FDLB_TILES_FP64(X)    \
+    X(0, double, 2, 2, 64, 4) \
+    X(1, double, 2, 2, 16, 4) \
+    X(2, double, 2, 2, 32, 4) \
+    X(3, double, 1, 2, 64, 4) \
+    X(4, double, 1, 4, 1, 1)  \
+    X(5, double, 1, 2, 16, 1) \
+    X(6, double, 2, 1, 64, 4) \
+    X(7, double, 1, 1, 16, 1)
+
+const std::vector<TileShape>& tile_shapes(int precision) {
+#define FDLB_SHAPE(id, T, VX, K, LX, WPB) TileShape{VX, LX, K, WPB},
+    static const std::vector<TileShape> s32 = {FDLB_TILES_FP32(FDLB_SHAPE)};
+    static const std::vector<TileShape> s64 = {FDLB_TILES_FP64(FDLB_SHAPE)};
+#undef FDLB_SHAPE
+    return precision == FDLB_FP32 ? s32 : s64;
+}
+
+template <>
+void launch_step<float>(int tile, const StepArgs<float>& a, int nblocks, hipStream_t stream) {
+    switch (tile) {
+#define FDLB_CASE(id, T, VX, K, LX, WPB) \
+    case id: hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB>), dim3(nblocks), dim3(64 * WPB), 0, stream, a); break;
+        FDLB_TILES_FP32(FDLB_CASE)
+#undef FDLB_CASE
+        default: throw Error(FDLB_EINVAL, "unknown tile shape");
+    }
+    FDLB_HIP(hipGetLastError());
+}
+
+template <>
+void launch_step<double>(int tile, const StepArgs<double>& a, int nblocks, hipStream_t stream) {
+    switch (tile) {
+#define FDLB_CASE(id, T, VX, K, LX, WPB) \
+    case id: hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB>), dim3(nblocks), dim3(64 * WPB), 0, stream, a); break;
+        FDLB_TILES_FP64(FDLB_CASE)
+#undef FDLB_CASE
+        default: throw Error(FDLB_EINVAL, "unknown tile shape");
+    }
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_reduce(const double* partials, int nblocks, double* ctrl, int64_t inc, hipStream_t stream) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, stream, partials, nblocks, ctrl, inc);
+    FDLB_HIP(hipGetLastError());
+}
+
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <class T>
+void launch_seed(T* h, int q, int64_t plane, const VelEntry<double>* vel, const double* rho,
+                 const double* ux, const double* uy, const float* frho, const float* fux, const float* fuy,
+                 const double* mass_scale, hipStream_t stream) {
+    hipLaunchKernelGGL(seed_kernel<T>, dim3(blocks_for(plane, 256)), dim3(256), 0, stream, h, q, plane, vel,
+                       rho, ux, uy, frho, fux, fuy, mass_scale);
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_mass_scale(const float* frho, int64_t cells, double* scale_out, hipStream_t stream) {
+    hipLaunchKernelGGL(mass_scale_kernel, dim3(1), dim3(1024), 0, stream, frho, cells, scale_out);
+    FDLB_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_moments(const T* h, T* mom, double* phi, const VelEntry<double>* vel, int q, int nx, int ny,
+                    int L, const WallConst* wall, hipStream_t stream) {
+    hipLaunchKernelGGL(moments_kernel<T>, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, stream, h,
+                       mom, phi, vel, q, nx, ny, L, wall);
+    FDLB_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_post(const T* h, const VelEntry<double>* vel, int q, int nx, int ny, double omega, double* out,
+                 hipStream_t stream) {
+    hipLaunchKernelGGL(post_kernel<T>, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, stream, h, vel,
+                       q, nx, ny, omega, out);
+    FDLB_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_wall_profile(const T* h, const VelEntry<double>* vel, int q, int nx, int ny, int wall,
+                         const WallConst* wc, double omega, double* out, hipStream_t stream) {
+    const int n = (wall == BOTTOM || wall == TOP) ? nx : ny;
+    hipLaunchKernelGGL(wall_profile_kernel<T>, dim3(blocks_for(n, 256)), dim3(256), 0, stream, h, vel, q, nx,
+                       ny, wall, *wc, omega, out);
+    FDLB_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_to_raw(const T* h, const double* w_nat, int a0, int a1, int64_t plane, double* f,
+                   hipStream_t stream) {
+    hipLaunchKernelGGL(to_raw_kernel<T>, dim3(blocks_for(plane * (a1 - a0), 256)), dim3(256), 0, stream, h,
+                       w_nat, a0, a1, plane, f);
+    FDLB_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_from_raw(const double* f, const double* w_nat, int a0, int a1, int64_t plane, T* h,
+                     hipStream_t stream) {
+    hipLaunchKernelGGL(from_raw_kernel<T>, dim3(blocks_for(plane * (a1 - a0), 256)), dim3(256), 0, stream, f,
+                       w_nat, a0, a1, plane, h);
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 > 0) {
+        hipLaunchKernelGGL(copy_kernel, dim3(256 * 16), dim3(256), 0, stream, (float4*)dst, (const float4*)src,
+                           n16);
+        FDLB_HIP(hipGetLastError());
+    }
+    const int64_t tail = (int64_t)bytes - n16 * 16;
+    if (tail > 0) {
+        hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(16), 0, stream, (char*)dst + n16 * 16,
+                           (const char*)src + n16 * 16, tail);
+        FDLB_HIP(hipGetLastError());
+    }
+}
+
+#define FDLB_INST(T)                                                                                      \
+    template void launch_seed<T>(T*, int, int64_t, const VelEntry<double>*, const double*, const double*, \
+                                 const double*, const float*, const float*, const float*, const double*, \
+                                 hipStream_t);                                                            \
+    template void launch_moments<T>(const T*, T*, double*, const VelEntry<double>*, int, int, int, int,   \
+                                    const WallConst*, hipStream_t);                                       \
+    template void launch_post<T>(const T*, const VelEntry<double>*, int, int, int, double, double*,       \
+                                 hipStream_t);                                                            \
+    template void launch_wall_profile<T>(const T*, const VelEntry<double>*, int, int, int, int,           \
+                                         const WallConst*, double, double*, hipStream_t);                 \
+    template void launch_to_raw<T>(const T*, const double*, int, int, int64_t, double*, hipStream_t);     \
+    template void launch_from_raw<T>(const double*, const double*, int, int, int64_t, T*, hipStream_t);
+FDLB_INST(float)
+FDLB_INST(double)
+#undef FDLB_INST
+
+}  // namespace fdlb

@@ -1,0 +1,664 @@
+// Host runtime of libfdlb: problem set-up, device memory layout, binding,
+// initial states, time marching, steady solves and outputs.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "fdlb_internal.h"
+
+fdlb_problem::~fdlb_problem() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (pinned) (void)hipHostFree(pinned);
+}
+
+namespace fdlb {
+
+namespace {
+
+constexpr double SQRT_2PI = 2.50662827463100050241576528481104525;
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+void rule(int kind, int n, std::vector<double>& x, std::vector<double>& w) {
+    if (kind == FDLB_HALF) {
+        if (n < 1 || n > 16) throw Error(FDLB_EINVAL, "half-range rule needs 1..16 nodes per half");
+        x.resize(2 * n);
+        w.resize(2 * n);
+        quad_half_range(n, x.data(), w.data());
+    } else if (kind == FDLB_FULL) {
+        if (n < 1 || n > 32) throw Error(FDLB_EINVAL, "full-range rule needs 1..32 nodes");
+        x.resize(n);
+        w.resize(n);
+        quad_full_range(n, x.data(), w.data());
+    } else {
+        throw Error(FDLB_EINVAL, "quadrature kind must be FDLB_HALF or FDLB_FULL");
+    }
+}
+
+}  // namespace
+
+bool tile_fits(const TileShape& t, int nx, int ny, bool periodic_x, bool periodic_y) {
+    if (nx % t.vx) return false;
+    if (!periodic_x && t.vx >= nx) return false;  // one lane must not hold both x walls
+    if (!periodic_y && t.k >= ny) return false;   // nor both y walls
+    if (t.lx == 1 && nx != 1) return false;       // column tiles are for single-cell-wide grids
+    if (t.lx > 1 && nx == 1) return false;
+    return true;
+}
+
+static int heuristic_tile(const fdlb_problem& p) {
+    const auto& shapes = tile_shapes(p.d.precision);
+    int best = -1;
+    double best_score = 1e300;
+    int best_vx = 0;
+    for (size_t i = 0; i < shapes.size(); ++i) {
+        const TileShape& t = shapes[i];
+        if (!tile_fits(t, p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y)) continue;
+        if (t.vx > best_vx) {  // widest vectors first
+            best_vx = t.vx;
+            best_score = 1e300;
+        } else if (t.vx < best_vx) {
+            continue;
+        }
+        const int64_t tx = (p.d.nx + t.tile_w() - 1) / t.tile_w();
+        const int64_t ty = (p.d.ny + t.tile_h() - 1) / t.tile_h();
+        const double cover = (double)(tx * t.tile_w() * ty * t.tile_h()) / (double)p.plane;
+        const double blocks = (double)(tx * ty);
+        // idle lanes cost directly; fewer than ~2 blocks per CU leaves the chip half idle
+        const double score = cover * (blocks < 512 ? 1.0 + (512 - blocks) / 1024.0 : 1.0);
+        if (score < best_score - 1e-12) {
+            best_score = score;
+            best = (int)i;
+        }
+    }
+    if (best < 0) throw Error(FDLB_EINVAL, "no compiled tile shape fits this grid");
+    return best;
+}
+
+void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
+    if (d.nx < 1 || d.ny < 1) throw Error(FDLB_EINVAL, "nx and ny must be >= 1");
+    if ((int64_t)d.nx * d.ny > (int64_t)1 << 28) throw Error(FDLB_EINVAL, "grid too large");
+    if ((d.periodic_x && d.nx != 1) || (d.periodic_y && d.ny != 1))
+        throw Error(FDLB_EINVAL, "a periodic axis must have exactly one cell");
+    if (!d.periodic_x && d.nx < 2) throw Error(FDLB_EINVAL, "a bounded axis needs at least 2 cells");
+    if (!d.periodic_y && d.ny < 2) throw Error(FDLB_EINVAL, "a bounded axis needs at least 2 cells");
+    if (d.precision != FDLB_FP32 && d.precision != FDLB_FP64)
+        throw Error(FDLB_EINVAL, "precision must be FDLB_FP32 or FDLB_FP64");
+    if (!(d.cfl > 0) || !std::isfinite(d.cfl)) throw Error(FDLB_EINVAL, "cfl must be positive and finite");
+    if (!(d.kn > 0)) throw Error(FDLB_EINVAL, "kn must be positive (INFINITY allowed)");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(d.wall_u[i])) throw Error(FDLB_EINVAL, "wall speeds must be finite");
+    p.d = d;
+    std::vector<double> x, wx, y, wy;
+    rule(d.qx_kind, d.qx_n, x, wx);
+    rule(d.qy_kind, d.qy_n, y, wy);
+    const int qx = (int)x.size(), qy = (int)y.size();
+    p.q = qx * qy;
+    if (p.q > 1024) throw Error(FDLB_EINVAL, "at most 1024 velocities");
+    p.xi_x.resize(p.q);
+    p.xi_y.resize(p.q);
+    p.w.resize(p.q);
+    for (int j = 0; j < qy; ++j)
+        for (int i = 0; i < qx; ++i) {
+            const int a = j * qx + i;
+            p.xi_x[a] = x[i];
+            p.xi_y[a] = y[j];
+            p.w[a] = wy[j] * wx[i];
+        }
+    p.plane = (int64_t)d.nx * d.ny;
+    p.L = std::max(d.nx, d.ny);
+    // Time step of the unsplit donor cell: dt max_alpha(|xi_x| N_x + |xi_y| N_y) = CFL,
+    // counting only bounded axes (transport along a periodic single cell vanishes).
+    p.nux_scale = d.periodic_x ? 0.0 : (double)d.nx;
+    p.nuy_scale = d.periodic_y ? 0.0 : (double)d.ny;
+    double speed = 0;
+    for (int a = 0; a < p.q; ++a)
+        speed = std::max(speed, std::fabs(p.xi_x[a]) * p.nux_scale + std::fabs(p.xi_y[a]) * p.nuy_scale);
+    if (!(speed > 0)) throw Error(FDLB_EINVAL, "no transport: both axes periodic");
+    p.dt = d.cfl / speed;
+    p.omega = std::isinf(d.kn) ? 0.0 : p.dt / d.kn;
+    if (!d.allow_unstable && (d.cfl > 1.0 || p.omega > 1.0))
+        throw Error(FDLB_EUNSTABLE, "explicit scheme unstable: need cfl <= 1 and dt/Kn <= 1 (dt/Kn = " +
+                                        std::to_string(p.omega) + ")");
+    // Wall constants of Eq. (9) in deviation form.
+    for (int wl = 0; wl < 4; ++wl) {
+        WallConst& W = p.wall[wl];
+        W = WallConst{};
+        W.active = (wl == BOTTOM || wl == TOP) ? !d.periodic_y : !d.periodic_x;
+        W.u = d.wall_u[wl];
+        long double A = 0, Bn = 0, Bt = 0;
+        for (int a = 0; a < p.q; ++a) {
+            const double xn = wl == BOTTOM ? p.xi_y[a] : wl == TOP ? -p.xi_y[a] : wl == LEFT ? p.xi_x[a] : -p.xi_x[a];
+            const double xt = (wl == BOTTOM || wl == TOP) ? p.xi_x[a] : p.xi_y[a];
+            if (xn < 0) {
+                A += (long double)(-xn) * p.w[a];
+                Bn += (long double)(-xn) * p.w[a] * xn;
+                Bt += (long double)(-xn) * p.w[a] * xt;
+            }
+        }
+        W.A = (double)A;
+        W.Bn = (double)Bn;
+        W.Bt = (double)Bt;
+        W.c0 = (double)((long double)SQRT_2PI * A - 1.0L);
+    }
+    // Velocity table grouped by quadrant: (+,+), (-,+), (+,-), (-,-); zero counts as +.
+    p.quad_order.clear();
+    for (int qd = 0; qd < 4; ++qd) {
+        p.quad_begin[qd] = (int)p.quad_order.size();
+        for (int a = 0; a < p.q; ++a) {
+            const int sx = p.xi_x[a] < 0 ? 1 : 0, sy = p.xi_y[a] < 0 ? 1 : 0;
+            if (sx + 2 * sy == qd) p.quad_order.push_back(a);
+        }
+    }
+    p.quad_begin[4] = p.q;
+    // Device layout.
+    p.elem = d.precision == FDLB_FP32 ? 4 : 8;
+    p.pop_bytes = align256((size_t)p.q * p.plane * p.elem);
+    p.state_bytes = 2 * p.pop_bytes;
+    int maxb = 1;
+    for (const TileShape& t : tile_shapes(d.precision)) {
+        const int64_t nb = (int64_t)((d.nx + t.tile_w() - 1) / t.tile_w()) * ((d.ny + t.tile_h() - 1) / t.tile_h());
+        maxb = (int)std::max<int64_t>(maxb, nb);
+    }
+    p.max_blocks = maxb;
+    size_t off = 0;
+    p.mom_bytes = align256(3 * (size_t)p.plane * p.elem);
+    p.off_mom = off;
+    off += 2 * p.mom_bytes;
+    p.phi_bytes = align256(4 * (size_t)p.L * sizeof(double));
+    p.off_phi = off;
+    off += 2 * p.phi_bytes;
+    p.off_part = off;
+    off += align256((size_t)maxb * 3 * sizeof(double));
+    p.off_ctrl = off;
+    off += align256(CTRL_DOUBLES * sizeof(double));
+    p.off_vel = off;
+    off += align256((size_t)p.q * (d.precision == FDLB_FP32 ? sizeof(VelEntry<float>) : sizeof(VelEntry<double>)));
+    p.off_vel64 = off;
+    off += align256((size_t)p.q * sizeof(VelEntry<double>));
+    p.off_wall = off;
+    off += align256(4 * sizeof(WallConst));
+    p.off_wnat = off;
+    off += align256((size_t)p.q * sizeof(double));
+    p.io_bytes = align256(std::max<size_t>(4 * (size_t)p.plane * sizeof(double) + 64, 3 * (size_t)p.L * sizeof(double)));
+    p.off_io = off;
+    off += p.io_bytes;
+    p.work_bytes = off;
+    p.tile = heuristic_tile(p);
+}
+
+template <class T>
+static std::vector<VelEntry<T>> vel_table(const fdlb_problem& p) {
+    std::vector<VelEntry<T>> v(p.q);
+    for (int e = 0; e < p.q; ++e) {
+        const int a = p.quad_order[e];
+        VelEntry<T>& c = v[e];
+        std::memset(&c, 0, sizeof(c));
+        const double w = p.w[a], x = p.xi_x[a], y = p.xi_y[a];
+        c.ow = (T)(p.omega * w);
+        c.owx = (T)(p.omega * w * x);
+        c.owy = (T)(p.omega * w * y);
+        c.w = (T)w;
+        c.wx = (T)(w * x);
+        c.wy = (T)(w * y);
+        c.xx = (T)x;
+        c.xy = (T)y;
+        c.nux = (T)(p.dt * std::fabs(x) * p.nux_scale);
+        c.nuy = (T)(p.dt * std::fabs(y) * p.nuy_scale);
+        c.alpha = a;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Binding and initial states.
+// ---------------------------------------------------------------------------
+static void require_bound(const fdlb_problem& p) {
+    if (!p.bound) throw Error(FDLB_ESTATE, "problem is not bound to device memory (call fdlb_bind)");
+}
+static void require_seeded(const fdlb_problem& p) {
+    require_bound(p);
+    if (!p.seeded) throw Error(FDLB_ESTATE, "state not initialised (call an init or upload function)");
+}
+
+void bind(fdlb_problem& p, void* d_state, void* d_work, void* stream) {
+    if (!d_state || !d_work) throw Error(FDLB_EINVAL, "device buffers must not be NULL");
+    if (((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
+        throw Error(FDLB_EINVAL, "device buffers must be 256-byte aligned");
+    for (auto& kv : p.graphs) (void)hipGraphExecDestroy(kv.second);
+    p.graphs.clear();
+    p.d_state = (char*)d_state;
+    p.d_work = (char*)d_work;
+    p.stream = (hipStream_t)stream;
+    if (!p.pinned) FDLB_HIP(hipHostMalloc((void**)&p.pinned, 64 * sizeof(double), hipHostMallocDefault));
+    if (p.d.precision == FDLB_FP32) {
+        auto v = vel_table<float>(p);
+        FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, p.stream));
+        FDLB_HIP(hipStreamSynchronize(p.stream));
+    }
+    auto v64 = vel_table<double>(p);
+    FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel64, v64.data(), v64.size() * sizeof(v64[0]), hipMemcpyHostToDevice,
+                            p.stream));
+    if (p.d.precision == FDLB_FP64)
+        FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel, v64.data(), v64.size() * sizeof(v64[0]), hipMemcpyHostToDevice,
+                                p.stream));
+    FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_wall, p.wall, sizeof(p.wall), hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_wnat, p.w.data(), p.q * sizeof(double), hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));  // host tables above are temporaries
+    p.bound = true;
+    p.seeded = false;
+}
+
+static char* pop_buf(fdlb_problem& p, int parity) { return p.d_state + (size_t)parity * p.pop_bytes; }
+static char* mom_buf(fdlb_problem& p, int parity) { return p.d_work + p.off_mom + (size_t)parity * p.mom_bytes; }
+static double* phi_buf(fdlb_problem& p, int parity) {
+    return (double*)(p.d_work + p.off_phi + (size_t)parity * p.phi_bytes);
+}
+static double* ctrl(fdlb_problem& p) { return (double*)(p.d_work + p.off_ctrl); }
+static const VelEntry<double>* vel64(fdlb_problem& p) { return (const VelEntry<double>*)(p.d_work + p.off_vel64); }
+static double* io(fdlb_problem& p) { return (double*)(p.d_work + p.off_io); }
+
+// Reset the step counter and convergence records (host-to-device copy, never inside a graph).
+static void reset_ctrl(fdlb_problem& p, double tol) {
+    double* h = p.pinned;
+    std::fill(h, h + 8, 0.0);
+    h[CTRL_FIRST_BELOW] = -1.0;
+    h[CTRL_DIVERGED] = -1.0;
+    h[CTRL_TOL] = tol;
+    FDLB_HIP(hipMemcpyAsync(ctrl(p), h, 8 * sizeof(double), hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+}
+
+// Recompute the moment and wall-flux buffers of the current state.
+static void refresh_moments(fdlb_problem& p) {
+    const int par = p.parity;
+    if (p.d.precision == FDLB_FP32)
+        launch_moments<float>((const float*)pop_buf(p, par), (float*)mom_buf(p, par), phi_buf(p, par), vel64(p), p.q,
+                              p.d.nx, p.d.ny, p.L, (const WallConst*)(p.d_work + p.off_wall), p.stream);
+    else
+        launch_moments<double>((const double*)pop_buf(p, par), (double*)mom_buf(p, par), phi_buf(p, par), vel64(p),
+                               p.q, p.d.nx, p.d.ny, p.L, (const WallConst*)(p.d_work + p.off_wall), p.stream);
+}
+
+void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, const double* uy, int renorm) {
+    require_bound(p);
+    const int64_t n = p.plane;
+    double* in = io(p);
+    std::vector<double> r;
+    const double *pr = nullptr, *pu = nullptr, *pv = nullptr;
+    if (rho || renorm) {
+        r.assign(n, 1.0);
+        if (rho) std::copy(rho, rho + n, r.begin());
+        if (renorm) {
+            long double s = 0;
+            for (double v : r) s += v;
+            if (!(s > 0)) throw Error(FDLB_EINVAL, "total mass must be positive");
+            const double scale = (double)((long double)n / s);
+            for (double& v : r) v *= scale;
+        }
+        FDLB_HIP(hipMemcpyAsync(in, r.data(), n * sizeof(double), hipMemcpyHostToDevice, p.stream));
+        pr = in;
+    }
+    if (ux) {
+        FDLB_HIP(hipMemcpyAsync(in + n, ux, n * sizeof(double), hipMemcpyHostToDevice, p.stream));
+        pu = in + n;
+    }
+    if (uy) {
+        FDLB_HIP(hipMemcpyAsync(in + 2 * n, uy, n * sizeof(double), hipMemcpyHostToDevice, p.stream));
+        pv = in + 2 * n;
+    }
+    p.parity = 0;
+    if (p.d.precision == FDLB_FP32)
+        launch_seed<float>((float*)pop_buf(p, 0), p.q, n, vel64(p), pr, pu, pv, nullptr, nullptr, nullptr, nullptr,
+                           p.stream);
+    else
+        launch_seed<double>((double*)pop_buf(p, 0), p.q, n, vel64(p), pr, pu, pv, nullptr, nullptr, nullptr, nullptr,
+                            p.stream);
+    refresh_moments(p);
+    FDLB_HIP(hipStreamSynchronize(p.stream));  // r is a host temporary
+    p.seeded = true;
+    reset_ctrl(p, 0.0);
+}
+
+void init_equilibrium_dev(fdlb_problem& p, const float* rho, const float* ux, const float* uy, int renorm) {
+    require_bound(p);
+    if (!rho || !ux || !uy) throw Error(FDLB_EINVAL, "device fields must not be NULL");
+    double* scale = nullptr;
+    if (renorm) {
+        scale = io(p) + 4 * p.plane;
+        launch_mass_scale(rho, p.plane, scale, p.stream);
+    }
+    p.parity = 0;
+    if (p.d.precision == FDLB_FP32)
+        launch_seed<float>((float*)pop_buf(p, 0), p.q, p.plane, vel64(p), nullptr, nullptr, nullptr, rho, ux, uy,
+                           scale, p.stream);
+    else
+        launch_seed<double>((double*)pop_buf(p, 0), p.q, p.plane, vel64(p), nullptr, nullptr, nullptr, rho, ux, uy,
+                            scale, p.stream);
+    refresh_moments(p);
+    p.seeded = true;
+    reset_ctrl(p, 0.0);
+}
+
+void state_upload(fdlb_problem& p, const double* f) {
+    require_bound(p);
+    if (!f) throw Error(FDLB_EINVAL, "NULL host array");
+    p.parity = 0;
+    const int chunk = 4;
+    for (int a0 = 0; a0 < p.q; a0 += chunk) {
+        const int a1 = std::min(p.q, a0 + chunk);
+        FDLB_HIP(hipMemcpyAsync(io(p), f + (size_t)a0 * p.plane, (size_t)(a1 - a0) * p.plane * sizeof(double),
+                                hipMemcpyHostToDevice, p.stream));
+        if (p.d.precision == FDLB_FP32)
+            launch_from_raw<float>(io(p), (const double*)(p.d_work + p.off_wnat), a0, a1, p.plane,
+                                   (float*)pop_buf(p, 0), p.stream);
+        else
+            launch_from_raw<double>(io(p), (const double*)(p.d_work + p.off_wnat), a0, a1, p.plane,
+                                    (double*)pop_buf(p, 0), p.stream);
+        FDLB_HIP(hipStreamSynchronize(p.stream));
+    }
+    refresh_moments(p);
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+    p.seeded = true;
+    reset_ctrl(p, 0.0);
+}
+
+void state_download(fdlb_problem& p, double* f) {
+    require_seeded(p);
+    if (!f) throw Error(FDLB_EINVAL, "NULL host array");
+    const int chunk = 4;
+    for (int a0 = 0; a0 < p.q; a0 += chunk) {
+        const int a1 = std::min(p.q, a0 + chunk);
+        if (p.d.precision == FDLB_FP32)
+            launch_to_raw<float>((const float*)pop_buf(p, p.parity), (const double*)(p.d_work + p.off_wnat), a0, a1,
+                                 p.plane, io(p), p.stream);
+        else
+            launch_to_raw<double>((const double*)pop_buf(p, p.parity), (const double*)(p.d_work + p.off_wnat), a0, a1,
+                                  p.plane, io(p), p.stream);
+        FDLB_HIP(hipMemcpyAsync(f + (size_t)a0 * p.plane, io(p), (size_t)(a1 - a0) * p.plane * sizeof(double),
+                                hipMemcpyDeviceToHost, p.stream));
+        FDLB_HIP(hipStreamSynchronize(p.stream));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Time marching.
+// ---------------------------------------------------------------------------
+template <class T>
+static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile) {
+    const TileShape& t = tile_shapes(p.d.precision)[tile];
+    StepArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.src = (const T*)pop_buf(p, parity);
+    a.dst = (T*)pop_buf(p, parity ^ 1);
+    a.mom_in = (const T*)mom_buf(p, parity);
+    a.mom_out = (T*)mom_buf(p, parity ^ 1);
+    a.phi_in = phi_buf(p, parity);
+    a.phi_out = phi_buf(p, parity ^ 1);
+    a.partials = (double*)(p.d_work + p.off_part);
+    a.vel = (const VelEntry<T>*)(p.d_work + p.off_vel);
+    for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
+    a.nx = p.d.nx;
+    a.ny = p.d.ny;
+    a.L = p.L;
+    a.tiles_x = (p.d.nx + t.tile_w() - 1) / t.tile_w();
+    a.tiles_y = (p.d.ny + t.tile_h() - 1) / t.tile_h();
+    a.plane = p.plane;
+    a.c1 = (T)(1.0 - p.omega);
+    for (int i = 0; i < 4; ++i) a.wall[i] = p.wall[i];
+    return a;
+}
+
+static int nblocks_of(const fdlb_problem& p, int tile) {
+    const TileShape& t = tile_shapes(p.d.precision)[tile];
+    return ((p.d.nx + t.tile_w() - 1) / t.tile_w()) * ((p.d.ny + t.tile_h() - 1) / t.tile_h());
+}
+
+// Enqueue one step (fused step kernel + residual reduction) from buffer `parity`.
+static void enqueue_step(fdlb_problem& p, int parity, int tile) {
+    const int nb = nblocks_of(p, tile);
+    if (p.d.precision == FDLB_FP32)
+        launch_step<float>(tile, step_args<float>(p, parity, tile), nb, p.stream);
+    else
+        launch_step<double>(tile, step_args<double>(p, parity, tile), nb, p.stream);
+    launch_reduce((const double*)(p.d_work + p.off_part), nb, ctrl(p), 1, p.stream);
+}
+
+void step(fdlb_problem& p, int64_t n) {
+    require_seeded(p);
+    if (n < 0) throw Error(FDLB_EINVAL, "nsteps must be >= 0");
+    for (int64_t i = 0; i < n; ++i) {
+        enqueue_step(p, p.parity, p.tile);
+        p.parity ^= 1;
+    }
+}
+
+void step_timed(fdlb_problem& p, int64_t n, double* ms_step, double* ms_reduce) {
+    require_seeded(p);
+    if (n < 1) throw Error(FDLB_EINVAL, "nsteps must be >= 1");
+    std::vector<hipEvent_t> ev(2 * n + 1, nullptr);
+    double a = 0, b = 0;
+    try {
+        for (auto& e : ev) FDLB_HIP(hipEventCreate(&e));
+        const int nb = nblocks_of(p, p.tile);
+        FDLB_HIP(hipEventRecord(ev[0], p.stream));
+        for (int64_t i = 0; i < n; ++i) {
+            if (p.d.precision == FDLB_FP32)
+                launch_step<float>(p.tile, step_args<float>(p, p.parity, p.tile), nb, p.stream);
+            else
+                launch_step<double>(p.tile, step_args<double>(p, p.parity, p.tile), nb, p.stream);
+            FDLB_HIP(hipEventRecord(ev[2 * i + 1], p.stream));
+            launch_reduce((const double*)(p.d_work + p.off_part), nb, ctrl(p), 1, p.stream);
+            FDLB_HIP(hipEventRecord(ev[2 * i + 2], p.stream));
+            p.parity ^= 1;
+        }
+        FDLB_HIP(hipEventSynchronize(ev[2 * n]));
+        for (int64_t i = 0; i < n; ++i) {
+            float t1 = 0, t2 = 0;
+            FDLB_HIP(hipEventElapsedTime(&t1, ev[2 * i], ev[2 * i + 1]));
+            FDLB_HIP(hipEventElapsedTime(&t2, ev[2 * i + 1], ev[2 * i + 2]));
+            a += t1;
+            b += t2;
+        }
+    } catch (...) {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        throw;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (ms_step) *ms_step = a;
+    if (ms_reduce) *ms_reduce = b;
+}
+
+// Replay k steps as one captured graph (k even keeps the buffer parity).
+static void enqueue_graph(fdlb_problem& p, int k) {
+    auto key = std::make_tuple(k, p.tile, p.parity);
+    auto it = p.graphs.find(key);
+    if (it == p.graphs.end()) {
+        hipGraph_t g;
+        FDLB_HIP(hipStreamBeginCapture(p.stream, hipStreamCaptureModeThreadLocal));
+        int par = p.parity;
+        try {
+            for (int i = 0; i < k; ++i) {
+                enqueue_step(p, par, p.tile);
+                par ^= 1;
+            }
+        } catch (...) {
+            hipGraph_t dummy;
+            (void)hipStreamEndCapture(p.stream, &dummy);
+            throw;
+        }
+        FDLB_HIP(hipStreamEndCapture(p.stream, &g));
+        hipGraphExec_t ge;
+        FDLB_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        FDLB_HIP(hipGraphDestroy(g));
+        it = p.graphs.emplace(key, ge).first;
+    }
+    FDLB_HIP(hipGraphLaunch(it->second, p.stream));
+    if (k & 1) p.parity ^= 1;
+}
+
+static void read_ctrl(fdlb_problem& p) {
+    FDLB_HIP(hipMemcpyAsync(p.pinned, ctrl(p), 8 * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+}
+
+void last_residual(fdlb_problem& p, double* r, int64_t* steps) {
+    require_seeded(p);
+    read_ctrl(p);
+    if (r) *r = p.pinned[CTRL_LAST_R];
+    if (steps) *steps = (int64_t)p.pinned[CTRL_STEP];
+}
+
+int solve_steady(fdlb_problem& p, double tol, int64_t max_steps, int32_t check_every, int32_t use_graph,
+                 fdlb_report* rep) {
+    require_seeded(p);
+    if (!(tol >= 0) || max_steps < 0 || check_every < 1) throw Error(FDLB_EINVAL, "bad solve arguments");
+    const bool graph = use_graph && p.stream != nullptr && check_every >= 2;
+    // Keep the step counter; clear the convergence records and set the tolerance.
+    read_ctrl(p);
+    const double base = p.pinned[CTRL_STEP];
+    p.pinned[CTRL_FIRST_BELOW] = -1.0;
+    p.pinned[CTRL_DIVERGED] = -1.0;
+    p.pinned[CTRL_TOL] = tol;
+    FDLB_HIP(hipMemcpyAsync(ctrl(p) + CTRL_FIRST_BELOW, p.pinned + CTRL_FIRST_BELOW, 4 * sizeof(double),
+                            hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    int64_t done = 0;
+    int status = FDLB_ENOTCONVERGED;
+    int32_t hlen = 0;
+    double last_r = std::numeric_limits<double>::quiet_NaN();
+    int64_t first = -1;
+    while (done < max_steps) {
+        const int64_t k = std::min<int64_t>(check_every, max_steps - done);
+        if (graph && k == check_every) enqueue_graph(p, (int)k);
+        else step(p, k);
+        done += k;
+        read_ctrl(p);
+        last_r = p.pinned[CTRL_LAST_R];
+        if (rep && rep->history && hlen < rep->history_cap) rep->history[hlen++] = last_r;
+        if (p.pinned[CTRL_DIVERGED] >= 0) {
+            status = FDLB_EDIVERGED;
+            first = -1;
+            break;
+        }
+        if (p.pinned[CTRL_FIRST_BELOW] >= 0) {
+            status = FDLB_OK;
+            first = (int64_t)(p.pinned[CTRL_FIRST_BELOW] - base);
+            break;
+        }
+    }
+    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) {
+        rep->steps = done;
+        rep->first_below = first;
+        rep->residual = last_r;
+        rep->wall_s = wall;
+        const double upd = (double)done * (double)p.plane * p.q;
+        rep->updates_per_s = wall > 0 ? upd / wall : 0;
+        rep->bytes_per_s = wall > 0 ? upd * 2.0 * (double)p.elem / wall : 0;
+        rep->status = status;
+        rep->history_len = hlen;
+    }
+    if (status == FDLB_EDIVERGED) {
+        throw Error(FDLB_EDIVERGED, "solve diverged at step " + std::to_string((int64_t)(p.pinned[CTRL_DIVERGED] - base)) +
+                                        " (non-finite residual or |u| > 0.5)");
+    }
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// Outputs.
+// ---------------------------------------------------------------------------
+void moments(fdlb_problem& p, double* rho, double* ux, double* uy, double* pxy) {
+    require_seeded(p);
+    if (p.d.precision == FDLB_FP32)
+        launch_post<float>((const float*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, p.omega, io(p), p.stream);
+    else
+        launch_post<double>((const double*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, p.omega, io(p),
+                            p.stream);
+    double* outs[4] = {rho, ux, uy, pxy};
+    for (int i = 0; i < 4; ++i)
+        if (outs[i])
+            FDLB_HIP(hipMemcpyAsync(outs[i], io(p) + (size_t)i * p.plane, p.plane * sizeof(double),
+                                    hipMemcpyDeviceToHost, p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+}
+
+void wall_profile(fdlb_problem& p, int wall, double* rho, double* ut, double* pxy) {
+    require_seeded(p);
+    if (wall < 0 || wall > 3) throw Error(FDLB_EINVAL, "wall index must be 0..3");
+    if (!p.wall[wall].active) throw Error(FDLB_EINVAL, "that wall is absent (periodic axis)");
+    const int n = (wall == BOTTOM || wall == TOP) ? p.d.nx : p.d.ny;
+    if (p.d.precision == FDLB_FP32)
+        launch_wall_profile<float>((const float*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, wall,
+                                   &p.wall[wall], p.omega, io(p), p.stream);
+    else
+        launch_wall_profile<double>((const double*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, wall,
+                                    &p.wall[wall], p.omega, io(p), p.stream);
+    double* outs[3] = {rho, ut, pxy};
+    for (int i = 0; i < 3; ++i)
+        if (outs[i])
+            FDLB_HIP(hipMemcpyAsync(outs[i], io(p) + (size_t)i * n, n * sizeof(double), hipMemcpyDeviceToHost,
+                                    p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+}
+
+// ---------------------------------------------------------------------------
+// Tiles.
+// ---------------------------------------------------------------------------
+void set_tile(fdlb_problem& p, int tile) {
+    if (tile < 0) {
+        p.tile = heuristic_tile(p);
+        return;
+    }
+    const auto& shapes = tile_shapes(p.d.precision);
+    if (tile >= (int)shapes.size()) throw Error(FDLB_EINVAL, "tile index out of range");
+    if (!tile_fits(shapes[tile], p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y))
+        throw Error(FDLB_EINVAL, "tile shape does not fit this grid");
+    if (nblocks_of(p, tile) > p.max_blocks) throw Error(FDLB_EINVAL, "tile needs more blocks than the workspace holds");
+    p.tile = tile;
+}
+
+double autotune(fdlb_problem& p, int steps) {
+    require_bound(p);
+    if (steps < 1) throw Error(FDLB_EINVAL, "steps must be >= 1");
+    const auto& shapes = tile_shapes(p.d.precision);
+    hipEvent_t e0, e1;
+    FDLB_HIP(hipEventCreate(&e0));
+    FDLB_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_tile = p.tile;
+    try {
+        for (int t = 0; t < (int)shapes.size(); ++t) {
+            if (!tile_fits(shapes[t], p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y)) continue;
+            p.tile = t;
+            init_equilibrium(p, nullptr, nullptr, nullptr, 0);
+            step(p, 2);  // warm-up
+            FDLB_HIP(hipEventRecord(e0, p.stream));
+            step(p, steps);
+            FDLB_HIP(hipEventRecord(e1, p.stream));
+            FDLB_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            FDLB_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / steps < best) {
+                best = ms / steps;
+                best_tile = t;
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p.tile = best_tile;
+    init_equilibrium(p, nullptr, nullptr, nullptr, 0);
+    return best;
+}
+
+}  // namespace fdlb

@@ -1,0 +1,336 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (stated per result): FP64 path <= 1e-12 relative after identical step
+counts; FP32 path (deviations stored in float) <= 2e-5 relative on rho and u
+against the oracle's converged FP64 solution.  Error measures:
+  eps_u   = max_cells |u - u_ref| / max_cells |u_ref|   (vector norm)
+  eps_rho = max_cells |rho - rho_ref|                    (rho_ref ~ 1)
+  eps_f   = max |f - f_ref| / max |f_ref - w|            (relative to the deviation scale)
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.scheme import BOTTOM, LEFT, RIGHT, TOP
+from oracle.scheme import Problem as OP
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1308_0692_amd as F
+    return F
+
+
+def eps_u(ux, uy, uxr, uyr):
+    return float(np.hypot(ux - uxr, uy - uyr).max() / np.hypot(uxr, uyr).max())
+
+
+def eps_f(f, fr, w):
+    dev = np.abs(fr - w[:, None, None]).max()
+    return float(np.abs(f - fr).max() / dev)
+
+
+def perturbed_state(xi_x, xi_y, w, nx, ny, seed, amp=0.02):
+    """Raw populations w rho (1 + xi.u) (1 + amp noise) from seeded fields; each side
+    builds it from its own velocity set."""
+    rho, ux, uy = W.random_fields(nx, ny, seed, amp=0.01)
+    noise = W.random_noise(len(w), nx, ny, seed + 1)
+    feq = w[:, None, None] * rho[None] * (1 + xi_x[:, None, None] * ux[None] + xi_y[:, None, None] * uy[None])
+    return feq * (1 + amp * noise)
+
+
+def both_perturbed(gp, op, seed):
+    x, y, w = gp.velocities()
+    fg = perturbed_state(x, y, w, gp.nx, gp.ny, seed)
+    fo = perturbed_state(op.xi_x, op.xi_y, op.w, op.nx, op.ny, seed)
+    return fg, fo
+
+
+# ---------------------------------------------------------------------------
+# FP64: identical step counts.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nsteps", [1, 10, 1000])
+def test_fp64_couette_steps(F, nsteps):
+    gp = F.Problem(W.C1, precision="fp64")
+    op = OP.from_case(W.C1)
+    gp.init_equilibrium()
+    gp.step(nsteps)
+    fo = op.step(op.equilibrium(), nsteps)
+    rho, ux, uy, pxy = gp.moments()
+    r0, ux0, uy0 = op.moments(fo)
+    assert eps_u(ux, uy, ux0, uy0) <= 1e-12
+    assert np.abs(rho - r0).max() <= 1e-13
+    assert np.abs(pxy - op.pxy(fo)).max() <= 1e-12 * np.abs(op.pxy(fo)).max()
+    assert eps_f(gp.download(), fo, op.w) <= 1e-12
+    for wall in (BOTTOM, TOP):
+        rg, ug, pg = gp.wall_profile(wall)
+        ro, uo, po = op.wall_profile(fo, wall)
+        assert np.abs(ug - uo).max() <= 1e-12 * np.abs(uo).max()
+        assert np.abs(pg - po).max() <= 1e-12 * np.abs(po).max()
+        assert np.abs(rg - ro).max() <= 1e-13
+
+
+def _fitting_tiles(F, case, prec):
+    p = F.Problem(case, precision=prec, bind=False)
+    out = []
+    for t in range(F.tile_count(prec)):
+        try:
+            p.set_tile(t)
+            out.append(t)
+        except F.FdlbError:
+            pass
+    return out
+
+
+GRIDS = [W.cavity(36, ny=22, kn=0.1, order=2), W.cavity(37, ny=29, kn=0.05, order=3),
+         W.cavity(128, ny=20, kn=0.3, order=4), W.cavity(64, kn=1.0, order=2),
+         W.cavity(300, ny=9, kn=0.2, order=2), W.cavity(8, ny=70, kn=0.5, order=2)]
+
+
+@pytest.mark.parametrize("case", GRIDS, ids=lambda c: f"{c.nx}x{c.ny}q{c.q}")
+def test_fp64_every_tile_matches_oracle(F, case):
+    """Non-equilibrium state, ragged grids (several tiles and a ragged tail), every tile shape."""
+    op = OP.from_case(case)
+    gp = F.Problem(case, precision="fp64")
+    fg, fo = both_perturbed(gp, op, seed=11)
+    ref = op.step(fo, 6)
+    tiles = _fitting_tiles(F, case, "fp64")
+    assert tiles
+    for t in tiles:
+        gp.set_tile(t)
+        gp.upload(fg)
+        gp.step(6)
+        e = eps_f(gp.download(), ref, op.w)
+        assert e <= 1e-12, (t, F.tile_describe("fp64", t), e)
+
+
+@pytest.mark.parametrize("case", GRIDS, ids=lambda c: f"{c.nx}x{c.ny}q{c.q}")
+def test_fp32_every_tile_matches_oracle(F, case):
+    op = OP.from_case(case)
+    gp = F.Problem(case, precision="fp32")
+    fg, fo = both_perturbed(gp, op, seed=12)
+    ref = op.step(fo, 6)
+    r0, ux0, uy0 = op.moments(ref)
+    for t in _fitting_tiles(F, case, "fp32"):
+        gp.set_tile(t)
+        gp.upload(fg)
+        gp.step(6)
+        e = eps_f(gp.download(), ref, op.w)
+        assert e <= 2e-6, (t, F.tile_describe("fp32", t), e)
+        rho, ux, uy, _ = gp.moments()
+        assert eps_u(ux, uy, ux0, uy0) <= 2e-5
+        assert np.abs(rho - r0).max() <= 2e-5
+
+
+@pytest.mark.parametrize("case", [W.couette_x(64, kn=0.2), W.couette(33, kn=0.7, qy=("half", 3)),
+                                  W.cavity(2, kn=1.0, order=2), W.cavity(3, ny=5, kn=1.0, order=2)],
+                         ids=["couettex64", "couette33", "cavity2", "cavity3x5"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_edge_geometries(F, case, prec):
+    """Plates on the x walls, odd Couette sizes, and the smallest cavities."""
+    op = OP.from_case(case)
+    gp = F.Problem(case, precision=prec)
+    gp.init_equilibrium()
+    gp.step(40)
+    fo = op.step(op.equilibrium(), 40)
+    e = eps_f(gp.download(), fo, op.w)
+    assert e <= (1e-12 if prec == "fp64" else 2e-6), e
+
+
+def test_free_molecular_cavity_fp64(F):
+    case = W.cavity(24, ny=16, kn=math.inf, order=3)
+    op = OP.from_case(case)
+    gp = F.Problem(case, precision="fp64")
+    assert gp.omega == 0.0
+    gp.init_equilibrium()
+    gp.step(50)
+    fo = op.step(op.equilibrium(), 50)
+    assert eps_f(gp.download(), fo, op.w) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Converged states.
+# ---------------------------------------------------------------------------
+
+def test_fp64_couette_converged(F):
+    """C1 to R < 1e-13 with a per-step check: same first step below the tolerance and
+    the same state."""
+    gp = F.Problem(W.C1, precision="fp64")
+    op = OP.from_case(W.C1)
+    gp.init_equilibrium()
+    rep = gp.solve(1e-13, 100000, check_every=1, use_graph=False)
+    fo, n, hist = op.solve(op.equilibrium(), 1e-13, 100000)
+    assert rep["status"] == 0
+    assert rep["first_below"] == rep["steps"] == n
+    rho, ux, uy, _ = gp.moments()
+    r0, ux0, uy0 = op.moments(fo)
+    assert eps_u(ux, uy, ux0, uy0) <= 1e-12
+    _, ut, pw = gp.wall_profile(TOP)
+    _, uto, pwo = op.wall_profile(fo, TOP)
+    assert abs(ut[0] - uto[0]) <= 1e-12 * abs(uto[0])
+    assert abs(pw[0] - pwo[0]) <= 1e-12 * abs(pwo[0])
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_fp32_cavity_converged_vs_oracle(F, n):
+    """The FP32 path stepped to R < 1e-8 against the oracle converged to 1e-10 (C2 at n=128);
+    the oracle is then within ~1e-8 of its fixed point, far inside the 2e-5 bar."""
+    case = W.cavity(n, kn=0.1, u_w=0.01, order=4)
+    gp = F.Problem(case, precision="fp32")
+    gp.init_equilibrium()
+    rep = gp.solve(1e-8, 200000, check_every=50)
+    assert rep["status"] == 0
+    op = OP.from_case(case)
+    fo, steps, hist = op.solve(op.equilibrium(), 1e-10, 400000)
+    assert hist[-1] < 1e-10
+    rho, ux, uy, _ = gp.moments()
+    r0, ux0, uy0 = op.moments(fo)
+    eu = eps_u(ux, uy, ux0, uy0)
+    er = float(np.abs(rho - r0).max())
+    assert eu <= 2e-5, eu
+    assert er <= 2e-5, er
+
+
+def test_fp64_cavity_converged_steps_match(F):
+    case = W.cavity(32, kn=0.1, order=4)
+    gp = F.Problem(case, precision="fp64")
+    op = OP.from_case(case)
+    gp.init_equilibrium()
+    rep = gp.solve(1e-10, 100000, check_every=1, use_graph=False)
+    fo, n, hist = op.solve(op.equilibrium(), 1e-10, 100000)
+    assert rep["first_below"] == n
+    rho, ux, uy, _ = gp.moments()
+    r0, ux0, uy0 = op.moments(fo)
+    assert eps_u(ux, uy, ux0, uy0) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Full size: the large cavity in the launch configuration the benchmark times.
+# ---------------------------------------------------------------------------
+
+def test_large_cavity_full_size_fp32(F):
+    """1024 x 1024 x 256 velocities: two steps from a seeded non-uniform equilibrium,
+    every cell's moments against the oracle run at full size."""
+    case = W.C4
+    gp = F.Problem(case, precision="fp32")
+    op = OP.from_case(case)
+    rho, ux, uy = W.random_fields(case.nx, case.ny, seed=4, amp=0.01)
+    gp.init_equilibrium(rho, ux, uy)
+    gp.step(2)
+    fo = op.step(op.equilibrium(rho, ux, uy), 2)
+    r1, ux1, uy1, _ = gp.moments()
+    r0, ux0, uy0 = op.moments(fo)
+    del fo
+    assert eps_u(ux1, uy1, ux0, uy0) <= 2e-5
+    assert np.abs(r1 - r0).max() <= 2e-6
+
+
+# ---------------------------------------------------------------------------
+# Runtime features.
+# ---------------------------------------------------------------------------
+
+def test_graph_replays_match_eager(F):
+    """A captured chunk replayed several times, with eager work and syncs in between,
+    gives bit-identical states to the same steps launched one by one."""
+    case = W.cavity(48, ny=40, kn=0.2, order=3)
+    a = F.Problem(case, precision="fp32")
+    b = F.Problem(case, precision="fp32")
+    a.init_equilibrium()
+    b.init_equilibrium()
+    for rep in range(4):
+        a.solve(0.0, 20, check_every=20, use_graph=True)   # one graph replay of 20 steps
+        b.step(20)
+        _ = b.last_residual()
+        fa, fb = a.download(), b.download()
+        assert np.array_equal(fa, fb), rep
+        assert a.last_residual() == b.last_residual()
+
+
+def test_checkpoint_resume(F):
+    case = W.cavity(40, kn=0.1, order=2)
+    for prec in ("fp32", "fp64"):
+        a = F.Problem(case, precision=prec)
+        a.init_equilibrium()
+        a.step(300)
+        straight = a.download()
+        b = F.Problem(case, precision=prec)
+        b.init_equilibrium()
+        b.step(150)
+        ck = b.download()
+        c = F.Problem(case, precision=prec)
+        c.upload(ck)
+        c.step(150)
+        resumed = c.download()
+        if prec == "fp32":
+            assert np.array_equal(straight, resumed)
+        else:
+            assert np.abs(straight - resumed).max() <= 1e-15
+
+
+def test_init_from_device_fields_and_mass(F):
+    import torch
+    case = W.cavity(32, ny=24, kn=0.1, order=2)
+    rho, ux, uy = W.random_fields(32, 24, seed=5, amp=0.01)
+    rho32, ux32, uy32 = (a.astype(np.float32) for a in (rho, ux, uy))
+    a = F.Problem(case, precision="fp64")
+    a.init_equilibrium(rho32.astype(np.float64) * 1.5, ux32.astype(np.float64), uy32.astype(np.float64),
+                       renormalize=True)
+    b = F.Problem(case, precision="fp64")
+    b.init_equilibrium_dev(*(torch.from_numpy(v * (1.5 if i == 0 else 1.0)).float().cuda()
+                             for i, v in enumerate((rho32, ux32, uy32))), renormalize=True)
+    ra = a.moments()[0]
+    rb = b.moments()[0]
+    assert abs(ra.sum() - 32 * 24) < 1e-9
+    assert abs(rb.sum() - 32 * 24) < 1e-9
+    assert np.abs(ra - rb).max() < 1e-12
+
+
+def test_solve_report(F):
+    case = W.cavity(32, kn=0.1, order=2)
+    p = F.Problem(case, precision="fp32")
+    p.init_equilibrium()
+    rep = p.solve(1e-6, 100000, check_every=64, history_cap=1000)
+    assert rep["status"] == 0
+    assert 0 < rep["first_below"] <= rep["steps"] < rep["first_below"] + 64
+    assert rep["steps"] % 64 == 0
+    assert len(rep["history"]) == rep["steps"] // 64
+    assert rep["history"][-1] < 1e-6 <= rep["history"][-2]
+    assert rep["updates_per_s"] > 0 and rep["bytes_per_s"] == pytest.approx(rep["updates_per_s"] * 8)
+    rep2 = p.solve(1e-6, 10, check_every=5)
+    assert rep2["status"] == 0 and rep2["steps"] == 5
+    rep3 = p.solve(1e-30, 10, check_every=5)
+    assert rep3["status"] == 1 and rep3["first_below"] == -1
+
+
+def test_divergence_is_reported(F):
+    """An unstable explicit step (CFL 2) blows up; the solve reports it instead of returning
+    garbage (the condition is forced by the host's choice of dt, no kernel misbehaves)."""
+    case = W.with_(W.cavity(32, kn=0.1, order=2), cfl=2.0)
+    p = F.Problem(case, precision="fp32", allow_unstable=True)
+    p.init_equilibrium()
+    rep = p.solve(1e-8, 20000, check_every=50, raise_on_diverge=False)
+    assert rep["status"] == F._lib.EDIVERGED
+    with pytest.raises(F.FdlbError) as e:
+        p.init_equilibrium()
+        p.solve(1e-8, 20000, check_every=50)
+    assert e.value.code == F._lib.EDIVERGED
+
+
+def test_autotune_keeps_results(F):
+    case = W.cavity(96, kn=0.1, order=2)
+    p = F.Problem(case, precision="fp32")
+    ms = p.autotune(steps=5)
+    assert ms > 0
+    p.init_equilibrium()
+    p.step(20)
+    op = OP.from_case(case)
+    fo = op.step(op.equilibrium(), 20)
+    assert eps_f(p.download(), fo, op.w) <= 2e-6

@@ -1,0 +1,131 @@
+"""Host-side checks of libfdlb (no GPU needed): the shared library loads and exports
+every entry point include/fdlb.h declares, its quadrature agrees with the oracle's
+independent construction, and problem set-up validates inputs and computes the
+same time step as the oracle."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1308_0692_amd as F
+    return F
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(fdlb\w+)\s*\(", src, flags=re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    assert "fdlb_step" in names and "fdlb_solve_steady" in names
+    assert len(names) > 25
+
+
+def test_library_exports_every_declared_symbol(F):
+    lib = C.CDLL(F._lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("n", list(range(1, 17)))
+def test_half_range_matches_oracle(F, n):
+    from oracle import quadrature as q
+    x, w = F.quad_half_range(n)
+    xo, wo = q.half_range(n)
+    assert np.allclose(x, xo, rtol=4e-16, atol=0)
+    assert np.allclose(w, wo, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 12, 20, 32])
+def test_full_range_matches_oracle(F, n):
+    from oracle import quadrature as q
+    x, w = F.quad_full_range(n)
+    xo, wo = q.full_range(n)
+    assert np.allclose(x, xo, rtol=1e-15, atol=1e-300)
+    assert np.allclose(w, wo, rtol=1e-14, atol=0)
+    if n % 2:
+        assert x[n // 2] == 0.0
+
+
+def test_quadrature_rejects_bad_orders(F):
+    x = np.empty(80)
+    for n in (0, 17, -3):
+        assert F._lib.lib.fdlb_quad_half_range(n, F._lib._dp(x), F._lib._dp(x)) == F._lib.EINVAL
+    assert F._lib.lib.fdlb_quad_half_range(2, None, None) == F._lib.EINVAL
+    assert F._lib.lib.fdlb_quad_full_range(33, F._lib._dp(x), F._lib._dp(x)) == F._lib.EINVAL
+
+
+@pytest.mark.parametrize("case", [W.C1, W.C2, W.C4, W.couette_x(50), W.cavity(37, ny=29, order=3),
+                                  W.cavity(64, kn=float("inf"), order=2)])
+def test_time_step_and_velocities_match_oracle(F, case):
+    from oracle.scheme import Problem as OP
+    p = F.Problem(case, bind=False)
+    o = OP.from_case(case)
+    assert p.q == o.q
+    assert p.dt == pytest.approx(o.dt, rel=1e-15)
+    assert p.omega == pytest.approx(o.omega, rel=1e-15, abs=0)
+    x, y, w = p.velocities()
+    assert np.allclose(x, o.xi_x, rtol=1e-15, atol=0)
+    assert np.allclose(y, o.xi_y, rtol=1e-15, atol=0)
+    assert np.allclose(w, o.w, rtol=1e-15, atol=0)
+
+
+def test_sizes(F):
+    p = F.Problem(W.C4, bind=False)
+    assert p.state_bytes == 2 * 256 * 1024 * 1024 * 4
+    assert p.workspace_bytes < 64 * 2 ** 20
+    p = F.Problem(W.C1, bind=False)
+    assert p.state_bytes == 2 * ((24 * 200 * 8 + 255) // 256 * 256)
+
+
+def test_validation_errors(F):
+    bad = [W.with_(W.C2, nx=0), W.with_(W.C2, periodic_x=True),
+           W.with_(W.C2, cfl=-1.0), W.with_(W.C2, kn=0.0), W.with_(W.C2, qx=("half", 17)),
+           W.with_(W.C2, qy=("full", 0)), W.with_(W.C2, nx=1)]
+    for c in bad:
+        with pytest.raises(F.FdlbError) as e:
+            F.Problem(c, bind=False)
+        assert e.value.code == F._lib.EINVAL, c
+    # stability limits of the explicit scheme
+    for c in (W.with_(W.C2, kn=0.001), W.with_(W.C2, cfl=1.2)):
+        with pytest.raises(F.FdlbError) as e:
+            F.Problem(c, bind=False)
+        assert e.value.code == F._lib.EUNSTABLE
+        F.Problem(c, bind=False, allow_unstable=True)
+
+
+def test_calls_before_bind_are_state_errors(F):
+    p = F.Problem(W.C2, bind=False)
+    assert F._lib.lib.fdlb_step(p._h, 1) == F._lib.ESTATE
+    assert "bind" in F._lib.lib.fdlb_last_error().decode()
+    assert F._lib.lib.fdlb_step(None, 1) == F._lib.EINVAL
+
+
+def test_tiles_listed_and_heuristic_fits(F):
+    for prec in ("fp32", "fp64"):
+        n = F.tile_count(prec)
+        assert n >= 6
+        for t in range(n):
+            assert "vx" in F.tile_describe(prec, t)
+    for case in (W.C1, W.C2, W.C4, W.cavity(2, kn=1.0, order=2), W.cavity(37, ny=29), W.couette_x(40)):
+        for prec in ("fp32", "fp64"):
+            p = F.Problem(case, precision=prec, bind=False)
+            assert 0 <= p.tile < F.tile_count(prec)
