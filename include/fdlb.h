@@ -167,6 +167,18 @@ int fdlb_init_equilibrium_dev(fdlb_problem *p, const float *d_rho, const float *
 int fdlb_state_upload(fdlb_problem *p, const double *f_host);
 int fdlb_state_download(fdlb_problem *p, double *f_host); /* synchronous */
 
+/*
+ * Exact checkpoint of the carried state (current populations in the stored
+ * precision, their moment and wall-flux buffers, the step counter) as an
+ * opaque host byte buffer of fdlb_checkpoint_bytes() bytes, owned by the
+ * caller.  Loading it into a problem built from the same description and
+ * marching on gives bit-identical results to never having stopped.
+ * Synchronous.
+ */
+size_t fdlb_checkpoint_bytes(const fdlb_problem *p);
+int fdlb_checkpoint_save(fdlb_problem *p, void *host_buf);
+int fdlb_checkpoint_load(fdlb_problem *p, const void *host_buf);
+
 /* ---- time marching ------------------------------------------------------------ */
 
 /*

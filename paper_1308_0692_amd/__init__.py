@@ -103,6 +103,20 @@ class Problem:
         check(_lib.lib.fdlb_state_download(self._h, _lib._dp(f)))
         return f
 
+    def checkpoint(self) -> bytes:
+        """Exact copy of the carried device state (see fdlb_checkpoint_save)."""
+        n = _lib.lib.fdlb_checkpoint_bytes(self._h)
+        buf = C.create_string_buffer(n)
+        check(_lib.lib.fdlb_checkpoint_save(self._h, C.cast(buf, C.c_void_p)))
+        return buf.raw
+
+    def restore(self, data: bytes):
+        n = _lib.lib.fdlb_checkpoint_bytes(self._h)
+        if len(data) != n:
+            raise ValueError(f"checkpoint has {len(data)} bytes, this problem needs {n}")
+        buf = C.create_string_buffer(data, n)
+        check(_lib.lib.fdlb_checkpoint_load(self._h, C.cast(buf, C.c_void_p)))
+
     # -- marching ------------------------------------------------------------------
     def step(self, n: int = 1):
         check(_lib.lib.fdlb_step(self._h, int(n)))

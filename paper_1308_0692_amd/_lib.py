@@ -71,6 +71,9 @@ def _load():
         "fdlb_init_equilibrium_dev": (C.c_int, [vp, fp, fp, fp, C.c_int]),
         "fdlb_state_upload": (C.c_int, [vp, dp]),
         "fdlb_state_download": (C.c_int, [vp, dp]),
+        "fdlb_checkpoint_bytes": (C.c_size_t, [vp]),
+        "fdlb_checkpoint_save": (C.c_int, [vp, vp]),
+        "fdlb_checkpoint_load": (C.c_int, [vp, vp]),
         "fdlb_step": (C.c_int, [vp, i64]),
         "fdlb_step_timed": (C.c_int, [vp, i64, dp, dp]),
         "fdlb_last_residual": (C.c_int, [vp, dp, C.POINTER(i64)]),

@@ -14,6 +14,9 @@ void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, cons
 void init_equilibrium_dev(fdlb_problem& p, const float* rho, const float* ux, const float* uy, int renorm);
 void state_upload(fdlb_problem& p, const double* f);
 void state_download(fdlb_problem& p, double* f);
+size_t checkpoint_bytes(const fdlb_problem& p);
+void checkpoint_save(fdlb_problem& p, void* host);
+void checkpoint_load(fdlb_problem& p, const void* host);
 void step(fdlb_problem& p, int64_t n);
 void step_timed(fdlb_problem& p, int64_t n, double* ms_step, double* ms_reduce);
 void last_residual(fdlb_problem& p, double* r, int64_t* steps);
@@ -145,6 +148,22 @@ int fdlb_state_upload(fdlb_problem* p, const double* f_host) {
 int fdlb_state_download(fdlb_problem* p, double* f_host) {
     return guard([&] {
         state_download(handle(p), f_host);
+        return FDLB_OK;
+    });
+}
+
+size_t fdlb_checkpoint_bytes(const fdlb_problem* p) { return p ? checkpoint_bytes(*p) : 0; }
+
+int fdlb_checkpoint_save(fdlb_problem* p, void* host_buf) {
+    return guard([&] {
+        checkpoint_save(handle(p), host_buf);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_checkpoint_load(fdlb_problem* p, const void* host_buf) {
+    return guard([&] {
+        checkpoint_load(handle(p), host_buf);
         return FDLB_OK;
     });
 }

@@ -55,8 +55,8 @@ template <class T>
 struct StepArgs {
     const T* src;
     T* dst;
-    const T* mom_in;      // [3][ny][nx]: sum h, sum xi_x h, sum xi_y h of src
-    T* mom_out;           // same for dst
+    const double* mom_in; // [3][ny][nx]: sum h, sum xi_x h, sum xi_y h of src (always double)
+    double* mom_out;      // same for dst
     const double* phi_in; // [4][L]: sum over arriving half of |xi_n| h at each wall cell of src
     double* phi_out;
     double* partials;     // [nblocks][3]: sum |du|^2, sum |u|^2, max |u|^2
@@ -93,7 +93,7 @@ void launch_seed(T* h, int q, int64_t plane, const VelEntry<double>* vel, const 
                  const double* ux, const double* uy, const float* frho, const float* fux,
                  const float* fuy, const double* mass_scale, hipStream_t stream);
 template <class T>
-void launch_moments(const T* h, T* mom, double* phi, const VelEntry<double>* vel, int q, int nx, int ny,
+void launch_moments(const T* h, double* mom, double* phi, const VelEntry<T>* vel, int q, int nx, int ny,
                     int L, const WallConst* d_wall, hipStream_t stream);
 template <class T>
 void launch_post(const T* h, const VelEntry<double>* vel, int q, int nx, int ny, double omega,

@@ -108,14 +108,22 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
     for (int r = 0; r < K; ++r) rv[r] = xv && (y0 + r < ny);
 
     // Density and momentum (deviation form) of this lane's cells, from the previous step.
+    // They are carried in double; the relaxation uses them rounded to the storage type.
     T mr[K][VX], mx[K][VX], my[K][VX];
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         if (rv[r]) {
             const int64_t o = (int64_t)(y0 + r) * nx + x0;
-            vload<VX>(mr[r], A.mom_in + o);
-            vload<VX>(mx[r], A.mom_in + plane + o);
-            vload<VX>(my[r], A.mom_in + 2 * plane + o);
+            double t0[VX], t1[VX], t2[VX];
+            vload<VX>(t0, A.mom_in + o);
+            vload<VX>(t1, A.mom_in + plane + o);
+            vload<VX>(t2, A.mom_in + 2 * plane + o);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                mr[r][v] = (T)t0[v];
+                mx[r][v] = (T)t1[v];
+                my[r][v] = (T)t2[v];
+            }
         } else {
 #pragma unroll
             for (int v = 0; v < VX; ++v) mr[r][v] = mx[r][v] = my[r][v] = T(0);
@@ -147,9 +155,10 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
         for (int r = 0; r < K; ++r) {
             if (rv[r]) {
                 const double phi = A.phi_in[xw * L + y0 + r];
+                const int64_t o = (int64_t)(y0 + r) * nx + x0 + vi;
                 const double s = (1.0 - omega) * phi +
-                                 omega * ((double)mr[r][vi] * W.A + sn * (double)mx[r][vi] * W.Bn +
-                                          (double)my[r][vi] * W.Bt);
+                                 omega * (A.mom_in[o] * W.A + sn * A.mom_in[plane + o] * W.Bn +
+                                          A.mom_in[2 * plane + o] * W.Bt);
                 const double P = W.c0 + SQRT_2PI * s;
                 Px[r] = (T)P;
                 Qx[r] = (T)(W.u * (1.0 + P));
@@ -169,17 +178,10 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
         const int rw = on_bot ? 0 : r_top;
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            T wr = T(0), wx = T(0), wy = T(0);
-#pragma unroll
-            for (int r = 0; r < K; ++r)
-                if (r == rw) {
-                    wr = mr[r][v];
-                    wx = mx[r][v];
-                    wy = my[r][v];
-                }
+            const int64_t o = (int64_t)(y0 + rw) * nx + x0 + v;
+            const double wr = A.mom_in[o], wx = A.mom_in[plane + o], wy = A.mom_in[2 * plane + o];
             const double phi = A.phi_in[yw * L + x0 + v];
-            const double s = (1.0 - omega) * phi +
-                             omega * ((double)wr * W.A + sn * (double)wy * W.Bn + (double)wx * W.Bt);
+            const double s = (1.0 - omega) * phi + omega * (wr * W.A + sn * wy * W.Bn + wx * W.Bt);
             const double P = W.c0 + SQRT_2PI * s;
             Py[v] = (T)P;
             Qy[v] = (T)(W.u * (1.0 + P));
@@ -187,12 +189,14 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
     }
     const int r_top_in = (r_top >= 0 && r_top < K - 1) ? r_top : -1;
 
-    // Moments of the new state, accumulated over all velocities.
-    T ar[K][VX], ax[K][VX], ay[K][VX];
+    // Moments of the new state, accumulated over all velocities in double (a float sum of
+    // terms dominated by the even part w rho_h would carry ~1e-7 relative noise into the
+    // momentum and hence into the residual).
+    double ar[K][VX], ax[K][VX], ay[K][VX];
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
-        for (int v = 0; v < VX; ++v) ar[r][v] = ax[r][v] = ay[r][v] = T(0);
+        for (int v = 0; v < VX; ++v) ar[r][v] = ax[r][v] = ay[r][v] = 0.0;
 
     auto quadrant = [&](auto sxc, auto syc, const int qb, const int qe) {
         constexpr int SX = decltype(sxc)::value;
@@ -223,20 +227,26 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
             hxr[r] = hxx[r] = hxy[r] = T(0);
             if (xmode == MODE_LOAD && rv[r]) {
                 const int64_t o = (int64_t)(y0 + r) * nx + xh;
-                hxr[r] = A.mom_in[o];
-                hxx[r] = A.mom_in[plane + o];
-                hxy[r] = A.mom_in[2 * plane + o];
+                hxr[r] = (T)A.mom_in[o];
+                hxx[r] = (T)A.mom_in[plane + o];
+                hxy[r] = (T)A.mom_in[2 * plane + o];
             }
         }
         T hyr[VX], hyx[VX], hyy[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) hyr[v] = hyx[v] = hyy[v] = T(0);
         if (ymode == MODE_LOAD) {
             const int64_t o = (int64_t)yh * nx + x0;
-            vload<VX>(hyr, A.mom_in + o);
-            vload<VX>(hyx, A.mom_in + plane + o);
-            vload<VX>(hyy, A.mom_in + 2 * plane + o);
-        } else {
+            double t0[VX], t1[VX], t2[VX];
+            vload<VX>(t0, A.mom_in + o);
+            vload<VX>(t1, A.mom_in + plane + o);
+            vload<VX>(t2, A.mom_in + 2 * plane + o);
 #pragma unroll
-            for (int v = 0; v < VX; ++v) hyr[v] = hyx[v] = hyy[v] = T(0);
+            for (int v = 0; v < VX; ++v) {
+                hyr[v] = (T)t0[v];
+                hyx[v] = (T)t1[v];
+                hyy[v] = (T)t2[v];
+            }
         }
 
         for (int e = qb; e < qe; ++e) {
@@ -321,9 +331,10 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
             for (int r = 0; r < K; ++r)
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    ar[r][v] += fn[r][v];
-                    ax[r][v] += c.xx * fn[r][v];
-                    ay[r][v] += c.xy * fn[r][v];
+                    const double fd = (double)fn[r][v];
+                    ar[r][v] += fd;
+                    ax[r][v] += (double)c.xx * fd;
+                    ay[r][v] += (double)c.xy * fd;
                 }
             if constexpr (SX < 0) {
                 if (on_left) {
@@ -385,17 +396,23 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
         for (int v = 0; v < VX; ++v) A.phi_out[yw * L + x0 + v] = phy[v];
     }
 
-    // Residual partials: sum |u_new - u_old|^2, sum |u_new|^2, max |u_new|^2.
+    // Residual partials: sum |u_new - u_old|^2, sum |u_new|^2, max |u_new|^2, from the
+    // double moments (the old ones re-read rather than kept in registers).
     double num = 0.0, den = 0.0, umax = 0.0;
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         if (rv[r]) {
+            const int64_t o = (int64_t)(y0 + r) * nx + x0;
+            double m0[VX], m1[VX], m2[VX];
+            vload<VX>(m0, A.mom_in + o);
+            vload<VX>(m1, A.mom_in + plane + o);
+            vload<VX>(m2, A.mom_in + 2 * plane + o);
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                const double r0 = 1.0 + (double)mr[r][v];
-                const double ux0 = (double)mx[r][v] / r0, uy0 = (double)my[r][v] / r0;
-                const double r1 = 1.0 + (double)ar[r][v];
-                const double ux1 = (double)ax[r][v] / r1, uy1 = (double)ay[r][v] / r1;
+                const double r0 = 1.0 + m0[v];
+                const double ux0 = m1[v] / r0, uy0 = m2[v] / r0;
+                const double r1 = 1.0 + ar[r][v];
+                const double ux1 = ax[r][v] / r1, uy1 = ay[r][v] / r1;
                 const double dx = ux1 - ux0, dy = uy1 - uy0;
                 const double u2 = ux1 * ux1 + uy1 * uy1;
                 num += dx * dx + dy * dy;
@@ -510,32 +527,36 @@ __global__ void __launch_bounds__(1024) mass_scale_kernel(const float* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Moments and wall fluxes of a state (after seeding or upload).
+// Moments and wall fluxes of a state (after seeding or upload), accumulated
+// exactly as the step kernel accumulates them for its output: velocity-table
+// order, moments in the storage type, wall fluxes in double.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) moments_kernel(const T* __restrict__ h, T* __restrict__ mom,
+__global__ void __launch_bounds__(256) moments_kernel(const T* __restrict__ h, double* __restrict__ mom,
                                                       double* __restrict__ phi,
-                                                      const VelEntry<double>* __restrict__ vel, int q,
+                                                      const VelEntry<T>* __restrict__ vel, int q,
                                                       int nx, int ny, int L, const WallConst* wall) {
     const int64_t plane = (int64_t)nx * ny;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= plane) return;
     const int x = (int)(c % nx), y = (int)(c / nx);
-    double r = 0, jx = 0, jy = 0, pb = 0, pt = 0, pl = 0, pr = 0;
+    double r = 0, jx = 0, jy = 0;
+    double pb = 0, pt = 0, pl = 0, pr = 0;
     for (int e = 0; e < q; ++e) {
-        const VelEntry<double> v = vel[e];
-        const double f = (double)h[(int64_t)v.alpha * plane + c];
-        r += f;
-        jx += v.xx * f;
-        jy += v.xy * f;
-        if (v.xy < 0) pb += -v.xy * f;
-        if (v.xy > 0) pt += v.xy * f;
-        if (v.xx < 0) pl += -v.xx * f;
-        if (v.xx > 0) pr += v.xx * f;
+        const VelEntry<T> v = vel[e];
+        const T f = h[(int64_t)v.alpha * plane + c];
+        const double fd = (double)f;
+        r += fd;
+        jx += (double)v.xx * fd;
+        jy += (double)v.xy * fd;
+        if (v.xy < 0) pb += -(double)v.xy * (double)f;
+        else pt += (double)v.xy * (double)f;
+        if (v.xx < 0) pl += -(double)v.xx * (double)f;
+        else pr += (double)v.xx * (double)f;
     }
-    mom[c] = (T)r;
-    mom[plane + c] = (T)jx;
-    mom[2 * plane + c] = (T)jy;
+    mom[c] = r;
+    mom[plane + c] = jx;
+    mom[2 * plane + c] = jy;
     if (wall[BOTTOM].active && y == 0) phi[BOTTOM * L + x] = pb;
     if (wall[TOP].active && y == ny - 1) phi[TOP * L + x] = pt;
     if (wall[LEFT].active && x == 0) phi[LEFT * L + y] = pl;
@@ -743,7 +764,7 @@ void launch_mass_scale(const float* frho, int64_t cells, double* scale_out, hipS
 }
 
 template <class T>
-void launch_moments(const T* h, T* mom, double* phi, const VelEntry<double>* vel, int q, int nx, int ny,
+void launch_moments(const T* h, double* mom, double* phi, const VelEntry<T>* vel, int q, int nx, int ny,
                     int L, const WallConst* wall, hipStream_t stream) {
     hipLaunchKernelGGL(moments_kernel<T>, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, stream, h,
                        mom, phi, vel, q, nx, ny, L, wall);
@@ -802,7 +823,7 @@ void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
     template void launch_seed<T>(T*, int, int64_t, const VelEntry<double>*, const double*, const double*, \
                                  const double*, const float*, const float*, const float*, const double*, \
                                  hipStream_t);                                                            \
-    template void launch_moments<T>(const T*, T*, double*, const VelEntry<double>*, int, int, int, int,   \
+    template void launch_moments<T>(const T*, double*, double*, const VelEntry<T>*, int, int, int, int,   \
                                     const WallConst*, hipStream_t);                                       \
     template void launch_post<T>(const T*, const VelEntry<double>*, int, int, int, double, double*,       \
                                  hipStream_t);                                                            \

@@ -164,7 +164,7 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     }
     p.max_blocks = maxb;
     size_t off = 0;
-    p.mom_bytes = align256(3 * (size_t)p.plane * p.elem);
+    p.mom_bytes = align256(3 * (size_t)p.plane * sizeof(double));
     p.off_mom = off;
     off += 2 * p.mom_bytes;
     p.phi_bytes = align256(4 * (size_t)p.L * sizeof(double));
@@ -275,8 +275,9 @@ static void reset_ctrl(fdlb_problem& p, double tol) {
 static void refresh_moments(fdlb_problem& p) {
     const int par = p.parity;
     if (p.d.precision == FDLB_FP32)
-        launch_moments<float>((const float*)pop_buf(p, par), (float*)mom_buf(p, par), phi_buf(p, par), vel64(p), p.q,
-                              p.d.nx, p.d.ny, p.L, (const WallConst*)(p.d_work + p.off_wall), p.stream);
+        launch_moments<float>((const float*)pop_buf(p, par), (double*)mom_buf(p, par), phi_buf(p, par),
+                              (const VelEntry<float>*)(p.d_work + p.off_vel), p.q, p.d.nx, p.d.ny, p.L,
+                              (const WallConst*)(p.d_work + p.off_wall), p.stream);
     else
         launch_moments<double>((const double*)pop_buf(p, par), (double*)mom_buf(p, par), phi_buf(p, par), vel64(p),
                                p.q, p.d.nx, p.d.ny, p.L, (const WallConst*)(p.d_work + p.off_wall), p.stream);
@@ -383,6 +384,40 @@ void state_download(fdlb_problem& p, double* f) {
     }
 }
 
+// Exact checkpoint: the current population buffer, its moment and wall-flux
+// buffers and the step counter, as raw device bytes.
+size_t checkpoint_bytes(const fdlb_problem& p) {
+    return p.pop_bytes + p.mom_bytes + p.phi_bytes + 8 * sizeof(double);
+}
+
+void checkpoint_save(fdlb_problem& p, void* host) {
+    require_seeded(p);
+    if (!host) throw Error(FDLB_EINVAL, "NULL host buffer");
+    char* h = (char*)host;
+    FDLB_HIP(hipMemcpyAsync(h, pop_buf(p, p.parity), p.pop_bytes, hipMemcpyDeviceToHost, p.stream));
+    FDLB_HIP(hipMemcpyAsync(h + p.pop_bytes, mom_buf(p, p.parity), p.mom_bytes, hipMemcpyDeviceToHost, p.stream));
+    FDLB_HIP(hipMemcpyAsync(h + p.pop_bytes + p.mom_bytes, phi_buf(p, p.parity), p.phi_bytes, hipMemcpyDeviceToHost,
+                            p.stream));
+    FDLB_HIP(hipMemcpyAsync(h + p.pop_bytes + p.mom_bytes + p.phi_bytes, ctrl(p), 8 * sizeof(double),
+                            hipMemcpyDeviceToHost, p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+}
+
+void checkpoint_load(fdlb_problem& p, const void* host) {
+    require_bound(p);
+    if (!host) throw Error(FDLB_EINVAL, "NULL host buffer");
+    const char* h = (const char*)host;
+    p.parity = 0;
+    FDLB_HIP(hipMemcpyAsync(pop_buf(p, 0), h, p.pop_bytes, hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipMemcpyAsync(mom_buf(p, 0), h + p.pop_bytes, p.mom_bytes, hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipMemcpyAsync(phi_buf(p, 0), h + p.pop_bytes + p.mom_bytes, p.phi_bytes, hipMemcpyHostToDevice,
+                            p.stream));
+    FDLB_HIP(hipMemcpyAsync(ctrl(p), h + p.pop_bytes + p.mom_bytes + p.phi_bytes, 8 * sizeof(double),
+                            hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+    p.seeded = true;
+}
+
 // ---------------------------------------------------------------------------
 // Time marching.
 // ---------------------------------------------------------------------------
@@ -393,8 +428,8 @@ static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile) {
     std::memset(&a, 0, sizeof(a));
     a.src = (const T*)pop_buf(p, parity);
     a.dst = (T*)pop_buf(p, parity ^ 1);
-    a.mom_in = (const T*)mom_buf(p, parity);
-    a.mom_out = (T*)mom_buf(p, parity ^ 1);
+    a.mom_in = (const double*)mom_buf(p, parity);
+    a.mom_out = (double*)mom_buf(p, parity ^ 1);
     a.phi_in = phi_buf(p, parity);
     a.phi_out = phi_buf(p, parity ^ 1);
     a.partials = (double*)(p.d_work + p.off_part);

