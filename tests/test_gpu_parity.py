@@ -322,7 +322,9 @@ def test_solve_report(F):
     assert len(rep["history"]) == rep["steps"] // 64
     assert rep["history"][-2] >= 1e-6   # no step of the previous chunks was below tol
     assert rep["updates_per_s"] > 0 and rep["bytes_per_s"] == pytest.approx(rep["updates_per_s"] * 8)
-    rep2 = p.solve(1e-6, 10, check_every=5)
+    # the residual is not monotone (the cavity relaxes through damped acoustic waves), so a
+    # further solve is checked against a tolerance far above the current level
+    rep2 = p.solve(1e-3, 10, check_every=5)
     assert rep2["status"] == 0 and rep2["steps"] == 5
     rep3 = p.solve(1e-30, 10, check_every=5)
     assert rep3["status"] == 1 and rep3["first_below"] == -1
