@@ -91,7 +91,7 @@ def test_time_step_and_velocities_match_oracle(F, case):
 def test_sizes(F):
     p = F.Problem(W.C4, bind=False)
     assert p.state_bytes == 2 * 256 * 1024 * 1024 * 4
-    assert p.workspace_bytes < 64 * 2 ** 20
+    assert p.workspace_bytes < 128 * 2 ** 20   # FP64 moments (48 MB) + staging (32 MB) for 1024^2
     p = F.Problem(W.C1, bind=False)
     assert p.state_bytes == 2 * ((24 * 200 * 8 + 255) // 256 * 256)
 
