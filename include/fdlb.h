@@ -218,11 +218,13 @@ typedef struct fdlb_report {
 
 /*
  * March until the residual of a step falls below tol or max_steps steps have
- * been taken; the host reads the residual every check_every steps (the only
- * device-to-host synchronisation in the loop), so up to check_every - 1 steps
- * may run past the first one below tol (report.first_below says where).
- * use_graph = 1 replays check_every steps as one captured HIP graph.
- * Synchronous.  Returns FDLB_OK, FDLB_ENOTCONVERGED or FDLB_EDIVERGED.
+ * been taken.  The device stops updating the state at the first step whose
+ * residual is below tol (or that diverges), so the state returned is that
+ * step's; the host reads the control block every check_every steps (the only
+ * device-to-host synchronisation in the loop).  use_graph = 1 replays
+ * check_every steps as one captured HIP graph.  A later fdlb_step resumes
+ * unconditional stepping.  Synchronous.  Returns FDLB_OK, FDLB_ENOTCONVERGED
+ * or FDLB_EDIVERGED.
  */
 int fdlb_solve_steady(fdlb_problem *p, double tol, int64_t max_steps, int32_t check_every,
                       int32_t use_graph, fdlb_report *report);
@@ -261,6 +263,52 @@ int fdlb_tile_describe(int precision, int tile, char *buf, size_t len);
 int fdlb_problem_set_tile(fdlb_problem *p, int tile);
 int fdlb_problem_get_tile(const fdlb_problem *p);
 int fdlb_autotune(fdlb_problem *p, int steps, double *best_ms_per_step);
+
+/* ---- batches ---------------------------------------------------------------------- */
+
+typedef struct fdlb_batch fdlb_batch; /* opaque: many independent problems, one launch per step */
+
+/*
+ * Build a batch of n problems (each validated as by fdlb_problem_create; all
+ * must share the precision).  Every instance's state and workspace live in
+ * one caller-provided arena each.  Host only.
+ */
+int fdlb_batch_create(const fdlb_problem_desc *descs, int n, fdlb_batch **out);
+void fdlb_batch_destroy(fdlb_batch *b);
+size_t fdlb_batch_state_bytes(const fdlb_batch *b);
+size_t fdlb_batch_workspace_bytes(const fdlb_batch *b);
+int fdlb_batch_bind(fdlb_batch *b, void *d_state, void *d_workspace, void *stream);
+/* Seed instance i as fdlb_init_equilibrium / fdlb_init_equilibrium_dev do. */
+int fdlb_batch_init_equilibrium(fdlb_batch *b, int i, const double *rho, const double *ux,
+                                const double *uy, int renormalize_mass);
+int fdlb_batch_init_equilibrium_dev(fdlb_batch *b, int i, const float *d_rho, const float *d_ux,
+                                    const float *d_uy, int renormalize_mass);
+/*
+ * March every instance until its own residual falls below tol or max_steps.
+ * Instances retire individually: an instance stops being updated at the first
+ * step below tol (or at divergence), on the device, and leaves the launch at
+ * the next host check.  All active instances advance together: one step-kernel
+ * launch and one reduction launch per time step for the whole batch; the host
+ * polls every check_every steps; use_graph replays check_every steps as one
+ * captured graph.  All instances must have been initialised (and have taken
+ * step counts of equal parity).  reports: caller array of n entries (may be
+ * NULL; each entry's history/history_cap are honoured).
+ * Returns FDLB_OK when every instance converged, FDLB_ENOTCONVERGED if some
+ * did not, FDLB_EDIVERGED if some diverged (each report says which).
+ * Synchronous.
+ */
+int fdlb_batch_solve(fdlb_batch *b, double tol, int64_t max_steps, int32_t check_every,
+                     int32_t use_graph, fdlb_report *reports);
+int fdlb_batch_moments(fdlb_batch *b, int i, double *rho, double *ux, double *uy, double *pxy);
+int fdlb_batch_state_download(fdlb_batch *b, int i, double *f_host);
+/*
+ * One tile shape serves the whole batch (it must fit every problem).  fdlb_batch_autotune
+ * times every fitting shape on the whole batch for `steps` steps (every problem is re-seeded
+ * at rest afterwards) and keeps the fastest.  Synchronous.
+ */
+int fdlb_batch_set_tile(fdlb_batch *b, int tile);
+int fdlb_batch_get_tile(const fdlb_batch *b);
+int fdlb_batch_autotune(fdlb_batch *b, int steps, double *best_ms_per_step);
 
 /* ---- measurement helpers ------------------------------------------------------------ */
 

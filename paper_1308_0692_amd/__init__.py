@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (BOTTOM, LEFT, RIGHT, TOP, FdlbError, check, desc_from_case, make_desc,
                    quad_full_range, quad_half_range, tile_count, tile_describe)
 
-__all__ = ["Problem", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
+__all__ = ["Problem", "Batch", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
            "RIGHT", "tile_count", "tile_describe", "stream_copy"]
 
 
@@ -194,3 +194,97 @@ def stream_copy(dst, src, nbytes: int, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     check(_lib.lib.fdlb_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
                                     int(nbytes), C.c_void_p(s.cuda_stream)))
+
+
+class Batch:
+    """Many independent problems solved together (one launch per step for all of them)."""
+
+    def __init__(self, cases, *, precision: Optional[str] = None, allow_unstable=False, device="cuda:0",
+                 stream=None, descs=None):
+        torch = _torch()
+        if descs is None:
+            descs = [desc_from_case(c, precision, allow_unstable) for c in cases]
+        self.n = len(descs)
+        arr = (_lib.ProblemDesc * self.n)(*descs)
+        h = C.c_void_p()
+        check(_lib.lib.fdlb_batch_create(arr, self.n, C.byref(h)))
+        self._h = h
+        self.shapes = [(d.nx, d.ny) for d in descs]
+        self.precision = "fp32" if descs[0].precision == _lib.FP32 else "fp64"
+        self.device = device
+        self._stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self._state_t, self._state = _alloc(_lib.lib.fdlb_batch_state_bytes(h), device)
+        self._work_t, self._work = _alloc(_lib.lib.fdlb_batch_workspace_bytes(h), device)
+        check(_lib.lib.fdlb_batch_bind(h, C.c_void_p(self._state), C.c_void_p(self._work),
+                                       C.c_void_p(self._stream.cuda_stream)))
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def init_equilibrium(self, i: int, rho=None, ux=None, uy=None, renormalize: bool = False):
+        nx, ny = self.shapes[i]
+        arr = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(ny, nx)
+               for a in (rho, ux, uy)]
+        check(_lib.lib.fdlb_batch_init_equilibrium(self._h, int(i), *[_lib._dp(a) for a in arr],
+                                                   int(renormalize)))
+
+    def init_equilibrium_dev(self, i: int, rho, ux, uy, renormalize: bool = True):
+        torch = _torch()
+        ts = [t.contiguous().to(torch.float32) for t in (rho, ux, uy)]
+        self._stream.wait_stream(torch.cuda.current_stream(self.device))
+        ptrs = [C.cast(C.c_void_p(t.data_ptr()), C.POINTER(C.c_float)) for t in ts]
+        check(_lib.lib.fdlb_batch_init_equilibrium_dev(self._h, int(i), *ptrs, int(renormalize)))
+        self._stream.synchronize()
+
+    def solve(self, tol: float, max_steps: int, check_every: int = 100, use_graph: bool = True,
+              history_cap: int = 0):
+        """Returns (status, [report dict per problem])."""
+        reps = (_lib.Report * self.n)()
+        hists = [np.zeros(max(history_cap, 1)) for _ in range(self.n)]
+        for r, h in zip(reps, hists):
+            r.history_cap = history_cap
+            r.history = _lib._dp(h) if history_cap else None
+        code = _lib.lib.fdlb_batch_solve(self._h, float(tol), int(max_steps), int(check_every),
+                                         int(use_graph), reps)
+        check(code, allow=(_lib.OK, _lib.ENOTCONVERGED, _lib.EDIVERGED))
+        out = [dict(status=r.status, steps=r.steps, first_below=r.first_below, residual=r.residual,
+                    wall_s=r.wall_s, updates_per_s=r.updates_per_s, history=h[:r.history_len].copy())
+               for r, h in zip(reps, hists)]
+        return code, out
+
+    def moments(self, i: int):
+        nx, ny = self.shapes[i]
+        out = [np.empty((ny, nx)) for _ in range(4)]
+        check(_lib.lib.fdlb_batch_moments(self._h, int(i), *[_lib._dp(a) for a in out]))
+        return tuple(out)
+
+    def download(self, i: int, q: int) -> np.ndarray:
+        nx, ny = self.shapes[i]
+        f = np.empty((q, ny, nx))
+        check(_lib.lib.fdlb_batch_state_download(self._h, int(i), _lib._dp(f)))
+        return f
+
+    @property
+    def tile(self) -> int:
+        return _lib.lib.fdlb_batch_get_tile(self._h)
+
+    def set_tile(self, tile: int):
+        check(_lib.lib.fdlb_batch_set_tile(self._h, int(tile)))
+
+    def autotune(self, steps: int = 5) -> float:
+        ms = C.c_double()
+        check(_lib.lib.fdlb_batch_autotune(self._h, int(steps), C.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._stream.synchronize()
+            _lib.lib.fdlb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -86,6 +86,19 @@ def _load():
         "fdlb_problem_get_tile": (C.c_int, [vp]),
         "fdlb_autotune": (C.c_int, [vp, C.c_int, dp]),
         "fdlb_stream_copy": (C.c_int, [vp, vp, C.c_size_t, vp]),
+        "fdlb_batch_create": (C.c_int, [C.POINTER(ProblemDesc), C.c_int, C.POINTER(vp)]),
+        "fdlb_batch_destroy": (None, [vp]),
+        "fdlb_batch_state_bytes": (C.c_size_t, [vp]),
+        "fdlb_batch_workspace_bytes": (C.c_size_t, [vp]),
+        "fdlb_batch_bind": (C.c_int, [vp, vp, vp, vp]),
+        "fdlb_batch_init_equilibrium": (C.c_int, [vp, C.c_int, dp, dp, dp, C.c_int]),
+        "fdlb_batch_init_equilibrium_dev": (C.c_int, [vp, C.c_int, fp, fp, fp, C.c_int]),
+        "fdlb_batch_solve": (C.c_int, [vp, C.c_double, i64, i32, i32, C.POINTER(Report)]),
+        "fdlb_batch_moments": (C.c_int, [vp, C.c_int, dp, dp, dp, dp]),
+        "fdlb_batch_state_download": (C.c_int, [vp, C.c_int, dp]),
+        "fdlb_batch_set_tile": (C.c_int, [vp, C.c_int]),
+        "fdlb_batch_get_tile": (C.c_int, [vp]),
+        "fdlb_batch_autotune": (C.c_int, [vp, C.c_int, dp]),
         "fdlb_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -1,0 +1,508 @@
+// Batched steady solves: many independent problems (different Kn, grids and velocity sets,
+// one precision) advanced together, one step-kernel launch and one reduction launch per
+// time step for all of them.
+//
+// Every problem keeps its own state, workspace and control block inside two caller-owned
+// arenas.  A block map assigns each block of the launch to (problem, tile); each problem's
+// blocks start at a multiple of 8 so that the XCD-aware tile order holds per problem.  A
+// problem whose residual falls below the tolerance (or diverges) freezes on the device at
+// that step; the host drops it from the block map at the next check, so the remaining
+// problems keep the chip.  Chunks of `check_every` steps are replayed as captured graphs.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+
+#include "fdlb_internal.h"
+
+namespace fdlb {
+void build_problem(fdlb_problem& p, const fdlb_problem_desc& d);
+void bind(fdlb_problem& p, void* d_state, void* d_work, void* stream);
+void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, const double* uy, int renorm);
+void init_equilibrium_dev(fdlb_problem& p, const float* rho, const float* ux, const float* uy, int renorm);
+void moments(fdlb_problem& p, double* rho, double* ux, double* uy, double* pxy);
+void state_download(fdlb_problem& p, double* f);
+}  // namespace fdlb
+
+struct fdlb_batch {
+    std::vector<std::unique_ptr<fdlb_problem>> probs;
+    int precision = FDLB_FP32;
+    int tile = -1;
+    std::vector<size_t> state_off, work_off;
+    size_t state_bytes = 0, work_bytes = 0;
+    size_t off_map = 0, off_args = 0, off_rargs = 0;  // batch region inside the workspace arena
+    int max_map = 0;
+    char* d_state = nullptr;
+    char* d_work = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    double* pinned = nullptr;       // n x 8 control doubles
+    std::vector<int> active;        // problems in the current block map
+    int map_blocks = 0;
+    int map_version = 0;
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (k, parity, map version, tile)
+    ~fdlb_batch() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+namespace fdlb {
+
+namespace {
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+int nblocks_tile(const fdlb_problem& p, const TileShape& t) {
+    return ((p.d.nx + t.tile_w() - 1) / t.tile_w()) * ((p.d.ny + t.tile_h() - 1) / t.tile_h());
+}
+
+bool tile_fits_all(const fdlb_batch& b, int tile) {
+    const TileShape& t = tile_shapes(b.precision)[tile];
+    for (auto& p : b.probs) {
+        if (!tile_fits(t, p->d.nx, p->d.ny, p->d.periodic_x, p->d.periodic_y)) return false;
+        if (nblocks_tile(*p, t) > p->max_blocks) return false;
+    }
+    return true;
+}
+
+double* ctrl_of(fdlb_problem& p) { return (double*)(p.d_work + p.off_ctrl); }
+}  // namespace
+
+void batch_set_tile(fdlb_batch& b, int tile);
+
+void batch_create(fdlb_batch& b, const fdlb_problem_desc* descs, int n) {
+    if (!descs || n < 1) throw Error(FDLB_EINVAL, "a batch needs at least one problem");
+    b.precision = descs[0].precision;
+    for (int i = 0; i < n; ++i) {
+        if (descs[i].precision != b.precision) throw Error(FDLB_EINVAL, "all problems of a batch share the precision");
+        auto p = std::make_unique<fdlb_problem>();
+        try {
+            build_problem(*p, descs[i]);
+        } catch (const Error& e) {
+            throw Error(e.code, "problem " + std::to_string(i) + ": " + e.msg);
+        }
+        b.probs.push_back(std::move(p));
+    }
+    // Arenas: each problem's state and workspace, then the batch region.
+    size_t so = 0, wo = 0;
+    for (auto& p : b.probs) {
+        b.state_off.push_back(so);
+        b.work_off.push_back(wo);
+        so += align256(p->state_bytes);
+        wo += align256(p->work_bytes);
+    }
+    int maxmap = 0;
+    for (const TileShape& t : tile_shapes(b.precision)) {
+        int tot = 0;
+        for (auto& p : b.probs) tot += (nblocks_tile(*p, t) + 7) / 8 * 8;
+        maxmap = std::max(maxmap, tot);
+    }
+    b.max_map = maxmap;
+    b.off_map = wo;
+    wo += align256((size_t)maxmap * sizeof(BlockMap));
+    b.off_args = wo;
+    const size_t argsz = b.precision == FDLB_FP32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
+    wo += align256(2 * (size_t)n * argsz);
+    b.off_rargs = wo;
+    wo += align256((size_t)n * sizeof(ReduceArgs));
+    b.state_bytes = so;
+    b.work_bytes = wo;
+    // Default tile: the built-in choice for the largest problem if it fits all, else any that does.
+    int big = 0;
+    for (int i = 1; i < n; ++i)
+        if (b.probs[i]->plane * b.probs[i]->q > b.probs[big]->plane * b.probs[big]->q) big = i;
+    const fdlb_problem& pb = *b.probs[big];
+    int t = heuristic_tile_for(b.precision, pb.d.nx, pb.d.ny, pb.d.periodic_x, pb.d.periodic_y);
+    if (!tile_fits_all(b, t)) {
+        t = -1;
+        for (int i = 0; i < (int)tile_shapes(b.precision).size(); ++i)
+            if (tile_fits_all(b, i)) {
+                t = i;
+                break;
+            }
+        if (t < 0) throw Error(FDLB_EINVAL, "no compiled tile shape fits every problem of the batch");
+    }
+    batch_set_tile(b, t);
+}
+
+void batch_set_tile(fdlb_batch& b, int tile) {
+    if (tile < 0 || tile >= (int)tile_shapes(b.precision).size()) throw Error(FDLB_EINVAL, "tile index out of range");
+    if (!tile_fits_all(b, tile)) throw Error(FDLB_EINVAL, "tile shape does not fit every problem of the batch");
+    b.tile = tile;
+    for (auto& p : b.probs) p->tile = tile;
+}
+
+void batch_bind(fdlb_batch& b, void* d_state, void* d_work, void* stream) {
+    if (!d_state || !d_work) throw Error(FDLB_EINVAL, "device buffers must not be NULL");
+    for (auto& kv : b.graphs) (void)hipGraphExecDestroy(kv.second);
+    b.graphs.clear();
+    b.d_state = (char*)d_state;
+    b.d_work = (char*)d_work;
+    b.stream = (hipStream_t)stream;
+    for (size_t i = 0; i < b.probs.size(); ++i) bind(*b.probs[i], b.d_state + b.state_off[i], b.d_work + b.work_off[i], stream);
+    if (!b.pinned)
+        FDLB_HIP(hipHostMalloc((void**)&b.pinned, b.probs.size() * 8 * sizeof(double), hipHostMallocDefault));
+    b.bound = true;
+}
+
+static fdlb_problem& inst(fdlb_batch& b, int i) {
+    if (i < 0 || i >= (int)b.probs.size()) throw Error(FDLB_EINVAL, "instance index out of range");
+    return *b.probs[i];
+}
+
+void batch_init_equilibrium(fdlb_batch& b, int i, const double* rho, const double* ux, const double* uy, int renorm) {
+    init_equilibrium(inst(b, i), rho, ux, uy, renorm);
+}
+void batch_init_equilibrium_dev(fdlb_batch& b, int i, const float* rho, const float* ux, const float* uy, int renorm) {
+    init_equilibrium_dev(inst(b, i), rho, ux, uy, renorm);
+}
+void batch_moments(fdlb_batch& b, int i, double* rho, double* ux, double* uy, double* pxy) {
+    moments(inst(b, i), rho, ux, uy, pxy);
+}
+void batch_state_download(fdlb_batch& b, int i, double* f) { state_download(inst(b, i), f); }
+
+template <class T>
+static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile) {
+    const TileShape& t = tile_shapes(p.d.precision)[tile];
+    StepArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    char* pop = p.d_state;
+    char* mom = p.d_work + p.off_mom;
+    char* phi = p.d_work + p.off_phi;
+    a.src = (const T*)(pop + (size_t)parity * p.pop_bytes);
+    a.dst = (T*)(pop + (size_t)(parity ^ 1) * p.pop_bytes);
+    a.mom_in = (const double*)(mom + (size_t)parity * p.mom_bytes);
+    a.mom_out = (double*)(mom + (size_t)(parity ^ 1) * p.mom_bytes);
+    a.phi_in = (const double*)(phi + (size_t)parity * p.phi_bytes);
+    a.phi_out = (double*)(phi + (size_t)(parity ^ 1) * p.phi_bytes);
+    a.partials = (double*)(p.d_work + p.off_part);
+    a.ctrl = ctrl_of(p);
+    a.vel = (const VelEntry<T>*)(p.d_work + p.off_vel);
+    for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
+    a.nx = p.d.nx;
+    a.ny = p.d.ny;
+    a.L = p.L;
+    a.tiles_x = (p.d.nx + t.tile_w() - 1) / t.tile_w();
+    a.tiles_y = (p.d.ny + t.tile_h() - 1) / t.tile_h();
+    a.plane = p.plane;
+    a.c1 = (T)(1.0 - p.omega);
+    for (int i = 0; i < 4; ++i) a.wall[i] = p.wall[i];
+    return a;
+}
+
+// Upload the per-problem step and reduce arguments (both parities).
+static void upload_args(fdlb_batch& b) {
+    const int n = (int)b.probs.size();
+    std::vector<ReduceArgs> ra(n);
+    for (int i = 0; i < n; ++i) {
+        fdlb_problem& p = *b.probs[i];
+        ra[i].partials = (const double*)(p.d_work + p.off_part);
+        ra[i].ctrl = ctrl_of(p);
+        ra[i].nb = nblocks_tile(p, tile_shapes(b.precision)[b.tile]);
+        ra[i].pad = 0;
+    }
+    if (b.precision == FDLB_FP32) {
+        std::vector<StepArgs<float>> a(2 * n);
+        for (int par = 0; par < 2; ++par)
+            for (int i = 0; i < n; ++i) a[par * n + i] = batch_step_args<float>(*b.probs[i], par, b.tile);
+        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_args, a.data(), a.size() * sizeof(a[0]), hipMemcpyHostToDevice, b.stream));
+        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_rargs, ra.data(), n * sizeof(ReduceArgs), hipMemcpyHostToDevice, b.stream));
+        FDLB_HIP(hipStreamSynchronize(b.stream));
+    } else {
+        std::vector<StepArgs<double>> a(2 * n);
+        for (int par = 0; par < 2; ++par)
+            for (int i = 0; i < n; ++i) a[par * n + i] = batch_step_args<double>(*b.probs[i], par, b.tile);
+        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_args, a.data(), a.size() * sizeof(a[0]), hipMemcpyHostToDevice, b.stream));
+        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_rargs, ra.data(), n * sizeof(ReduceArgs), hipMemcpyHostToDevice, b.stream));
+        FDLB_HIP(hipStreamSynchronize(b.stream));
+    }
+}
+
+// Block map of the active problems.
+static void upload_map(fdlb_batch& b) {
+    std::vector<BlockMap> m;
+    const TileShape& t = tile_shapes(b.precision)[b.tile];
+    for (int i : b.active) {
+        const int nb = nblocks_tile(*b.probs[i], t);
+        for (int l = 0; l < nb; ++l) m.push_back(BlockMap{i, l, nb, 0});
+        while (m.size() % 8) m.push_back(BlockMap{-1, 0, 0, 0});
+    }
+    b.map_blocks = (int)m.size();
+    if (b.map_blocks > b.max_map) throw Error(FDLB_EINVAL, "block map overflow");
+    if (!m.empty())
+        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_map, m.data(), m.size() * sizeof(BlockMap), hipMemcpyHostToDevice,
+                                b.stream));
+    FDLB_HIP(hipStreamSynchronize(b.stream));
+    ++b.map_version;
+}
+
+static void enqueue_batch_step(fdlb_batch& b, int parity) {
+    const int n = (int)b.probs.size();
+    if (b.map_blocks > 0) {
+        const BlockMap* map = (const BlockMap*)(b.d_work + b.off_map);
+        if (b.precision == FDLB_FP32)
+            launch_batch_step<float>(b.tile, map, (const StepArgs<float>*)(b.d_work + b.off_args) + (size_t)parity * n,
+                                     b.map_blocks, b.stream);
+        else
+            launch_batch_step<double>(b.tile, map,
+                                      (const StepArgs<double>*)(b.d_work + b.off_args) + (size_t)parity * n,
+                                      b.map_blocks, b.stream);
+    }
+    launch_batch_reduce((const ReduceArgs*)(b.d_work + b.off_rargs), n, b.stream);
+}
+
+static void enqueue_batch_chunk(fdlb_batch& b, int k, int parity, bool graph) {
+    if (!graph) {
+        for (int i = 0; i < k; ++i) enqueue_batch_step(b, parity ^ (i & 1));
+        return;
+    }
+    auto key = std::make_tuple(k, parity, b.map_version, b.tile);
+    auto it = b.graphs.find(key);
+    if (it == b.graphs.end()) {
+        // Graphs of an older block map are stale: drop them.
+        for (auto g = b.graphs.begin(); g != b.graphs.end();) {
+            if (std::get<2>(g->first) != b.map_version) {
+                (void)hipGraphExecDestroy(g->second);
+                g = b.graphs.erase(g);
+            } else {
+                ++g;
+            }
+        }
+        hipGraph_t g;
+        FDLB_HIP(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
+        try {
+            for (int i = 0; i < k; ++i) enqueue_batch_step(b, parity ^ (i & 1));
+        } catch (...) {
+            hipGraph_t dummy;
+            (void)hipStreamEndCapture(b.stream, &dummy);
+            throw;
+        }
+        FDLB_HIP(hipStreamEndCapture(b.stream, &g));
+        hipGraphExec_t ge;
+        FDLB_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        FDLB_HIP(hipGraphDestroy(g));
+        it = b.graphs.emplace(key, ge).first;
+    }
+    FDLB_HIP(hipGraphLaunch(it->second, b.stream));
+}
+
+static void read_all_ctrl(fdlb_batch& b) {
+    for (size_t i = 0; i < b.probs.size(); ++i)
+        FDLB_HIP(hipMemcpyAsync(b.pinned + 8 * i, ctrl_of(*b.probs[i]), 8 * sizeof(double), hipMemcpyDeviceToHost,
+                                b.stream));
+    FDLB_HIP(hipStreamSynchronize(b.stream));
+}
+
+int batch_solve(fdlb_batch& b, double tol, int64_t max_steps, int32_t check_every, int32_t use_graph,
+                fdlb_report* reps) {
+    if (!b.bound) throw Error(FDLB_ESTATE, "batch is not bound to device memory");
+    if (!(tol >= 0) || max_steps < 0 || check_every < 1) throw Error(FDLB_EINVAL, "bad solve arguments");
+    const int n = (int)b.probs.size();
+    for (auto& p : b.probs)
+        if (!p->seeded) throw Error(FDLB_ESTATE, "every problem of the batch must be initialised");
+    read_all_ctrl(b);
+    // All problems advance together, so they must share the buffer parity.
+    const int parity0 = (int)((int64_t)b.pinned[CTRL_STEP] & 1);
+    std::vector<double> base(n);
+    for (int i = 0; i < n; ++i) {
+        base[i] = b.pinned[8 * i + CTRL_STEP];
+        if ((int)((int64_t)base[i] & 1) != parity0)
+            throw Error(FDLB_ESTATE, "problems of a batch must have taken step counts of equal parity");
+        double* h = b.pinned + 8 * i;
+        h[CTRL_FIRST_BELOW] = -1.0;
+        h[CTRL_DIVERGED] = -1.0;
+        h[CTRL_TOL] = tol;
+        h[CTRL_FREEZE] = 1.0;
+        FDLB_HIP(hipMemcpyAsync(ctrl_of(*b.probs[i]) + CTRL_FIRST_BELOW, h + CTRL_FIRST_BELOW, 5 * sizeof(double),
+                                hipMemcpyHostToDevice, b.stream));
+        b.probs[i]->freeze_on = true;
+    }
+    FDLB_HIP(hipStreamSynchronize(b.stream));
+    upload_args(b);
+    b.active.clear();
+    for (int i = 0; i < n; ++i) b.active.push_back(i);
+    upload_map(b);
+    const bool graph = use_graph && b.stream != nullptr && check_every >= 2;
+    std::vector<int32_t> hlen(n, 0);
+    const auto t0 = std::chrono::steady_clock::now();
+    int64_t launched = 0;
+    int parity = parity0;
+    while (launched < max_steps && !b.active.empty()) {
+        const int64_t k = std::min<int64_t>(check_every, max_steps - launched);
+        enqueue_batch_chunk(b, (int)k, parity, graph && k == check_every);
+        if (k & 1) parity ^= 1;
+        launched += k;
+        read_all_ctrl(b);
+        std::vector<int> still;
+        for (int i : b.active) {
+            const double* c = b.pinned + 8 * i;
+            if (reps && reps[i].history && hlen[i] < reps[i].history_cap) reps[i].history[hlen[i]++] = c[CTRL_LAST_R];
+            if (c[CTRL_FIRST_BELOW] < 0 && c[CTRL_DIVERGED] < 0) still.push_back(i);
+        }
+        if (still.size() != b.active.size()) {
+            b.active = still;
+            upload_map(b);
+        }
+    }
+    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int status = FDLB_OK;
+    for (int i = 0; i < n; ++i) {
+        fdlb_problem& p = *b.probs[i];
+        const double* c = b.pinned + 8 * i;
+        int st = FDLB_ENOTCONVERGED;
+        if (c[CTRL_DIVERGED] >= 0) st = FDLB_EDIVERGED;
+        else if (c[CTRL_FIRST_BELOW] >= 0) st = FDLB_OK;
+        if (st == FDLB_EDIVERGED) status = FDLB_EDIVERGED;
+        else if (st == FDLB_ENOTCONVERGED && status == FDLB_OK) status = FDLB_ENOTCONVERGED;
+        p.parity = (int)((int64_t)c[CTRL_STEP] & 1);
+        if (reps) {
+            fdlb_report& r = reps[i];
+            r.steps = (int64_t)(c[CTRL_STEP] - base[i]);
+            r.first_below = st == FDLB_OK ? (int64_t)(c[CTRL_FIRST_BELOW] - base[i]) : -1;
+            r.residual = c[CTRL_LAST_R];
+            r.wall_s = wall;
+            const double upd = (double)r.steps * (double)p.plane * p.q;
+            r.updates_per_s = wall > 0 ? upd / wall : 0;
+            r.bytes_per_s = wall > 0 ? upd * 2.0 * (double)p.elem / wall : 0;
+            r.status = st;
+            r.history_len = hlen[i];
+        }
+    }
+    return status;
+}
+
+double batch_autotune(fdlb_batch& b, int steps) {
+    if (!b.bound) throw Error(FDLB_ESTATE, "batch is not bound to device memory");
+    if (steps < 1) throw Error(FDLB_EINVAL, "steps must be >= 1");
+    hipEvent_t e0, e1;
+    FDLB_HIP(hipEventCreate(&e0));
+    FDLB_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_tile = b.tile;
+    try {
+        for (int t = 0; t < (int)tile_shapes(b.precision).size(); ++t) {
+            if (!tile_fits_all(b, t)) continue;
+            batch_set_tile(b, t);
+            for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+            upload_args(b);
+            b.active.clear();
+            for (size_t i = 0; i < b.probs.size(); ++i) b.active.push_back((int)i);
+            upload_map(b);
+            enqueue_batch_chunk(b, 2, 0, false);
+            FDLB_HIP(hipEventRecord(e0, b.stream));
+            enqueue_batch_chunk(b, steps, 0, false);
+            FDLB_HIP(hipEventRecord(e1, b.stream));
+            FDLB_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            FDLB_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / steps < best) {
+                best = ms / steps;
+                best_tile = t;
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    batch_set_tile(b, best_tile);
+    for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+    return best;
+}
+
+}  // namespace fdlb
+
+// ---- C ABI -------------------------------------------------------------------------------
+namespace fdlb {
+int guard_batch(const std::function<int()>& f);
+}
+
+using namespace fdlb;
+
+extern "C" {
+
+int fdlb_batch_create(const fdlb_problem_desc* descs, int n, fdlb_batch** out) {
+    return guard_batch([&] {
+        if (!out) throw Error(FDLB_EINVAL, "NULL output handle");
+        *out = nullptr;
+        auto b = std::make_unique<fdlb_batch>();
+        batch_create(*b, descs, n);
+        *out = b.release();
+        return FDLB_OK;
+    });
+}
+
+void fdlb_batch_destroy(fdlb_batch* b) { delete b; }
+
+size_t fdlb_batch_state_bytes(const fdlb_batch* b) { return b ? b->state_bytes : 0; }
+size_t fdlb_batch_workspace_bytes(const fdlb_batch* b) { return b ? b->work_bytes : 0; }
+
+static fdlb_batch& bh(fdlb_batch* b) {
+    if (!b) throw Error(FDLB_EINVAL, "NULL batch handle");
+    return *b;
+}
+
+int fdlb_batch_bind(fdlb_batch* b, void* d_state, void* d_workspace, void* stream) {
+    return guard_batch([&] {
+        batch_bind(bh(b), d_state, d_workspace, stream);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_init_equilibrium(fdlb_batch* b, int i, const double* rho, const double* ux, const double* uy,
+                                int renormalize_mass) {
+    return guard_batch([&] {
+        batch_init_equilibrium(bh(b), i, rho, ux, uy, renormalize_mass);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_init_equilibrium_dev(fdlb_batch* b, int i, const float* d_rho, const float* d_ux, const float* d_uy,
+                                    int renormalize_mass) {
+    return guard_batch([&] {
+        batch_init_equilibrium_dev(bh(b), i, d_rho, d_ux, d_uy, renormalize_mass);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_solve(fdlb_batch* b, double tol, int64_t max_steps, int32_t check_every, int32_t use_graph,
+                     fdlb_report* reports) {
+    return guard_batch([&] { return batch_solve(bh(b), tol, max_steps, check_every, use_graph, reports); });
+}
+
+int fdlb_batch_moments(fdlb_batch* b, int i, double* rho, double* ux, double* uy, double* pxy) {
+    return guard_batch([&] {
+        batch_moments(bh(b), i, rho, ux, uy, pxy);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_state_download(fdlb_batch* b, int i, double* f_host) {
+    return guard_batch([&] {
+        batch_state_download(bh(b), i, f_host);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_set_tile(fdlb_batch* b, int tile) {
+    return guard_batch([&] {
+        batch_set_tile(bh(b), tile);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_get_tile(const fdlb_batch* b) { return b ? b->tile : FDLB_EINVAL; }
+
+int fdlb_batch_autotune(fdlb_batch* b, int steps, double* best_ms_per_step) {
+    return guard_batch([&] {
+        const double ms = batch_autotune(bh(b), steps);
+        if (best_ms_per_step) *best_ms_per_step = ms;
+        return FDLB_OK;
+    });
+}
+
+}  // extern "C"

@@ -2,6 +2,7 @@
 // converts exceptions into status codes and a thread-local message.
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 
@@ -52,6 +53,8 @@ static int guard(F&& f) {
         return FDLB_EINVAL;
     }
 }
+
+int guard_batch(const std::function<int()>& f) { return guard(f); }
 
 static fdlb_problem& handle(fdlb_problem* p) {
     if (!p) throw Error(FDLB_EINVAL, "NULL problem handle");

@@ -60,6 +60,7 @@ struct StepArgs {
     const double* phi_in; // [4][L]: sum over arriving half of |xi_n| h at each wall cell of src
     double* phi_out;
     double* partials;     // [nblocks][3]: sum |du|^2, sum |u|^2, max |u|^2
+    const double* ctrl;   // control block (freeze flags)
     const VelEntry<T>* vel;
     int32_t quad_begin[5];
     int32_t nx, ny, L;
@@ -76,18 +77,39 @@ struct TileShape {
     int vx;    // cells per lane along x (vector width)
     int lx;    // lanes along x in a wave (64 / lx lanes along y)
     int k;     // rows per lane
-    int wpb;   // waves per block (stacked along y)
+    int wpb;   // waves per block stacked along y
+    int wa;    // waves per block sharing one tile, splitting the velocities
     int tile_w() const { return vx * lx; }
     int tile_h() const { return (64 / lx) * k * wpb; }
 };
 
+// Batch launch: which problem and tile a block works on.
+struct BlockMap {
+    int32_t inst;   // problem index, -1 for a padding block
+    int32_t local;  // block index within the problem
+    int32_t nb;     // blocks of the problem
+    int32_t pad;
+};
+
+// Batch reduction: one entry per problem.
+struct ReduceArgs {
+    const double* partials;
+    double* ctrl;
+    int32_t nb;     // <= 0: skip
+    int32_t pad;
+};
+
 const std::vector<TileShape>& tile_shapes(int precision);
+int heuristic_tile_for(int precision, int nx, int ny, bool periodic_x, bool periodic_y);
 bool tile_fits(const TileShape& t, int nx, int ny, bool periodic_x, bool periodic_y);
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return immediately.
 template <class T>
 void launch_step(int tile, const StepArgs<T>& a, int nblocks, hipStream_t stream);
 void launch_reduce(const double* partials, int nblocks, double* ctrl, int64_t inc, hipStream_t stream);
+template <class T>
+void launch_batch_step(int tile, const BlockMap* map, const StepArgs<T>* args, int nblocks, hipStream_t stream);
+void launch_batch_reduce(const ReduceArgs* ra, int n, hipStream_t stream);
 template <class T>
 void launch_seed(T* h, int q, int64_t plane, const VelEntry<double>* vel, const double* rho,
                  const double* ux, const double* uy, const float* frho, const float* fux,
@@ -120,6 +142,7 @@ enum CtrlSlot {
     CTRL_DIVERGED = 3,    // step count of the first non-finite / runaway step, -1 if none
     CTRL_MAXU = 4,        // max |u| of the last step
     CTRL_TOL = 5,         // tolerance the reduce kernel compares against
+    CTRL_FREEZE = 6,      // 1: stop updating once converged or diverged (steady solves)
     CTRL_RING = 8,        // ring of residuals, CTRL_RING_LEN entries
 };
 constexpr int CTRL_RING_LEN = 4096;
@@ -154,6 +177,7 @@ struct fdlb_problem {
     bool seeded = false;
     int parity = 0;                        // population buffer holding the current state
     double* pinned = nullptr;              // small pinned host buffer for control reads
+    bool freeze_on = false;                // the device control block has the freeze flag set
     // captured graphs keyed by (steps per replay, tile, starting parity)
     std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
     ~fdlb_problem();

@@ -26,6 +26,7 @@
 // edge lane), or the wall emission of Eq. (8).  Blocks are mapped to tiles
 // so that each of the 8 XCDs owns a contiguous band of tile rows (its own
 // L2 then serves the halo rows shared between vertically adjacent tiles).
+#include <algorithm>
 #include <type_traits>
 
 #include "fdlb_internal.h"
@@ -88,18 +89,24 @@ __device__ __forceinline__ double wave_max(double v) {
 // ---------------------------------------------------------------------------
 // The fused time step.
 // ---------------------------------------------------------------------------
-template <class T, int VX, int K, int LX, int WPB>
-__global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
+// A block is WPB x WA waves: WPB waves stacked along y, each replicated WA times along the
+// velocity index (wave wa takes every WA-th velocity of each quadrant; the partial moments
+// are summed through LDS in a fixed order).  bid/nb: this block's index among the blocks of
+// its problem; part: where its three residual partials go.
+template <class T, int VX, int K, int LX, int WPB, int WA>
+__device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, const int nb,
+                                          double* __restrict__ part) {
     constexpr int LY = 64 / LX;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const int wy = wave % WPB, wa = wave / WPB;
     const int lx = lane % LX, ly = lane / LX;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile(bid, nb);
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int nx = A.nx, ny = A.ny, L = A.L;
     const int64_t plane = A.plane;
     const int x0 = tx * (LX * VX) + lx * VX;
-    const int y0 = ((ty * WPB + wave) * LY + ly) * K;
+    const int y0 = ((ty * WPB + wy) * LY + ly) * K;
     const bool xv = x0 < nx;
     const T c1 = A.c1;
 
@@ -249,32 +256,38 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
             }
         }
 
-        for (int e = qb; e < qe; ++e) {
-            const VelEntry<T> c = A.vel[e];
-            const T* __restrict__ s = A.src + (int64_t)c.alpha * plane;
-            T* __restrict__ d = A.dst + (int64_t)c.alpha * plane;
-
-            T g[K][VX];
+        // Loads of one velocity plane: this lane's cells and the halo cells it relaxes itself.
+        auto load_plane = [&](const int e, T (&hv)[K][VX], T (&hx)[K], T (&hy)[VX]) {
+            const T* __restrict__ s = A.src + (int64_t)A.vel[e].alpha * plane;
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 if (rv[r]) {
-                    vload<VX>(g[r], s + (int64_t)(y0 + r) * nx + x0);
+                    vload<VX>(hv[r], s + (int64_t)(y0 + r) * nx + x0);
                 } else {
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) g[r][v] = T(0);
+                    for (int v = 0; v < VX; ++v) hv[r][v] = T(0);
                 }
             }
-            T gxh[K];
 #pragma unroll
             for (int r = 0; r < K; ++r)
-                gxh[r] = (xmode == MODE_LOAD && rv[r]) ? s[(int64_t)(y0 + r) * nx + xh] : T(0);
-            T gyh[VX];
+                hx[r] = (xmode == MODE_LOAD && rv[r]) ? s[(int64_t)(y0 + r) * nx + xh] : T(0);
             if (ymode == MODE_LOAD) {
-                vload<VX>(gyh, s + (int64_t)yh * nx + x0);
+                vload<VX>(hy, s + (int64_t)yh * nx + x0);
             } else {
 #pragma unroll
-                for (int v = 0; v < VX; ++v) gyh[v] = T(0);
+                for (int v = 0; v < VX; ++v) hy[v] = T(0);
             }
+        };
+
+        // Software pipeline over velocities: the next plane's loads are in flight while
+        // the current one is relaxed, transported and stored.
+        T g[K][VX], gxh[K], gyh[VX];
+        if (qb + wa < qe) load_plane(qb + wa, g, gxh, gyh);
+        for (int e = qb + wa; e < qe; e += WA) {
+            const VelEntry<T> c = A.vel[e];
+            T* __restrict__ d = A.dst + (int64_t)c.alpha * plane;
+            T pg[K][VX], pgx[K], pgy[VX];
+            load_plane(e + WA < qe ? e + WA : e, pg, pgx, pgy);
 
             // Relaxation (explicit Euler of Eq. 1 towards Eq. 5, deviation form).
 #pragma unroll
@@ -364,6 +377,14 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
                     }
                 }
             }
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+#pragma unroll
+                for (int v = 0; v < VX; ++v) g[r][v] = pg[r][v];
+                gxh[r] = pgx[r];
+            }
+#pragma unroll
+            for (int v = 0; v < VX; ++v) gyh[v] = pgy[v];
         }
     };
 
@@ -376,48 +397,93 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
     quadrant(std::integral_constant<int, -1>{}, std::integral_constant<int, -1>{}, A.quad_begin[3],
              A.quad_begin[4]);
 
-    // Outputs for the next step.
+    // Sum the partial moments of the WA waves that share this tile (fixed order: wave 0 adds
+    // the others' contributions in increasing wa).
+    if constexpr (WA > 1) {
+        constexpr int NM = 3 * K * VX + K + VX;  // doubles per lane
+        __shared__ double xred[WA - 1][WPB][NM][64];
+        if (wa > 0) {
+            double* o = &xred[wa - 1][wy][0][lane];
+            int i = 0;
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-        if (rv[r]) {
-            const int64_t o = (int64_t)(y0 + r) * nx + x0;
-            vstore<VX>(A.mom_out + o, ar[r]);
-            vstore<VX>(A.mom_out + plane + o, ax[r]);
-            vstore<VX>(A.mom_out + 2 * plane + o, ay[r]);
+            for (int r = 0; r < K; ++r)
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    o[64 * i++] = ar[r][v];
+                    o[64 * i++] = ax[r][v];
+                    o[64 * i++] = ay[r][v];
+                }
+#pragma unroll
+            for (int r = 0; r < K; ++r) o[64 * i++] = phx[r];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[64 * i++] = phy[v];
+        }
+        __syncthreads();
+        if (wa == 0) {
+#pragma unroll 1
+            for (int w = 0; w < WA - 1; ++w) {
+                const double* o = &xred[w][wy][0][lane];
+                int i = 0;
+#pragma unroll
+                for (int r = 0; r < K; ++r)
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        ar[r][v] += o[64 * i++];
+                        ax[r][v] += o[64 * i++];
+                        ay[r][v] += o[64 * i++];
+                    }
+#pragma unroll
+                for (int r = 0; r < K; ++r) phx[r] += o[64 * i++];
+#pragma unroll
+                for (int v = 0; v < VX; ++v) phy[v] += o[64 * i++];
+            }
         }
     }
-    if (on_left || on_right) {
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-            if (rv[r]) A.phi_out[xw * L + y0 + r] = phx[r];
-    }
-    if (on_bot || on_top) {
-#pragma unroll
-        for (int v = 0; v < VX; ++v) A.phi_out[yw * L + x0 + v] = phy[v];
-    }
 
-    // Residual partials: sum |u_new - u_old|^2, sum |u_new|^2, max |u_new|^2, from the
-    // double moments (the old ones re-read rather than kept in registers).
+    // Outputs for the next step (one wave per tile row writes them).
     double num = 0.0, den = 0.0, umax = 0.0;
+    if (wa == 0) {
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-        if (rv[r]) {
-            const int64_t o = (int64_t)(y0 + r) * nx + x0;
-            double m0[VX], m1[VX], m2[VX];
-            vload<VX>(m0, A.mom_in + o);
-            vload<VX>(m1, A.mom_in + plane + o);
-            vload<VX>(m2, A.mom_in + 2 * plane + o);
+        for (int r = 0; r < K; ++r) {
+            if (rv[r]) {
+                const int64_t o = (int64_t)(y0 + r) * nx + x0;
+                vstore<VX>(A.mom_out + o, ar[r]);
+                vstore<VX>(A.mom_out + plane + o, ax[r]);
+                vstore<VX>(A.mom_out + 2 * plane + o, ay[r]);
+            }
+        }
+        if (on_left || on_right) {
 #pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                const double r0 = 1.0 + m0[v];
-                const double ux0 = m1[v] / r0, uy0 = m2[v] / r0;
-                const double r1 = 1.0 + ar[r][v];
-                const double ux1 = ax[r][v] / r1, uy1 = ay[r][v] / r1;
-                const double dx = ux1 - ux0, dy = uy1 - uy0;
-                const double u2 = ux1 * ux1 + uy1 * uy1;
-                num += dx * dx + dy * dy;
-                den += u2;
-                umax = fmax(umax, u2);
+            for (int r = 0; r < K; ++r)
+                if (rv[r]) A.phi_out[xw * L + y0 + r] = phx[r];
+        }
+        if (on_bot || on_top) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) A.phi_out[yw * L + x0 + v] = phy[v];
+        }
+
+        // Residual partials: sum |u_new - u_old|^2, sum |u_new|^2, max |u_new|^2, from the
+        // double moments (the old ones re-read rather than kept in registers).
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (rv[r]) {
+                const int64_t o = (int64_t)(y0 + r) * nx + x0;
+                double m0[VX], m1[VX], m2[VX];
+                vload<VX>(m0, A.mom_in + o);
+                vload<VX>(m1, A.mom_in + plane + o);
+                vload<VX>(m2, A.mom_in + 2 * plane + o);
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    const double r0 = 1.0 + m0[v];
+                    const double ux0 = m1[v] / r0, uy0 = m2[v] / r0;
+                    const double r1 = 1.0 + ar[r][v];
+                    const double ux1 = ax[r][v] / r1, uy1 = ay[r][v] / r1;
+                    const double dx = ux1 - ux0, dy = uy1 - uy0;
+                    const double u2 = ux1 * ux1 + uy1 * uy1;
+                    num += dx * dx + dy * dy;
+                    den += u2;
+                    umax = fmax(umax, u2);
+                }
             }
         }
     }
@@ -425,10 +491,10 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
     den = wave_sum(den);
     umax = wave_max(umax);
     __shared__ double red[WPB][3];
-    if (lane == 0) {
-        red[wave][0] = num;
-        red[wave][1] = den;
-        red[wave][2] = umax;
+    if (lane == 0 && wa == 0) {
+        red[wy][0] = num;
+        red[wy][1] = den;
+        red[wy][2] = umax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -439,17 +505,41 @@ __global__ void __launch_bounds__(64 * WPB) step_kernel(const StepArgs<T> A) {
             b += red[w][1];
             m = fmax(m, red[w][2]);
         }
-        A.partials[3 * blockIdx.x + 0] = a;
-        A.partials[3 * blockIdx.x + 1] = b;
-        A.partials[3 * blockIdx.x + 2] = m;
+        part[0] = a;
+        part[1] = b;
+        part[2] = m;
     }
+}
+
+// A problem whose solve has converged or diverged stops being updated (its state stays at
+// the step that met the criterion), when the control block asks for it.
+__device__ __forceinline__ bool frozen(const double* __restrict__ ctrl) {
+    return ctrl[CTRL_FREEZE] != 0.0 && (ctrl[CTRL_FIRST_BELOW] >= 0.0 || ctrl[CTRL_DIVERGED] >= 0.0);
+}
+
+template <class T, int VX, int K, int LX, int WPB, int WA>
+__global__ void __launch_bounds__(64 * WPB * WA) step_kernel(const StepArgs<T> A) {
+    if (frozen(A.ctrl)) return;
+    step_body<T, VX, K, LX, WPB, WA>(A, blockIdx.x, gridDim.x, A.partials + 3 * blockIdx.x);
+}
+
+// Many problems in one launch: block g works on tile map[g].local of problem map[g].inst.
+// Each problem's blocks start at a multiple of 8, so the XCD-aware tile order holds per problem.
+template <class T, int VX, int K, int LX, int WPB, int WA>
+__global__ void __launch_bounds__(64 * WPB * WA) batch_step_kernel(const BlockMap* __restrict__ map,
+                                                                   const StepArgs<T>* __restrict__ args) {
+    const BlockMap m = map[blockIdx.x];
+    if (m.inst < 0) return;  // padding block
+    const StepArgs<T> A = args[m.inst];
+    if (frozen(A.ctrl)) return;
+    step_body<T, VX, K, LX, WPB, WA>(A, m.local, m.nb, A.partials + 3 * m.local);
 }
 
 // ---------------------------------------------------------------------------
 // Residual: second stage of the reduction, and the step bookkeeping.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ partials, int nblocks,
-                                                     double* __restrict__ ctrl, int64_t inc) {
+__device__ __forceinline__ void reduce_body(const double* __restrict__ partials, int nblocks,
+                                            double* __restrict__ ctrl, int64_t inc) {
     __shared__ double s[3][256];
     double a = 0, b = 0, m = 0;
     for (int i = threadIdx.x; i < nblocks; i += 256) {
@@ -483,6 +573,19 @@ __global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ 
         const bool bad = !(R <= 1e300) || !(umax2 <= 0.25);
         if (bad && ctrl[CTRL_DIVERGED] < 0.0) ctrl[CTRL_DIVERGED] = step;
     }
+}
+
+__global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ partials, int nblocks,
+                                                     double* __restrict__ ctrl, int64_t inc) {
+    if (frozen(ctrl)) return;
+    reduce_body(partials, nblocks, ctrl, inc);
+}
+
+// One block per problem of a batch.
+__global__ void __launch_bounds__(256) batch_reduce_kernel(const ReduceArgs* __restrict__ ra) {
+    const ReduceArgs r = ra[blockIdx.x];
+    if (r.nb <= 0 || frozen(r.ctrl)) return;
+    reduce_body(r.partials, r.nb, r.ctrl, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,11 +776,25 @@ __global__ void __launch_bounds__(256) from_raw_kernel(const double* __restrict_
     h[(int64_t)a * plane + i % plane] = (T)(f[i] - w_nat[a]);
 }
 
-// Streaming copy (16-byte vectors, grid-stride) for the bandwidth ceiling.
-__global__ void __launch_bounds__(256) copy_kernel(float4* __restrict__ dst, const float4* __restrict__ src,
+// Streaming copy for the bandwidth ceiling: each thread keeps 8 x 16-byte loads in flight.
+constexpr int COPY_UNROLL = 8;
+typedef float copy_vec_t __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) copy_kernel(copy_vec_t* __restrict__ dst, const copy_vec_t* __restrict__ src,
                                                    int64_t n16) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    const int64_t chunk = (int64_t)blockDim.x * COPY_UNROLL;
+    for (int64_t base = (int64_t)blockIdx.x * chunk; base < n16; base += (int64_t)gridDim.x * chunk) {
+        copy_vec_t v[COPY_UNROLL];
+#pragma unroll
+        for (int u = 0; u < COPY_UNROLL; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i < n16) v[u] = __builtin_nontemporal_load(src + i);
+        }
+#pragma unroll
+        for (int u = 0; u < COPY_UNROLL; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i < n16) __builtin_nontemporal_store(v[u], dst + i);
+        }
+    }
 }
 __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict__ src, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -687,31 +804,42 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
 // ---------------------------------------------------------------------------
 // Tile shapes and launchers.
 // ---------------------------------------------------------------------------
-#define FDLB_TILES_FP32(X)   \
-    X(0, float, 4, 2, 64, 4) \
-    X(1, float, 4, 2, 16, 4) \
-    X(2, float, 4, 2, 32, 4) \
-    X(3, float, 4, 1, 64, 4) \
-    X(4, float, 4, 4, 16, 2) \
-    X(5, float, 2, 4, 64, 4) \
-    X(6, float, 1, 4, 64, 4) \
-    X(7, float, 1, 4, 1, 1)  \
-    X(8, float, 1, 2, 16, 1) \
-    X(9, float, 4, 1, 16, 4) \
-    X(10, float, 1, 1, 16, 1)
+// Compiled tile shapes: (id, type, VX, K, LX, WPB, WA).
+#define FDLB_TILES_FP32(X)          \
+    X(0, float, 4, 2, 64, 4, 1)     \
+    X(1, float, 4, 2, 16, 4, 1)     \
+    X(2, float, 4, 2, 32, 4, 1)     \
+    X(3, float, 4, 1, 64, 4, 1)     \
+    X(4, float, 4, 4, 16, 2, 1)     \
+    X(5, float, 2, 4, 64, 4, 1)     \
+    X(6, float, 1, 4, 64, 4, 1)     \
+    X(7, float, 1, 4, 1, 1, 1)      \
+    X(8, float, 1, 2, 16, 1, 1)     \
+    X(9, float, 4, 1, 16, 4, 1)     \
+    X(10, float, 1, 1, 16, 1, 1)    \
+    X(11, float, 4, 1, 16, 1, 4)    \
+    X(12, float, 1, 1, 64, 1, 8)    \
+    X(13, float, 4, 1, 64, 1, 4)    \
+    X(14, float, 1, 4, 1, 1, 4)     \
+    X(15, float, 2, 1, 32, 1, 8)    \
+    X(16, float, 4, 1, 16, 2, 2)
 
-#define FDLB_TILES_FP64(X)    \
-    X(0, double, 2, 2, 64, 4) \
-    X(1, double, 2, 2, 16, 4) \
-    X(2, double, 2, 2, 32, 4) \
-    X(3, double, 1, 2, 64, 4) \
-    X(4, double, 1, 4, 1, 1)  \
-    X(5, double, 1, 2, 16, 1) \
-    X(6, double, 2, 1, 64, 4) \
-    X(7, double, 1, 1, 16, 1)
+#define FDLB_TILES_FP64(X)          \
+    X(0, double, 2, 2, 64, 4, 1)    \
+    X(1, double, 2, 2, 16, 4, 1)    \
+    X(2, double, 2, 2, 32, 4, 1)    \
+    X(3, double, 1, 2, 64, 4, 1)    \
+    X(4, double, 1, 4, 1, 1, 1)     \
+    X(5, double, 1, 2, 16, 1, 1)    \
+    X(6, double, 2, 1, 64, 4, 1)    \
+    X(7, double, 1, 1, 16, 1, 1)    \
+    X(8, double, 2, 1, 16, 1, 4)    \
+    X(9, double, 1, 1, 64, 1, 8)    \
+    X(10, double, 1, 4, 1, 1, 4)    \
+    X(11, double, 2, 1, 32, 1, 8)
 
 const std::vector<TileShape>& tile_shapes(int precision) {
-#define FDLB_SHAPE(id, T, VX, K, LX, WPB) TileShape{VX, LX, K, WPB},
+#define FDLB_SHAPE(id, T, VX, K, LX, WPB, WA) TileShape{VX, LX, K, WPB, WA},
     static const std::vector<TileShape> s32 = {FDLB_TILES_FP32(FDLB_SHAPE)};
     static const std::vector<TileShape> s64 = {FDLB_TILES_FP64(FDLB_SHAPE)};
 #undef FDLB_SHAPE
@@ -721,8 +849,11 @@ const std::vector<TileShape>& tile_shapes(int precision) {
 template <>
 void launch_step<float>(int tile, const StepArgs<float>& a, int nblocks, hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB) \
-    case id: hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB>), dim3(nblocks), dim3(64 * WPB), 0, stream, a); break;
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA)                                                              \
+    case id:                                                                                             \
+        hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA>), dim3(nblocks), dim3(64 * WPB * WA), 0, \
+                           stream, a);                                                                   \
+        break;
         FDLB_TILES_FP32(FDLB_CASE)
 #undef FDLB_CASE
         default: throw Error(FDLB_EINVAL, "unknown tile shape");
@@ -733,12 +864,52 @@ void launch_step<float>(int tile, const StepArgs<float>& a, int nblocks, hipStre
 template <>
 void launch_step<double>(int tile, const StepArgs<double>& a, int nblocks, hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB) \
-    case id: hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB>), dim3(nblocks), dim3(64 * WPB), 0, stream, a); break;
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA)                                                              \
+    case id:                                                                                             \
+        hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA>), dim3(nblocks), dim3(64 * WPB * WA), 0, \
+                           stream, a);                                                                   \
+        break;
         FDLB_TILES_FP64(FDLB_CASE)
 #undef FDLB_CASE
         default: throw Error(FDLB_EINVAL, "unknown tile shape");
     }
+    FDLB_HIP(hipGetLastError());
+}
+
+template <>
+void launch_batch_step<float>(int tile, const BlockMap* map, const StepArgs<float>* args, int nblocks,
+                              hipStream_t stream) {
+    switch (tile) {
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA)                                                                    \
+    case id:                                                                                                   \
+        hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA>), dim3(nblocks), dim3(64 * WPB * WA), 0, \
+                           stream, map, args);                                                                 \
+        break;
+        FDLB_TILES_FP32(FDLB_CASE)
+#undef FDLB_CASE
+        default: throw Error(FDLB_EINVAL, "unknown tile shape");
+    }
+    FDLB_HIP(hipGetLastError());
+}
+
+template <>
+void launch_batch_step<double>(int tile, const BlockMap* map, const StepArgs<double>* args, int nblocks,
+                               hipStream_t stream) {
+    switch (tile) {
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA)                                                                    \
+    case id:                                                                                                   \
+        hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA>), dim3(nblocks), dim3(64 * WPB * WA), 0, \
+                           stream, map, args);                                                                 \
+        break;
+        FDLB_TILES_FP64(FDLB_CASE)
+#undef FDLB_CASE
+        default: throw Error(FDLB_EINVAL, "unknown tile shape");
+    }
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_batch_reduce(const ReduceArgs* ra, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(n), dim3(256), 0, stream, ra);
     FDLB_HIP(hipGetLastError());
 }
 
@@ -807,8 +978,9 @@ void launch_from_raw(const double* f, const double* w_nat, int a0, int a1, int64
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
     const int64_t n16 = (int64_t)(bytes / 16);
     if (n16 > 0) {
-        hipLaunchKernelGGL(copy_kernel, dim3(256 * 16), dim3(256), 0, stream, (float4*)dst, (const float4*)src,
-                           n16);
+        const int64_t blocks = std::min<int64_t>(256 * 8, (n16 + 256 * COPY_UNROLL - 1) / (256 * COPY_UNROLL));
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, (copy_vec_t*)dst,
+                           (const copy_vec_t*)src, n16);
         FDLB_HIP(hipGetLastError());
     }
     const int64_t tail = (int64_t)bytes - n16 * 16;

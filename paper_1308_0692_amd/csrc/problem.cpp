@@ -48,33 +48,45 @@ bool tile_fits(const TileShape& t, int nx, int ny, bool periodic_x, bool periodi
     return true;
 }
 
-static int heuristic_tile(const fdlb_problem& p) {
-    const auto& shapes = tile_shapes(p.d.precision);
+// Built-in choice of tile shape (the autotuner measures instead).  Among the shapes that fit:
+// a grid with many cells (at least ~8 waves per CU without splitting the velocities) takes the
+// widest vectors and the least idle lanes; a small grid takes the shape with the most waves,
+// splitting the velocities over several waves per tile.
+int heuristic_tile_for(int precision, int nx, int ny, bool px, bool py) {
+    const auto& shapes = tile_shapes(precision);
+    const double cells = (double)nx * ny;
+    const bool small = cells / (64.0 * 4.0) < 2048.0;  // < 8 waves/CU at 4 cells per lane
     int best = -1;
     double best_score = 1e300;
-    int best_vx = 0;
     for (size_t i = 0; i < shapes.size(); ++i) {
         const TileShape& t = shapes[i];
-        if (!tile_fits(t, p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y)) continue;
-        if (t.vx > best_vx) {  // widest vectors first
-            best_vx = t.vx;
-            best_score = 1e300;
-        } else if (t.vx < best_vx) {
-            continue;
+        if (!tile_fits(t, nx, ny, px, py)) continue;
+        if (!small && t.wa != 1) continue;
+        const int64_t tx = (nx + t.tile_w() - 1) / t.tile_w();
+        const int64_t ty = (ny + t.tile_h() - 1) / t.tile_h();
+        const double cover = (double)(tx * t.tile_w() * ty * t.tile_h()) / cells;
+        double score;
+        if (small) {
+            const double waves = (double)(tx * ty) * t.wpb * t.wa;
+            score = cover / std::min(waves, 8192.0);
+        } else {
+            score = cover * (4.0 / t.vx) * (t.k > 1 ? 1.0 : 1.02);
         }
-        const int64_t tx = (p.d.nx + t.tile_w() - 1) / t.tile_w();
-        const int64_t ty = (p.d.ny + t.tile_h() - 1) / t.tile_h();
-        const double cover = (double)(tx * t.tile_w() * ty * t.tile_h()) / (double)p.plane;
-        const double blocks = (double)(tx * ty);
-        // idle lanes cost directly; fewer than ~2 blocks per CU leaves the chip half idle
-        const double score = cover * (blocks < 512 ? 1.0 + (512 - blocks) / 1024.0 : 1.0);
         if (score < best_score - 1e-12) {
             best_score = score;
             best = (int)i;
         }
     }
-    if (best < 0) throw Error(FDLB_EINVAL, "no compiled tile shape fits this grid");
+    if (best < 0) {  // small-grid shapes may not fit: any shape will do
+        for (size_t i = 0; i < shapes.size(); ++i)
+            if (tile_fits(shapes[i], nx, ny, px, py)) return (int)i;
+        throw Error(FDLB_EINVAL, "no compiled tile shape fits this grid");
+    }
     return best;
+}
+
+static int heuristic_tile(const fdlb_problem& p) {
+    return heuristic_tile_for(p.d.precision, p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y);
 }
 
 void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
@@ -267,6 +279,8 @@ static void reset_ctrl(fdlb_problem& p, double tol) {
     h[CTRL_FIRST_BELOW] = -1.0;
     h[CTRL_DIVERGED] = -1.0;
     h[CTRL_TOL] = tol;
+    h[CTRL_FREEZE] = 0.0;
+    p.freeze_on = false;
     FDLB_HIP(hipMemcpyAsync(ctrl(p), h, 8 * sizeof(double), hipMemcpyHostToDevice, p.stream));
     FDLB_HIP(hipStreamSynchronize(p.stream));
 }
@@ -433,6 +447,7 @@ static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile) {
     a.phi_in = phi_buf(p, parity);
     a.phi_out = phi_buf(p, parity ^ 1);
     a.partials = (double*)(p.d_work + p.off_part);
+    a.ctrl = ctrl(p);
     a.vel = (const VelEntry<T>*)(p.d_work + p.off_vel);
     for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
     a.nx = p.d.nx;
@@ -461,18 +476,34 @@ static void enqueue_step(fdlb_problem& p, int parity, int tile) {
     launch_reduce((const double*)(p.d_work + p.off_part), nb, ctrl(p), 1, p.stream);
 }
 
-void step(fdlb_problem& p, int64_t n) {
-    require_seeded(p);
-    if (n < 0) throw Error(FDLB_EINVAL, "nsteps must be >= 0");
+static void enqueue_steps(fdlb_problem& p, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
         enqueue_step(p, p.parity, p.tile);
         p.parity ^= 1;
     }
 }
 
+// Plain stepping never freezes: clear the flag a previous steady solve left set.
+static void unfreeze(fdlb_problem& p) {
+    if (!p.freeze_on) return;
+    p.pinned[CTRL_FREEZE] = 0.0;
+    FDLB_HIP(hipMemcpyAsync(ctrl(p) + CTRL_FREEZE, p.pinned + CTRL_FREEZE, sizeof(double), hipMemcpyHostToDevice,
+                            p.stream));
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+    p.freeze_on = false;
+}
+
+void step(fdlb_problem& p, int64_t n) {
+    require_seeded(p);
+    if (n < 0) throw Error(FDLB_EINVAL, "nsteps must be >= 0");
+    unfreeze(p);
+    enqueue_steps(p, n);
+}
+
 void step_timed(fdlb_problem& p, int64_t n, double* ms_step, double* ms_reduce) {
     require_seeded(p);
     if (n < 1) throw Error(FDLB_EINVAL, "nsteps must be >= 1");
+    unfreeze(p);
     std::vector<hipEvent_t> ev(2 * n + 1, nullptr);
     double a = 0, b = 0;
     try {
@@ -552,45 +583,46 @@ int solve_steady(fdlb_problem& p, double tol, int64_t max_steps, int32_t check_e
     require_seeded(p);
     if (!(tol >= 0) || max_steps < 0 || check_every < 1) throw Error(FDLB_EINVAL, "bad solve arguments");
     const bool graph = use_graph && p.stream != nullptr && check_every >= 2;
-    // Keep the step counter; clear the convergence records and set the tolerance.
+    // Keep the step counter; clear the convergence records, set the tolerance, and ask the
+    // kernels to stop updating at the first step below it (the state then stays there).
     read_ctrl(p);
     const double base = p.pinned[CTRL_STEP];
     p.pinned[CTRL_FIRST_BELOW] = -1.0;
     p.pinned[CTRL_DIVERGED] = -1.0;
     p.pinned[CTRL_TOL] = tol;
-    FDLB_HIP(hipMemcpyAsync(ctrl(p) + CTRL_FIRST_BELOW, p.pinned + CTRL_FIRST_BELOW, 4 * sizeof(double),
+    p.pinned[CTRL_FREEZE] = 1.0;
+    FDLB_HIP(hipMemcpyAsync(ctrl(p) + CTRL_FIRST_BELOW, p.pinned + CTRL_FIRST_BELOW, 5 * sizeof(double),
                             hipMemcpyHostToDevice, p.stream));
     FDLB_HIP(hipStreamSynchronize(p.stream));
+    p.freeze_on = true;
     const auto t0 = std::chrono::steady_clock::now();
-    int64_t done = 0;
+    int64_t launched = 0;
     int status = FDLB_ENOTCONVERGED;
     int32_t hlen = 0;
-    double last_r = std::numeric_limits<double>::quiet_NaN();
-    int64_t first = -1;
-    while (done < max_steps) {
-        const int64_t k = std::min<int64_t>(check_every, max_steps - done);
+    while (launched < max_steps) {
+        const int64_t k = std::min<int64_t>(check_every, max_steps - launched);
         if (graph && k == check_every) enqueue_graph(p, (int)k);
-        else step(p, k);
-        done += k;
+        else enqueue_steps(p, k);
+        launched += k;
         read_ctrl(p);
-        last_r = p.pinned[CTRL_LAST_R];
-        if (rep && rep->history && hlen < rep->history_cap) rep->history[hlen++] = last_r;
+        if (rep && rep->history && hlen < rep->history_cap) rep->history[hlen++] = p.pinned[CTRL_LAST_R];
         if (p.pinned[CTRL_DIVERGED] >= 0) {
             status = FDLB_EDIVERGED;
-            first = -1;
             break;
         }
         if (p.pinned[CTRL_FIRST_BELOW] >= 0) {
             status = FDLB_OK;
-            first = (int64_t)(p.pinned[CTRL_FIRST_BELOW] - base);
             break;
         }
     }
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    // The device may have stopped inside the last chunk: its step counter says where.
+    const int64_t done = (int64_t)(p.pinned[CTRL_STEP] - base);
+    p.parity = (int)((int64_t)p.pinned[CTRL_STEP] & 1);
     if (rep) {
         rep->steps = done;
-        rep->first_below = first;
-        rep->residual = last_r;
+        rep->first_below = status == FDLB_OK ? (int64_t)(p.pinned[CTRL_FIRST_BELOW] - base) : -1;
+        rep->residual = p.pinned[CTRL_LAST_R];
         rep->wall_s = wall;
         const double upd = (double)done * (double)p.plane * p.q;
         rep->updates_per_s = wall > 0 ? upd / wall : 0;

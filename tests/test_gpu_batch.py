@@ -1,0 +1,101 @@
+"""Batched solves: many problems in one launch per step.  Each member must evolve exactly
+as it does alone (same tile: bit-identical, including the step at which it stops), match
+the oracle, and be isolated from members that diverge."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.scheme import Problem as OP
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1308_0692_amd as F
+    return F
+
+
+MIXED = [W.cavity(64, kn=0.3, order=2), W.cavity(48, ny=40, kn=1.0, order=3),
+         W.cavity(96, kn=0.1, order=4), W.cavity(32, kn=3.0, order=2),
+         W.cavity(40, ny=72, kn=0.05, order=2), W.cavity(64, kn=10.0, order=3)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_members_equal_solo_runs(F, prec):
+    b = F.Batch(MIXED, precision=prec)
+    for i in range(len(MIXED)):
+        b.init_equilibrium(i)
+    status, reps = b.solve(1e-7, 60000, check_every=50)
+    assert status == 0, [r["status"] for r in reps]
+    for i, case in enumerate(MIXED):
+        p = F.Problem(case, precision=prec)
+        p.set_tile(b.tile)
+        p.init_equilibrium()
+        rep = p.solve(1e-7, 60000, check_every=50)
+        assert rep["steps"] == reps[i]["steps"] == reps[i]["first_below"], i
+        assert np.array_equal(p.download(), b.download(i, p.q)), i
+        assert np.array_equal(p.moments()[1], b.moments(i)[1]), i
+
+
+def test_batch_fp64_matches_oracle_at_fixed_steps(F):
+    cases = MIXED[:4]
+    b = F.Batch(cases, precision="fp64")
+    for i in range(len(cases)):
+        b.init_equilibrium(i)
+    status, reps = b.solve(0.0, 37, check_every=10)   # tol 0: every member takes 37 steps
+    assert status == 1 and all(r["steps"] == 37 for r in reps)
+    for i, case in enumerate(cases):
+        op = OP.from_case(case)
+        fo = op.step(op.equilibrium(), 37)
+        f = b.download(i, op.q)
+        dev = np.abs(fo - op.w[:, None, None]).max()
+        assert np.abs(f - fo).max() <= 1e-12 * dev, i
+
+
+def test_batch_isolates_a_diverging_member(F):
+    good = [W.cavity(48, kn=0.2, order=2), W.cavity(64, kn=1.0, order=2)]
+    bad = W.with_(W.cavity(48, kn=0.2, order=2), cfl=2.0)
+    b = F.Batch([good[0], bad, good[1]], precision="fp32", allow_unstable=True)
+    for i in range(3):
+        b.init_equilibrium(i)
+    status, reps = b.solve(1e-6, 50000, check_every=40)
+    assert status == F._lib.EDIVERGED
+    assert reps[1]["status"] == F._lib.EDIVERGED
+    assert reps[0]["status"] == 0 and reps[2]["status"] == 0
+    for i, j in ((0, 0), (2, 1)):
+        p = F.Problem(good[j], precision="fp32")
+        p.set_tile(b.tile)
+        p.init_equilibrium()
+        rep = p.solve(1e-6, 50000, check_every=40)
+        assert rep["steps"] == reps[i]["steps"]
+        assert np.array_equal(p.download(), b.download(i, p.q))
+
+
+def test_batch_reports_unconverged_members(F):
+    b = F.Batch([W.cavity(32, kn=0.1, order=2), W.cavity(32, kn=5.0, order=2)], precision="fp32")
+    for i in range(2):
+        b.init_equilibrium(i)
+    status, reps = b.solve(1e-12, 30, check_every=10)
+    assert status == 1
+    assert all(r["status"] == 1 and r["steps"] == 30 for r in reps)
+
+
+def test_batch_autotune_and_graph_vs_eager(F):
+    cases = MIXED[:3]
+    a = F.Batch(cases, precision="fp32")
+    ms = a.autotune(steps=3)
+    assert ms > 0
+    b = F.Batch(cases, precision="fp32")
+    b.set_tile(a.tile)
+    for i in range(3):
+        a.init_equilibrium(i)
+        b.init_equilibrium(i)
+    for rep in range(3):
+        a.solve(0.0, 20, check_every=20, use_graph=True)
+        b.solve(0.0, 20, check_every=5, use_graph=False)
+        for i, c in enumerate(cases):
+            assert np.array_equal(a.download(i, c.q), b.download(i, c.q)), (rep, i)

@@ -173,6 +173,7 @@ def test_fp64_couette_converged(F):
     assert rep["status"] == 0
     assert rep["first_below"] == rep["steps"]
     assert abs(rep["first_below"] - n) <= 1
+    assert gp.last_residual()[1] == rep["steps"]
     h = rep["history"]
     # The per-step change carries absolute rounding noise of ~1e-16 |u|, so R agrees to
     # ~1e-16 / R relative: bound the difference by 1e-11 R + 1e-14.
@@ -312,22 +313,33 @@ def test_init_from_device_fields_and_mass(F):
 
 
 def test_solve_report(F):
+    """A steady solve stops the state at the first step below the tolerance (the device
+    freezes it there even inside a chunk) and reports it."""
     case = W.cavity(32, kn=0.1, order=2)
     p = F.Problem(case, precision="fp32")
     p.init_equilibrium()
     rep = p.solve(1e-6, 100000, check_every=64, history_cap=1000)
     assert rep["status"] == 0
-    assert 0 < rep["first_below"] <= rep["steps"] < rep["first_below"] + 64
-    assert rep["steps"] % 64 == 0
-    assert len(rep["history"]) == rep["steps"] // 64
-    assert rep["history"][-2] >= 1e-6   # no step of the previous chunks was below tol
+    assert 0 < rep["first_below"] == rep["steps"]
+    assert len(rep["history"]) == (rep["steps"] + 63) // 64
+    assert rep["history"][-1] < 1e-6
     assert rep["updates_per_s"] > 0 and rep["bytes_per_s"] == pytest.approx(rep["updates_per_s"] * 8)
+    r, n = p.last_residual()
+    assert n == rep["steps"] and r < 1e-6
+    # the same run with a per-step check gives the same step and the same state
+    q = F.Problem(case, precision="fp32")
+    q.init_equilibrium()
+    rep1 = q.solve(1e-6, 100000, check_every=1, use_graph=False)
+    assert rep1["steps"] == rep["steps"]
+    assert np.array_equal(p.download(), q.download())
     # the residual is not monotone (the cavity relaxes through damped acoustic waves), so a
     # further solve is checked against a tolerance far above the current level
     rep2 = p.solve(1e-3, 10, check_every=5)
-    assert rep2["status"] == 0 and rep2["steps"] == 5
+    assert rep2["status"] == 0 and rep2["steps"] == 1
     rep3 = p.solve(1e-30, 10, check_every=5)
-    assert rep3["status"] == 1 and rep3["first_below"] == -1
+    assert rep3["status"] == 1 and rep3["first_below"] == -1 and rep3["steps"] == 10
+    p.step(3)   # plain stepping resumes after a frozen solve
+    assert p.last_residual()[1] == rep["steps"] + 1 + 10 + 3
 
 
 def test_divergence_is_reported(F):
