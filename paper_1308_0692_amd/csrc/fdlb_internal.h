@@ -79,7 +79,9 @@ struct TileShape {
     int k;     // rows per lane
     int wpb;   // waves per block stacked along y
     int wa;    // waves per block sharing one tile, splitting the velocities
-    int tile_w() const { return vx * lx; }
+    int wx;    // waves per block side by side along x
+    int nt;    // non-temporal population stores
+    int tile_w() const { return vx * lx * wx; }
     int tile_h() const { return (64 / lx) * k * wpb; }
 };
 
