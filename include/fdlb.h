@@ -67,6 +67,18 @@ extern "C" {
 #define FDLB_FP64 0 /* populations stored and updated in double */
 #define FDLB_FP32 1 /* deviations f_alpha - w_alpha stored and updated in float;
                        wall densities and the residual in double */
+#define FDLB_MIXED 2 /* FDLB_FP32 kernels until a steady solve nears its tolerance,
+                        then the state is widened in place and FDLB_FP64 kernels
+                        finish; the state buffers are sized for double */
+
+/* FDLB_MIXED leaves float, during fdlb_solve_steady / fdlb_batch_solve with
+ * tol < FDLB_MIXED_SWITCH_R, at the first host check whose residual is below
+ * FDLB_MIXED_SWITCH_R, or once the lowest residual seen has not fallen by 10 %
+ * for FDLB_MIXED_STALL_STEPS steps.  Float deviations carry about 7 digits,
+ * which puts the float residual floor near 1e-8 (rounding makes the float
+ * iteration cycle instead of settling). */
+#define FDLB_MIXED_SWITCH_R 5e-8
+#define FDLB_MIXED_STALL_STEPS 4000
 #define FDLB_WALL_BOTTOM 0
 #define FDLB_WALL_TOP 1
 #define FDLB_WALL_LEFT 2
@@ -100,7 +112,7 @@ typedef struct fdlb_problem_desc {
     double cfl;                     /* Courant number in (0, 1]; 0.9 is customary */
     int32_t qx_kind, qx_n;          /* FDLB_HALF (n per half) or FDLB_FULL (n total) */
     int32_t qy_kind, qy_n;
-    int32_t precision;              /* FDLB_FP64 or FDLB_FP32 */
+    int32_t precision;              /* FDLB_FP64, FDLB_FP32 or FDLB_MIXED */
     int32_t allow_unstable;         /* 1: accept CFL > 1 or dt/Kn > 1 (tests only) */
 } fdlb_problem_desc;
 
@@ -214,6 +226,7 @@ typedef struct fdlb_report {
     int32_t history_cap;    /* capacity of history (set by the caller) */
     int32_t pad_;
     double *history;        /* caller-owned, may be NULL: residual at every check */
+    int64_t steps_fp32;     /* steps of the call taken in float (FDLB_MIXED: before the switch) */
 } fdlb_report;
 
 /*
@@ -263,6 +276,25 @@ int fdlb_tile_describe(int precision, int tile, char *buf, size_t len);
 int fdlb_problem_set_tile(fdlb_problem *p, int tile);
 int fdlb_problem_get_tile(const fdlb_problem *p);
 int fdlb_autotune(fdlb_problem *p, int steps, double *best_ms_per_step);
+
+/* ---- mixed precision (FDLB_MIXED) ------------------------------------------------- */
+
+/*
+ * Precision the kernels of a problem run in now: FDLB_FP32 or FDLB_FP64.  A
+ * FDLB_MIXED problem starts every new state (init, upload) in FDLB_FP32, and
+ * its tile calls above act on the table of this precision (fdlb_autotune
+ * restarts the float phase and tunes it).
+ */
+int fdlb_problem_active_precision(const fdlb_problem *p);
+
+/*
+ * Widen the float state of a FDLB_MIXED problem to double in place (exact)
+ * and recompute its moments and wall fluxes in double; marching then goes on
+ * with the FDLB_FP64 kernels, from the same step count.  A no-op if already
+ * in double; FDLB_EINVAL for other precisions.  Steady solves call it
+ * themselves (see FDLB_MIXED_SWITCH_R).  Synchronous.
+ */
+int fdlb_promote(fdlb_problem *p);
 
 /* ---- batches ---------------------------------------------------------------------- */
 

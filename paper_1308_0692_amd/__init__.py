@@ -41,7 +41,7 @@ class Problem:
     def __init__(self, case=None, *, precision: Optional[str] = None, allow_unstable: bool = False,
                  device="cuda:0", stream=None, bind: bool = True, desc: Optional[_lib.ProblemDesc] = None):
         self.desc = desc if desc is not None else desc_from_case(case, precision, allow_unstable)
-        self.precision = "fp32" if self.desc.precision == _lib.FP32 else "fp64"
+        self.precision = _lib.PRECISION_NAMES[self.desc.precision]
         h = C.c_void_p()
         check(_lib.lib.fdlb_problem_create(C.byref(self.desc), C.byref(h)))
         self._h = h
@@ -146,7 +146,7 @@ class Problem:
             check(code, allow=(_lib.OK, _lib.ENOTCONVERGED))
         return dict(status=code, steps=rep.steps, first_below=rep.first_below, residual=rep.residual,
                     wall_s=rep.wall_s, updates_per_s=rep.updates_per_s, bytes_per_s=rep.bytes_per_s,
-                    history=hist[:rep.history_len].copy())
+                    steps_fp32=rep.steps_fp32, history=hist[:rep.history_len].copy())
 
     # -- outputs ----------------------------------------------------------------------
     def moments(self):
@@ -160,6 +160,16 @@ class Problem:
         out = [np.empty(n) for _ in range(3)]
         check(_lib.lib.fdlb_wall_profile(self._h, int(wall), *[_lib._dp(a) for a in out]))
         return tuple(out)
+
+    # -- precision ----------------------------------------------------------------------
+    @property
+    def active_precision(self) -> str:
+        """'fp32' or 'fp64': the kernels the state is marched with now."""
+        return _lib.PRECISION_NAMES[check(_lib.lib.fdlb_problem_active_precision(self._h), allow=(0, 1))]
+
+    def promote(self):
+        """Mixed precision: widen the float state to double now (fdlb_promote)."""
+        check(_lib.lib.fdlb_promote(self._h))
 
     # -- tiles ------------------------------------------------------------------------
     @property
@@ -210,7 +220,7 @@ class Batch:
         check(_lib.lib.fdlb_batch_create(arr, self.n, C.byref(h)))
         self._h = h
         self.shapes = [(d.nx, d.ny) for d in descs]
-        self.precision = "fp32" if descs[0].precision == _lib.FP32 else "fp64"
+        self.precision = _lib.PRECISION_NAMES[descs[0].precision]
         self.device = device
         self._stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self._state_t, self._state = _alloc(_lib.lib.fdlb_batch_state_bytes(h), device)
@@ -249,7 +259,8 @@ class Batch:
                                          int(use_graph), reps)
         check(code, allow=(_lib.OK, _lib.ENOTCONVERGED, _lib.EDIVERGED))
         out = [dict(status=r.status, steps=r.steps, first_below=r.first_below, residual=r.residual,
-                    wall_s=r.wall_s, updates_per_s=r.updates_per_s, history=h[:r.history_len].copy())
+                    wall_s=r.wall_s, updates_per_s=r.updates_per_s, steps_fp32=r.steps_fp32,
+                    history=h[:r.history_len].copy())
                for r, h in zip(reps, hists)]
         return code, out
 
@@ -264,6 +275,9 @@ class Batch:
         f = np.empty((q, ny, nx))
         check(_lib.lib.fdlb_batch_state_download(self._h, int(i), _lib._dp(f)))
         return f
+
+    def active_precision(self, i: int) -> str:
+        return _lib.PRECISION_NAMES[check(_lib.lib.fdlb_batch_active_precision(self._h, int(i)), allow=(0, 1))]
 
     @property
     def tile(self) -> int:

@@ -16,7 +16,9 @@ LIB_PATH = os.path.join(HERE, "libfdlb.so")
 
 OK, ENOTCONVERGED, EINVAL, EUNSTABLE, EHIP, EDIVERGED, ESTATE, ENOMEM = 0, 1, -1, -2, -3, -4, -5, -6
 HALF, FULL = 0, 1
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
+PRECISION_NAMES = {v: k for k, v in PRECISIONS.items()}
 BOTTOM, TOP, LEFT, RIGHT = 0, 1, 2, 3
 
 
@@ -45,6 +47,7 @@ class Report(C.Structure):
         ("updates_per_s", C.c_double), ("bytes_per_s", C.c_double),
         ("status", C.c_int32), ("history_len", C.c_int32), ("history_cap", C.c_int32),
         ("pad_", C.c_int32), ("history", C.POINTER(C.c_double)),
+        ("steps_fp32", C.c_int64),
     ]
 
 
@@ -85,6 +88,8 @@ def _load():
         "fdlb_problem_set_tile": (C.c_int, [vp, C.c_int]),
         "fdlb_problem_get_tile": (C.c_int, [vp]),
         "fdlb_autotune": (C.c_int, [vp, C.c_int, dp]),
+        "fdlb_problem_active_precision": (C.c_int, [vp]),
+        "fdlb_promote": (C.c_int, [vp]),
         "fdlb_stream_copy": (C.c_int, [vp, vp, C.c_size_t, vp]),
         "fdlb_batch_create": (C.c_int, [C.POINTER(ProblemDesc), C.c_int, C.POINTER(vp)]),
         "fdlb_batch_destroy": (None, [vp]),
@@ -99,6 +104,7 @@ def _load():
         "fdlb_batch_set_tile": (C.c_int, [vp, C.c_int]),
         "fdlb_batch_get_tile": (C.c_int, [vp]),
         "fdlb_batch_autotune": (C.c_int, [vp, C.c_int, dp]),
+        "fdlb_batch_active_precision": (C.c_int, [vp, C.c_int]),
         "fdlb_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -147,7 +153,7 @@ def make_desc(nx, ny, periodic_x, periodic_y, wall_u, kn, qx, qy, cfl=0.9, preci
     d.cfl = float(cfl)
     d.qx_kind, d.qx_n = kinds[qx[0]], int(qx[1])
     d.qy_kind, d.qy_n = kinds[qy[0]], int(qy[1])
-    d.precision = FP32 if precision == "fp32" else FP64
+    d.precision = PRECISIONS[precision]
     d.allow_unstable = int(bool(allow_unstable))
     return d
 

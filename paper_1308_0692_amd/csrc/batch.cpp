@@ -1,6 +1,8 @@
 // Batched steady solves: many independent problems (different Kn, grids and velocity sets,
 // one precision) advanced together, one step-kernel launch and one reduction launch per
-// time step for all of them.
+// time step for all of them.  In FDLB_MIXED each problem leaves float on its own; the batch
+// then launches the float members and the double members as two groups (two step launches,
+// one reduction).
 //
 // Every problem keeps its own state, workspace and control block inside two caller-owned
 // arenas.  A block map assigns each block of the launch to (problem, tile); each problem's
@@ -14,10 +16,12 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <type_traits>
 
 #include "fdlb_internal.h"
 
 namespace fdlb {
+void promote(fdlb_problem& p);
 void build_problem(fdlb_problem& p, const fdlb_problem_desc& d);
 void bind(fdlb_problem& p, void* d_state, void* d_work, void* stream);
 void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, const double* uy, int renorm);
@@ -26,23 +30,32 @@ void moments(fdlb_problem& p, double* rho, double* ux, double* uy, double* pxy);
 void state_download(fdlb_problem& p, double* f);
 }  // namespace fdlb
 
+// The members that run in one precision: their block map and step arguments.
+struct BatchGroup {
+    bool used = false;
+    int tile = -1;            // a shape of tile_shapes(prec)
+    size_t off_map = 0;       // BlockMap[max_map]
+    size_t off_args = 0;      // StepArgs<T>[2][n]: every member, both parities
+    int max_map = 0;
+    int map_blocks = 0;
+};
+
 struct fdlb_batch {
     std::vector<std::unique_ptr<fdlb_problem>> probs;
     int precision = FDLB_FP32;
-    int tile = -1;
+    BatchGroup grp[2];              // [0]: float kernels, [1]: double kernels
     std::vector<size_t> state_off, work_off;
     size_t state_bytes = 0, work_bytes = 0;
-    size_t off_map = 0, off_args = 0, off_rargs = 0;  // batch region inside the workspace arena
-    int max_map = 0;
+    size_t off_rargs = 0;           // batch region inside the workspace arena
     char* d_state = nullptr;
     char* d_work = nullptr;
     hipStream_t stream = nullptr;
     bool bound = false;
     double* pinned = nullptr;       // n x 8 control doubles
-    std::vector<int> active;        // problems in the current block map
-    int map_blocks = 0;
+    std::vector<int> active;        // problems in the current block maps
     int map_version = 0;
-    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (k, parity, map version, tile)
+    // (k, parity, map version, float tile, double tile)
+    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
     ~fdlb_batch() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         if (pinned) (void)hipHostFree(pinned);
@@ -58,8 +71,13 @@ int nblocks_tile(const fdlb_problem& p, const TileShape& t) {
     return ((p.d.nx + t.tile_w() - 1) / t.tile_w()) * ((p.d.ny + t.tile_h() - 1) / t.tile_h());
 }
 
-bool tile_fits_all(const fdlb_batch& b, int tile) {
-    const TileShape& t = tile_shapes(b.precision)[tile];
+int prec_of_group(int g) { return g == 0 ? FDLB_FP32 : FDLB_FP64; }
+int group_of(const fdlb_problem& p) { return p.prec == FDLB_FP32 ? 0 : 1; }
+// The group the public tile calls act on: float unless the batch is all double.
+int primary_group(const fdlb_batch& b) { return b.precision == FDLB_FP64 ? 1 : 0; }
+
+bool tile_fits_all(const fdlb_batch& b, int g, int tile) {
+    const TileShape& t = tile_shapes(prec_of_group(g))[tile];
     for (auto& p : b.probs) {
         if (!tile_fits(t, p->d.nx, p->d.ny, p->d.periodic_x, p->d.periodic_y)) return false;
         if (nblocks_tile(*p, t) > p->max_blocks) return false;
@@ -67,10 +85,15 @@ bool tile_fits_all(const fdlb_batch& b, int tile) {
     return true;
 }
 
+int member_blocks(const fdlb_batch& b, const fdlb_problem& p) {
+    const int g = group_of(p);
+    return nblocks_tile(p, tile_shapes(prec_of_group(g))[b.grp[g].tile]);
+}
+
 double* ctrl_of(fdlb_problem& p) { return (double*)(p.d_work + p.off_ctrl); }
 }  // namespace
 
-void batch_set_tile(fdlb_batch& b, int tile);
+static void group_set_tile(fdlb_batch& b, int g, int tile);
 
 void batch_create(fdlb_batch& b, const fdlb_problem_desc* descs, int n) {
     if (!descs || n < 1) throw Error(FDLB_EINVAL, "a batch needs at least one problem");
@@ -93,46 +116,63 @@ void batch_create(fdlb_batch& b, const fdlb_problem_desc* descs, int n) {
         so += align256(p->state_bytes);
         wo += align256(p->work_bytes);
     }
-    int maxmap = 0;
-    for (const TileShape& t : tile_shapes(b.precision)) {
-        int tot = 0;
-        for (auto& p : b.probs) tot += (nblocks_tile(*p, t) + 7) / 8 * 8;
-        maxmap = std::max(maxmap, tot);
+    b.grp[0].used = b.precision != FDLB_FP64;
+    b.grp[1].used = b.precision != FDLB_FP32;
+    for (int g = 0; g < 2; ++g) {
+        BatchGroup& G = b.grp[g];
+        if (!G.used) continue;
+        int maxmap = 0;
+        for (const TileShape& t : tile_shapes(prec_of_group(g))) {
+            int tot = 0;
+            for (auto& p : b.probs) tot += (nblocks_tile(*p, t) + 7) / 8 * 8;
+            maxmap = std::max(maxmap, tot);
+        }
+        G.max_map = maxmap;
+        G.off_map = wo;
+        wo += align256((size_t)maxmap * sizeof(BlockMap));
+        G.off_args = wo;
+        wo += align256(2 * (size_t)n * (g == 0 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>)));
     }
-    b.max_map = maxmap;
-    b.off_map = wo;
-    wo += align256((size_t)maxmap * sizeof(BlockMap));
-    b.off_args = wo;
-    const size_t argsz = b.precision == FDLB_FP32 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>);
-    wo += align256(2 * (size_t)n * argsz);
     b.off_rargs = wo;
     wo += align256((size_t)n * sizeof(ReduceArgs));
     b.state_bytes = so;
     b.work_bytes = wo;
-    // Default tile: the built-in choice for the largest problem if it fits all, else any that does.
+    // Default tiles: the built-in choice for the largest problem if it fits all, else any that does.
     int big = 0;
     for (int i = 1; i < n; ++i)
         if (b.probs[i]->plane * b.probs[i]->q > b.probs[big]->plane * b.probs[big]->q) big = i;
     const fdlb_problem& pb = *b.probs[big];
-    int t = heuristic_tile_for(b.precision, pb.d.nx, pb.d.ny, pb.d.periodic_x, pb.d.periodic_y);
-    if (!tile_fits_all(b, t)) {
-        t = -1;
-        for (int i = 0; i < (int)tile_shapes(b.precision).size(); ++i)
-            if (tile_fits_all(b, i)) {
-                t = i;
-                break;
-            }
-        if (t < 0) throw Error(FDLB_EINVAL, "no compiled tile shape fits every problem of the batch");
+    for (int g = 0; g < 2; ++g) {
+        if (!b.grp[g].used) continue;
+        const int prec = prec_of_group(g);
+        int t = heuristic_tile_for(prec, pb.d.nx, pb.d.ny, pb.d.periodic_x, pb.d.periodic_y);
+        if (!tile_fits_all(b, g, t)) {
+            t = -1;
+            for (int i = 0; i < (int)tile_shapes(prec).size(); ++i)
+                if (tile_fits_all(b, g, i)) {
+                    t = i;
+                    break;
+                }
+            if (t < 0) throw Error(FDLB_EINVAL, "no compiled tile shape fits every problem of the batch");
+        }
+        group_set_tile(b, g, t);
     }
-    batch_set_tile(b, t);
 }
 
-void batch_set_tile(fdlb_batch& b, int tile) {
-    if (tile < 0 || tile >= (int)tile_shapes(b.precision).size()) throw Error(FDLB_EINVAL, "tile index out of range");
-    if (!tile_fits_all(b, tile)) throw Error(FDLB_EINVAL, "tile shape does not fit every problem of the batch");
-    b.tile = tile;
-    for (auto& p : b.probs) p->tile = tile;
+// Each member keeps the group tiles in its own handle (tile: active precision, tile_alt:
+// the other one), so that its solo calls agree with the batch.
+static void group_set_tile(fdlb_batch& b, int g, int tile) {
+    const int prec = prec_of_group(g);
+    if (tile < 0 || tile >= (int)tile_shapes(prec).size()) throw Error(FDLB_EINVAL, "tile index out of range");
+    if (!tile_fits_all(b, g, tile)) throw Error(FDLB_EINVAL, "tile shape does not fit every problem of the batch");
+    b.grp[g].tile = tile;
+    for (auto& p : b.probs) {
+        if (p->prec == prec) p->tile = tile;
+        else p->tile_alt = tile;
+    }
 }
+
+void batch_set_tile(fdlb_batch& b, int tile) { group_set_tile(b, primary_group(b), tile); }
 
 void batch_bind(fdlb_batch& b, void* d_state, void* d_work, void* stream) {
     if (!d_state || !d_work) throw Error(FDLB_EINVAL, "device buffers must not be NULL");
@@ -165,7 +205,8 @@ void batch_state_download(fdlb_batch& b, int i, double* f) { state_download(inst
 
 template <class T>
 static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile) {
-    const TileShape& t = tile_shapes(p.d.precision)[tile];
+    constexpr bool f32 = std::is_same<T, float>::value;
+    const TileShape& t = tile_shapes(f32 ? FDLB_FP32 : FDLB_FP64)[tile];
     StepArgs<T> a;
     std::memset(&a, 0, sizeof(a));
     char* pop = p.d_state;
@@ -179,7 +220,7 @@ static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile) {
     a.phi_out = (double*)(phi + (size_t)(parity ^ 1) * p.phi_bytes);
     a.partials = (double*)(p.d_work + p.off_part);
     a.ctrl = ctrl_of(p);
-    a.vel = (const VelEntry<T>*)(p.d_work + p.off_vel);
+    a.vel = (const VelEntry<T>*)(p.d_work + (f32 ? p.off_vel : p.off_vel64));
     for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
     a.nx = p.d.nx;
     a.ny = p.d.ny;
@@ -187,68 +228,82 @@ static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile) {
     a.tiles_x = (p.d.nx + t.tile_w() - 1) / t.tile_w();
     a.tiles_y = (p.d.ny + t.tile_h() - 1) / t.tile_h();
     a.plane = p.plane;
-    a.c1 = (T)(1.0 - p.omega);
+    a.omega = (T)p.omega;
+    a.omega_d = p.omega;
     for (int i = 0; i < 4; ++i) a.wall[i] = p.wall[i];
     return a;
 }
 
-// Upload the per-problem step and reduce arguments (both parities).
-static void upload_args(fdlb_batch& b) {
+// Reduce arguments: each member's partials are laid out by its group's tile.
+static void upload_rargs(fdlb_batch& b) {
     const int n = (int)b.probs.size();
     std::vector<ReduceArgs> ra(n);
     for (int i = 0; i < n; ++i) {
         fdlb_problem& p = *b.probs[i];
         ra[i].partials = (const double*)(p.d_work + p.off_part);
         ra[i].ctrl = ctrl_of(p);
-        ra[i].nb = nblocks_tile(p, tile_shapes(b.precision)[b.tile]);
+        ra[i].nb = member_blocks(b, p);
         ra[i].pad = 0;
     }
-    if (b.precision == FDLB_FP32) {
-        std::vector<StepArgs<float>> a(2 * n);
-        for (int par = 0; par < 2; ++par)
-            for (int i = 0; i < n; ++i) a[par * n + i] = batch_step_args<float>(*b.probs[i], par, b.tile);
-        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_args, a.data(), a.size() * sizeof(a[0]), hipMemcpyHostToDevice, b.stream));
-        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_rargs, ra.data(), n * sizeof(ReduceArgs), hipMemcpyHostToDevice, b.stream));
-        FDLB_HIP(hipStreamSynchronize(b.stream));
-    } else {
-        std::vector<StepArgs<double>> a(2 * n);
-        for (int par = 0; par < 2; ++par)
-            for (int i = 0; i < n; ++i) a[par * n + i] = batch_step_args<double>(*b.probs[i], par, b.tile);
-        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_args, a.data(), a.size() * sizeof(a[0]), hipMemcpyHostToDevice, b.stream));
-        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_rargs, ra.data(), n * sizeof(ReduceArgs), hipMemcpyHostToDevice, b.stream));
-        FDLB_HIP(hipStreamSynchronize(b.stream));
-    }
+    FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_rargs, ra.data(), n * sizeof(ReduceArgs), hipMemcpyHostToDevice, b.stream));
+    FDLB_HIP(hipStreamSynchronize(b.stream));
 }
 
-// Block map of the active problems.
+template <class T>
+static void upload_group_args(fdlb_batch& b, int g) {
+    const int n = (int)b.probs.size();
+    std::vector<StepArgs<T>> a(2 * n);
+    for (int par = 0; par < 2; ++par)
+        for (int i = 0; i < n; ++i) a[par * n + i] = batch_step_args<T>(*b.probs[i], par, b.grp[g].tile);
+    FDLB_HIP(hipMemcpyAsync(b.d_work + b.grp[g].off_args, a.data(), a.size() * sizeof(a[0]), hipMemcpyHostToDevice,
+                            b.stream));
+    FDLB_HIP(hipStreamSynchronize(b.stream));  // a is a host temporary
+}
+
+// Upload the per-problem step arguments of every group (all members, both parities) and the
+// reduce arguments.
+static void upload_args(fdlb_batch& b) {
+    if (b.grp[0].used) upload_group_args<float>(b, 0);
+    if (b.grp[1].used) upload_group_args<double>(b, 1);
+    upload_rargs(b);
+}
+
+// Block maps of the active problems, one per group.
 static void upload_map(fdlb_batch& b) {
-    std::vector<BlockMap> m;
-    const TileShape& t = tile_shapes(b.precision)[b.tile];
-    for (int i : b.active) {
-        const int nb = nblocks_tile(*b.probs[i], t);
-        for (int l = 0; l < nb; ++l) m.push_back(BlockMap{i, l, nb, 0});
-        while (m.size() % 8) m.push_back(BlockMap{-1, 0, 0, 0});
+    for (int g = 0; g < 2; ++g) {
+        BatchGroup& G = b.grp[g];
+        if (!G.used) continue;
+        std::vector<BlockMap> m;
+        const TileShape& t = tile_shapes(prec_of_group(g))[G.tile];
+        for (int i : b.active) {
+            if (group_of(*b.probs[i]) != g) continue;
+            const int nb = nblocks_tile(*b.probs[i], t);
+            for (int l = 0; l < nb; ++l) m.push_back(BlockMap{i, l, nb, 0});
+            while (m.size() % 8) m.push_back(BlockMap{-1, 0, 0, 0});
+        }
+        G.map_blocks = (int)m.size();
+        if (G.map_blocks > G.max_map) throw Error(FDLB_EINVAL, "block map overflow");
+        if (!m.empty())
+            FDLB_HIP(hipMemcpyAsync(b.d_work + G.off_map, m.data(), m.size() * sizeof(BlockMap), hipMemcpyHostToDevice,
+                                    b.stream));
+        FDLB_HIP(hipStreamSynchronize(b.stream));
     }
-    b.map_blocks = (int)m.size();
-    if (b.map_blocks > b.max_map) throw Error(FDLB_EINVAL, "block map overflow");
-    if (!m.empty())
-        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_map, m.data(), m.size() * sizeof(BlockMap), hipMemcpyHostToDevice,
-                                b.stream));
-    FDLB_HIP(hipStreamSynchronize(b.stream));
     ++b.map_version;
 }
 
 static void enqueue_batch_step(fdlb_batch& b, int parity) {
     const int n = (int)b.probs.size();
-    if (b.map_blocks > 0) {
-        const BlockMap* map = (const BlockMap*)(b.d_work + b.off_map);
-        if (b.precision == FDLB_FP32)
-            launch_batch_step<float>(b.tile, map, (const StepArgs<float>*)(b.d_work + b.off_args) + (size_t)parity * n,
-                                     b.map_blocks, b.stream);
+    for (int g = 0; g < 2; ++g) {
+        const BatchGroup& G = b.grp[g];
+        if (!G.used || G.map_blocks == 0) continue;
+        const BlockMap* map = (const BlockMap*)(b.d_work + G.off_map);
+        if (g == 0)
+            launch_batch_step<float>(G.tile, map, (const StepArgs<float>*)(b.d_work + G.off_args) + (size_t)parity * n,
+                                     G.map_blocks, b.stream);
         else
-            launch_batch_step<double>(b.tile, map,
-                                      (const StepArgs<double>*)(b.d_work + b.off_args) + (size_t)parity * n,
-                                      b.map_blocks, b.stream);
+            launch_batch_step<double>(G.tile, map,
+                                      (const StepArgs<double>*)(b.d_work + G.off_args) + (size_t)parity * n,
+                                      G.map_blocks, b.stream);
     }
     launch_batch_reduce((const ReduceArgs*)(b.d_work + b.off_rargs), n, b.stream);
 }
@@ -258,7 +313,7 @@ static void enqueue_batch_chunk(fdlb_batch& b, int k, int parity, bool graph) {
         for (int i = 0; i < k; ++i) enqueue_batch_step(b, parity ^ (i & 1));
         return;
     }
-    auto key = std::make_tuple(k, parity, b.map_version, b.tile);
+    auto key = std::make_tuple(k, parity, b.map_version, b.grp[0].tile, b.grp[1].tile);
     auto it = b.graphs.find(key);
     if (it == b.graphs.end()) {
         // Graphs of an older block map are stale: drop them.
@@ -326,6 +381,13 @@ int batch_solve(fdlb_batch& b, double tol, int64_t max_steps, int32_t check_ever
     upload_map(b);
     const bool graph = use_graph && b.stream != nullptr && check_every >= 2;
     std::vector<int32_t> hlen(n, 0);
+    std::vector<MixedSwitch> sw;
+    std::vector<double> fp32_until(n);  // step count where a member's float phase ended, -1: not yet
+    for (int i = 0; i < n; ++i) {
+        const fdlb_problem& p = *b.probs[i];
+        sw.emplace_back(p.d.precision == FDLB_MIXED && p.prec == FDLB_FP32 && tol < FDLB_MIXED_SWITCH_R, base[i]);
+        fp32_until[i] = p.prec == FDLB_FP32 ? -1.0 : base[i];
+    }
     const auto t0 = std::chrono::steady_clock::now();
     int64_t launched = 0;
     int parity = parity0;
@@ -336,12 +398,22 @@ int batch_solve(fdlb_batch& b, double tol, int64_t max_steps, int32_t check_ever
         launched += k;
         read_all_ctrl(b);
         std::vector<int> still;
+        bool switched = false;
         for (int i : b.active) {
             const double* c = b.pinned + 8 * i;
             if (reps && reps[i].history && hlen[i] < reps[i].history_cap) reps[i].history[hlen[i]++] = c[CTRL_LAST_R];
-            if (c[CTRL_FIRST_BELOW] < 0 && c[CTRL_DIVERGED] < 0) still.push_back(i);
+            if (c[CTRL_FIRST_BELOW] >= 0 || c[CTRL_DIVERGED] >= 0) continue;
+            still.push_back(i);
+            fdlb_problem& p = *b.probs[i];
+            if (p.prec == FDLB_FP32 && sw[i].update(c[CTRL_LAST_R], (int64_t)c[CTRL_STEP])) {
+                p.parity = parity;  // every active member is at the batch's parity
+                promote(p);
+                fp32_until[i] = c[CTRL_STEP];
+                switched = true;
+            }
         }
-        if (still.size() != b.active.size()) {
+        if (switched) upload_rargs(b);
+        if (switched || still.size() != b.active.size()) {
             b.active = still;
             upload_map(b);
         }
@@ -365,7 +437,10 @@ int batch_solve(fdlb_batch& b, double tol, int64_t max_steps, int32_t check_ever
             r.wall_s = wall;
             const double upd = (double)r.steps * (double)p.plane * p.q;
             r.updates_per_s = wall > 0 ? upd / wall : 0;
-            r.bytes_per_s = wall > 0 ? upd * 2.0 * (double)p.elem / wall : 0;
+            r.steps_fp32 = fp32_until[i] < 0 ? r.steps : (int64_t)(fp32_until[i] - base[i]);
+            const double cell_q = (double)p.plane * p.q;
+            r.bytes_per_s =
+                wall > 0 ? cell_q * (8.0 * (double)r.steps_fp32 + 16.0 * (double)(r.steps - r.steps_fp32)) / wall : 0;
             r.status = st;
             r.history_len = hlen[i];
         }
@@ -379,12 +454,14 @@ double batch_autotune(fdlb_batch& b, int steps) {
     hipEvent_t e0, e1;
     FDLB_HIP(hipEventCreate(&e0));
     FDLB_HIP(hipEventCreate(&e1));
+    const int g = primary_group(b);
     double best = 1e300;
-    int best_tile = b.tile;
+    int best_tile = b.grp[g].tile;
     try {
-        for (int t = 0; t < (int)tile_shapes(b.precision).size(); ++t) {
-            if (!tile_fits_all(b, t)) continue;
-            batch_set_tile(b, t);
+        for (int t = 0; t < (int)tile_shapes(prec_of_group(g)).size(); ++t) {
+            if (!tile_fits_all(b, g, t)) continue;
+            group_set_tile(b, g, t);
+            // Re-seeding starts every member in the primary group's precision.
             for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
             upload_args(b);
             b.active.clear();
@@ -409,7 +486,7 @@ double batch_autotune(fdlb_batch& b, int steps) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    batch_set_tile(b, best_tile);
+    group_set_tile(b, g, best_tile);
     for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
     return best;
 }
@@ -495,7 +572,12 @@ int fdlb_batch_set_tile(fdlb_batch* b, int tile) {
     });
 }
 
-int fdlb_batch_get_tile(const fdlb_batch* b) { return b ? b->tile : FDLB_EINVAL; }
+int fdlb_batch_get_tile(const fdlb_batch* b) { return b ? b->grp[primary_group(*b)].tile : FDLB_EINVAL; }
+
+int fdlb_batch_active_precision(const fdlb_batch* b, int i) {
+    if (!b || i < 0 || i >= (int)b->probs.size()) return FDLB_EINVAL;
+    return b->probs[i]->prec;
+}
 
 int fdlb_batch_autotune(fdlb_batch* b, int steps, double* best_ms_per_step) {
     return guard_batch([&] {

@@ -27,6 +27,7 @@ void moments(fdlb_problem& p, double* rho, double* ux, double* uy, double* pxy);
 void wall_profile(fdlb_problem& p, int wall, double* rho, double* ut, double* pxy);
 void set_tile(fdlb_problem& p, int tile);
 double autotune(fdlb_problem& p, int steps);
+void promote(fdlb_problem& p);
 
 static thread_local std::string g_last_error;
 
@@ -241,6 +242,15 @@ int fdlb_problem_set_tile(fdlb_problem* p, int tile) {
 }
 
 int fdlb_problem_get_tile(const fdlb_problem* p) { return p ? p->tile : FDLB_EINVAL; }
+
+int fdlb_problem_active_precision(const fdlb_problem* p) { return p ? p->prec : FDLB_EINVAL; }
+
+int fdlb_promote(fdlb_problem* p) {
+    return guard([&] {
+        promote(handle(p));
+        return FDLB_OK;
+    });
+}
 
 int fdlb_autotune(fdlb_problem* p, int steps, double* best_ms_per_step) {
     return guard([&] {

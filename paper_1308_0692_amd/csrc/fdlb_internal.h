@@ -67,8 +67,9 @@ struct StepArgs {
     int32_t tiles_x, tiles_y;
     int32_t pad0;
     int64_t plane;        // nx * ny
-    T c1;                 // 1 - omega
+    T omega;              // dt / Kn in the storage type
     T pad1;
+    double omega_d;       // dt / Kn
     WallConst wall[4];
 };
 
@@ -99,6 +100,18 @@ struct ReduceArgs {
     double* ctrl;
     int32_t nb;     // <= 0: skip
     int32_t pad;
+};
+
+// When a FDLB_MIXED state leaves float during a steady solve: at a host check whose residual
+// is below FDLB_MIXED_SWITCH_R, or once the lowest residual seen has not dropped by 10 % for
+// FDLB_MIXED_STALL_STEPS steps (a float state stuck above the switch level).  Never when the
+// tolerance is at or above the switch level: float reaches it alone.
+struct MixedSwitch {
+    bool on;
+    double best = 1e300;
+    int64_t best_step;
+    MixedSwitch(bool enabled, double start_step) : on(enabled), best_step((int64_t)start_step) {}
+    bool update(double residual, int64_t step);  // true: switch now
 };
 
 const std::vector<TileShape>& tile_shapes(int precision);
@@ -135,6 +148,7 @@ void launch_from_raw(const double* f, const double* w_nat, int a0, int a1, int64
                      hipStream_t stream);
 void launch_mass_scale(const float* frho, int64_t cells, double* scale_out, hipStream_t stream);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+void launch_widen(const float* src, double* dst, int64_t n, hipStream_t stream);
 
 // Control block layout (doubles) written by the reduce kernel.
 enum CtrlSlot {
@@ -145,6 +159,7 @@ enum CtrlSlot {
     CTRL_MAXU = 4,        // max |u| of the last step
     CTRL_TOL = 5,         // tolerance the reduce kernel compares against
     CTRL_FREEZE = 6,      // 1: stop updating once converged or diverged (steady solves)
+    CTRL_HOST = 7,        // not used by the kernels (checkpoints keep the precision in it)
     CTRL_RING = 8,        // ring of residuals, CTRL_RING_LEN entries
 };
 constexpr int CTRL_RING_LEN = 4096;
@@ -164,13 +179,15 @@ struct fdlb_problem {
     std::vector<int> quad_order;           // velocity index of each table entry (quadrant-grouped)
     int L = 0;                             // max(nx, ny): stride of the per-wall arrays
     int64_t plane = 0;                     // nx * ny
-    size_t elem = 0;                       // bytes per stored population (4 or 8)
+    int prec = FDLB_FP64;                  // precision the kernels run in now (FDLB_FP32 / FDLB_FP64)
+    size_t elem = 0;                       // bytes per population in that precision (4 or 8)
     // layout (byte offsets into the state / workspace)
     size_t pop_bytes = 0, state_bytes = 0, work_bytes = 0;
     size_t off_mom = 0, mom_bytes = 0, off_phi = 0, phi_bytes = 0, off_part = 0, off_ctrl = 0,
            off_vel = 0, off_vel64 = 0, off_wall = 0, off_wnat = 0, off_io = 0, io_bytes = 0;
     int max_blocks = 0;
-    int tile = -1;                         // tile shape in use
+    int tile = -1;                         // tile shape in use (a shape of tile_shapes(prec))
+    int tile_alt = -1;                     // FDLB_MIXED: the shape kept for the other precision
     // binding
     char* d_state = nullptr;
     char* d_work = nullptr;
@@ -180,7 +197,7 @@ struct fdlb_problem {
     int parity = 0;                        // population buffer holding the current state
     double* pinned = nullptr;              // small pinned host buffer for control reads
     bool freeze_on = false;                // the device control block has the freeze flag set
-    // captured graphs keyed by (steps per replay, tile, starting parity)
-    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+    // captured graphs keyed by (steps per replay, precision, tile, starting parity)
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
     ~fdlb_problem();
 };

@@ -164,7 +164,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
     const int x0 = (tx * WX + wxi) * (LX * VX) + lx * VX;
     const int y0 = ((ty * WPB + wy) * LY + ly) * K;
     const bool xv = x0 < nx;
-    const T c1 = A.c1;
+    const T om = A.omega;
 
     bool rv[K];  // row r of this lane is a cell of the grid
 #pragma unroll
@@ -194,7 +194,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
     }
 
     // Wall emission parameters of this step (Eqs. 8-9): rho_w - 1 and u_w rho_w per wall face.
-    const double omega = 1.0 - (double)c1;
+    const double omega = A.omega_d;
     const bool on_left = xv && x0 == 0 && A.wall[LEFT].active;
     const bool on_right = xv && (x0 + VX == nx) && A.wall[RIGHT].active;
     const bool on_bot = xv && y0 == 0 && A.wall[BOTTOM].active;
@@ -358,15 +358,19 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
             T gr[K][VX];
 
             // Relaxation (explicit Euler of Eq. 1 towards Eq. 5, deviation form).
+            // g = h + (omega h_eq - omega h): the increment is formed before it is added, so the
+            // relaxation rate is omega itself (a rounded 1 - omega would bias a small omega).
 #pragma unroll
             for (int r = 0; r < K; ++r)
 #pragma unroll
                 for (int v = 0; v < VX; ++v)
-                    gr[r][v] = c1 * g[r][v] + (c.ow * mr[r][v] + c.owx * mx[r][v] + c.owy * my[r][v]);
+                    gr[r][v] = g[r][v] + ((c.ow * mr[r][v] + c.owx * mx[r][v] + c.owy * my[r][v]) - om * g[r][v]);
 #pragma unroll
-            for (int r = 0; r < K; ++r) gxh[r] = c1 * gxh[r] + (c.ow * hxr[r] + c.owx * hxx[r] + c.owy * hxy[r]);
+            for (int r = 0; r < K; ++r)
+                gxh[r] = gxh[r] + ((c.ow * hxr[r] + c.owx * hxx[r] + c.owy * hxy[r]) - om * gxh[r]);
 #pragma unroll
-            for (int v = 0; v < VX; ++v) gyh[v] = c1 * gyh[v] + (c.ow * hyr[v] + c.owx * hyx[v] + c.owy * hyy[v]);
+            for (int v = 0; v < VX; ++v)
+                gyh[v] = gyh[v] + ((c.ow * hyr[v] + c.owx * hyx[v] + c.owy * hyy[v]) - om * gyh[v]);
 
             // Upwind values across the lane boundary: neighbour lane, halo, or wall emission.
             T xb[K];
@@ -865,6 +869,13 @@ __global__ void __launch_bounds__(256) from_raw_kernel(const double* __restrict_
     h[(int64_t)a * plane + i % plane] = (T)(f[i] - w_nat[a]);
 }
 
+// Float deviations -> double deviations (exact), for the switch of a mixed-precision state.
+__global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ src, double* __restrict__ dst,
+                                                    int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
 // Streaming copy for the bandwidth ceiling: each thread keeps 8 x 16-byte loads in flight.
 constexpr int COPY_UNROLL = 8;
 typedef float copy_vec_t __attribute__((ext_vector_type(4)));
@@ -1067,6 +1078,13 @@ void launch_from_raw(const double* f, const double* w_nat, int a0, int a1, int64
                      hipStream_t stream) {
     hipLaunchKernelGGL(from_raw_kernel<T>, dim3(blocks_for(plane * (a1 - a0), 256)), dim3(256), 0, stream, f,
                        w_nat, a0, a1, plane, h);
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_widen(const float* src, double* dst, int64_t n, hipStream_t stream) {
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>(16384, (n + 255) / 256);
+    hipLaunchKernelGGL(widen_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, src, dst, n);
     FDLB_HIP(hipGetLastError());
 }
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <type_traits>
 
 #include "fdlb_internal.h"
 
@@ -85,9 +86,10 @@ int heuristic_tile_for(int precision, int nx, int ny, bool px, bool py) {
     return best;
 }
 
-static int heuristic_tile(const fdlb_problem& p) {
-    return heuristic_tile_for(p.d.precision, p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y);
+static int heuristic_tile(const fdlb_problem& p, int precision) {
+    return heuristic_tile_for(precision, p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y);
 }
+static int heuristic_tile(const fdlb_problem& p) { return heuristic_tile(p, p.prec); }
 
 void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     if (d.nx < 1 || d.ny < 1) throw Error(FDLB_EINVAL, "nx and ny must be >= 1");
@@ -96,8 +98,8 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
         throw Error(FDLB_EINVAL, "a periodic axis must have exactly one cell");
     if (!d.periodic_x && d.nx < 2) throw Error(FDLB_EINVAL, "a bounded axis needs at least 2 cells");
     if (!d.periodic_y && d.ny < 2) throw Error(FDLB_EINVAL, "a bounded axis needs at least 2 cells");
-    if (d.precision != FDLB_FP32 && d.precision != FDLB_FP64)
-        throw Error(FDLB_EINVAL, "precision must be FDLB_FP32 or FDLB_FP64");
+    if (d.precision != FDLB_FP32 && d.precision != FDLB_FP64 && d.precision != FDLB_MIXED)
+        throw Error(FDLB_EINVAL, "precision must be FDLB_FP32, FDLB_FP64 or FDLB_MIXED");
     if (!(d.cfl > 0) || !std::isfinite(d.cfl)) throw Error(FDLB_EINVAL, "cfl must be positive and finite");
     if (!(d.kn > 0)) throw Error(FDLB_EINVAL, "kn must be positive (INFINITY allowed)");
     for (int i = 0; i < 4; ++i)
@@ -165,14 +167,20 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
         }
     }
     p.quad_begin[4] = p.q;
-    // Device layout.
-    p.elem = d.precision == FDLB_FP32 ? 4 : 8;
-    p.pop_bytes = align256((size_t)p.q * p.plane * p.elem);
+    // Device layout.  A mixed-precision state starts in float inside buffers sized for double.
+    p.prec = d.precision == FDLB_FP64 ? FDLB_FP64 : FDLB_FP32;
+    p.elem = p.prec == FDLB_FP32 ? 4 : 8;
+    const size_t store_elem = d.precision == FDLB_FP32 ? 4 : 8;
+    p.pop_bytes = align256((size_t)p.q * p.plane * store_elem);
     p.state_bytes = 2 * p.pop_bytes;
     int maxb = 1;
-    for (const TileShape& t : tile_shapes(d.precision)) {
-        const int64_t nb = (int64_t)((d.nx + t.tile_w() - 1) / t.tile_w()) * ((d.ny + t.tile_h() - 1) / t.tile_h());
-        maxb = (int)std::max<int64_t>(maxb, nb);
+    for (int prec : {FDLB_FP32, FDLB_FP64}) {
+        if (d.precision != FDLB_MIXED && prec != p.prec) continue;
+        for (const TileShape& t : tile_shapes(prec)) {
+            const int64_t nb =
+                (int64_t)((d.nx + t.tile_w() - 1) / t.tile_w()) * ((d.ny + t.tile_h() - 1) / t.tile_h());
+            maxb = (int)std::max<int64_t>(maxb, nb);
+        }
     }
     p.max_blocks = maxb;
     size_t off = 0;
@@ -187,7 +195,7 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     p.off_ctrl = off;
     off += align256(CTRL_DOUBLES * sizeof(double));
     p.off_vel = off;
-    off += align256((size_t)p.q * (d.precision == FDLB_FP32 ? sizeof(VelEntry<float>) : sizeof(VelEntry<double>)));
+    off += align256((size_t)p.q * (p.prec == FDLB_FP32 ? sizeof(VelEntry<float>) : sizeof(VelEntry<double>)));
     p.off_vel64 = off;
     off += align256((size_t)p.q * sizeof(VelEntry<double>));
     p.off_wall = off;
@@ -199,6 +207,21 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     off += p.io_bytes;
     p.work_bytes = off;
     p.tile = heuristic_tile(p);
+    p.tile_alt = d.precision == FDLB_MIXED ? heuristic_tile(p, FDLB_FP64) : -1;
+}
+
+// Switch the precision the kernels run in (FDLB_MIXED only changes it); the tile of the
+// other precision is kept for the way back.
+static void set_active(fdlb_problem& p, int prec) {
+    if (p.prec == prec) return;
+    p.prec = prec;
+    p.elem = prec == FDLB_FP32 ? 4 : 8;
+    std::swap(p.tile, p.tile_alt);
+}
+
+// A new state of a mixed-precision problem starts in float.
+static void restart_precision(fdlb_problem& p) {
+    if (p.d.precision == FDLB_MIXED) set_active(p, FDLB_FP32);
 }
 
 template <class T>
@@ -245,7 +268,7 @@ void bind(fdlb_problem& p, void* d_state, void* d_work, void* stream) {
     p.d_work = (char*)d_work;
     p.stream = (hipStream_t)stream;
     if (!p.pinned) FDLB_HIP(hipHostMalloc((void**)&p.pinned, 64 * sizeof(double), hipHostMallocDefault));
-    if (p.d.precision == FDLB_FP32) {
+    if (p.d.precision != FDLB_FP64) {
         auto v = vel_table<float>(p);
         FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, p.stream));
         FDLB_HIP(hipStreamSynchronize(p.stream));
@@ -288,7 +311,7 @@ static void reset_ctrl(fdlb_problem& p, double tol) {
 // Recompute the moment and wall-flux buffers of the current state.
 static void refresh_moments(fdlb_problem& p) {
     const int par = p.parity;
-    if (p.d.precision == FDLB_FP32)
+    if (p.prec == FDLB_FP32)
         launch_moments<float>((const float*)pop_buf(p, par), (double*)mom_buf(p, par), phi_buf(p, par),
                               (const VelEntry<float>*)(p.d_work + p.off_vel), p.q, p.d.nx, p.d.ny, p.L,
                               (const WallConst*)(p.d_work + p.off_wall), p.stream);
@@ -325,7 +348,8 @@ void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, cons
         pv = in + 2 * n;
     }
     p.parity = 0;
-    if (p.d.precision == FDLB_FP32)
+    restart_precision(p);
+    if (p.prec == FDLB_FP32)
         launch_seed<float>((float*)pop_buf(p, 0), p.q, n, vel64(p), pr, pu, pv, nullptr, nullptr, nullptr, nullptr,
                            p.stream);
     else
@@ -346,7 +370,8 @@ void init_equilibrium_dev(fdlb_problem& p, const float* rho, const float* ux, co
         launch_mass_scale(rho, p.plane, scale, p.stream);
     }
     p.parity = 0;
-    if (p.d.precision == FDLB_FP32)
+    restart_precision(p);
+    if (p.prec == FDLB_FP32)
         launch_seed<float>((float*)pop_buf(p, 0), p.q, p.plane, vel64(p), nullptr, nullptr, nullptr, rho, ux, uy,
                            scale, p.stream);
     else
@@ -361,12 +386,13 @@ void state_upload(fdlb_problem& p, const double* f) {
     require_bound(p);
     if (!f) throw Error(FDLB_EINVAL, "NULL host array");
     p.parity = 0;
+    restart_precision(p);
     const int chunk = 4;
     for (int a0 = 0; a0 < p.q; a0 += chunk) {
         const int a1 = std::min(p.q, a0 + chunk);
         FDLB_HIP(hipMemcpyAsync(io(p), f + (size_t)a0 * p.plane, (size_t)(a1 - a0) * p.plane * sizeof(double),
                                 hipMemcpyHostToDevice, p.stream));
-        if (p.d.precision == FDLB_FP32)
+        if (p.prec == FDLB_FP32)
             launch_from_raw<float>(io(p), (const double*)(p.d_work + p.off_wnat), a0, a1, p.plane,
                                    (float*)pop_buf(p, 0), p.stream);
         else
@@ -386,7 +412,7 @@ void state_download(fdlb_problem& p, double* f) {
     const int chunk = 4;
     for (int a0 = 0; a0 < p.q; a0 += chunk) {
         const int a1 = std::min(p.q, a0 + chunk);
-        if (p.d.precision == FDLB_FP32)
+        if (p.prec == FDLB_FP32)
             launch_to_raw<float>((const float*)pop_buf(p, p.parity), (const double*)(p.d_work + p.off_wnat), a0, a1,
                                  p.plane, io(p), p.stream);
         else
@@ -415,12 +441,21 @@ void checkpoint_save(fdlb_problem& p, void* host) {
     FDLB_HIP(hipMemcpyAsync(h + p.pop_bytes + p.mom_bytes + p.phi_bytes, ctrl(p), 8 * sizeof(double),
                             hipMemcpyDeviceToHost, p.stream));
     FDLB_HIP(hipStreamSynchronize(p.stream));
+    const double prec = (double)p.prec;
+    std::memcpy(h + p.pop_bytes + p.mom_bytes + p.phi_bytes + CTRL_HOST * sizeof(double), &prec, sizeof(prec));
 }
 
 void checkpoint_load(fdlb_problem& p, const void* host) {
     require_bound(p);
     if (!host) throw Error(FDLB_EINVAL, "NULL host buffer");
     const char* h = (const char*)host;
+    double prec = 0;
+    std::memcpy(&prec, h + p.pop_bytes + p.mom_bytes + p.phi_bytes + CTRL_HOST * sizeof(double), sizeof(prec));
+    if (p.d.precision == FDLB_MIXED) {
+        if (prec != (double)FDLB_FP32 && prec != (double)FDLB_FP64)
+            throw Error(FDLB_EINVAL, "not a checkpoint of a mixed-precision problem");
+        set_active(p, (int)prec);
+    }
     p.parity = 0;
     FDLB_HIP(hipMemcpyAsync(pop_buf(p, 0), h, p.pop_bytes, hipMemcpyHostToDevice, p.stream));
     FDLB_HIP(hipMemcpyAsync(mom_buf(p, 0), h + p.pop_bytes, p.mom_bytes, hipMemcpyHostToDevice, p.stream));
@@ -437,7 +472,8 @@ void checkpoint_load(fdlb_problem& p, const void* host) {
 // ---------------------------------------------------------------------------
 template <class T>
 static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile) {
-    const TileShape& t = tile_shapes(p.d.precision)[tile];
+    constexpr bool f32 = std::is_same<T, float>::value;
+    const TileShape& t = tile_shapes(f32 ? FDLB_FP32 : FDLB_FP64)[tile];
     StepArgs<T> a;
     std::memset(&a, 0, sizeof(a));
     a.src = (const T*)pop_buf(p, parity);
@@ -448,7 +484,7 @@ static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile) {
     a.phi_out = phi_buf(p, parity ^ 1);
     a.partials = (double*)(p.d_work + p.off_part);
     a.ctrl = ctrl(p);
-    a.vel = (const VelEntry<T>*)(p.d_work + p.off_vel);
+    a.vel = (const VelEntry<T>*)(p.d_work + (f32 ? p.off_vel : p.off_vel64));
     for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
     a.nx = p.d.nx;
     a.ny = p.d.ny;
@@ -456,20 +492,21 @@ static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile) {
     a.tiles_x = (p.d.nx + t.tile_w() - 1) / t.tile_w();
     a.tiles_y = (p.d.ny + t.tile_h() - 1) / t.tile_h();
     a.plane = p.plane;
-    a.c1 = (T)(1.0 - p.omega);
+    a.omega = (T)p.omega;
+    a.omega_d = p.omega;
     for (int i = 0; i < 4; ++i) a.wall[i] = p.wall[i];
     return a;
 }
 
 static int nblocks_of(const fdlb_problem& p, int tile) {
-    const TileShape& t = tile_shapes(p.d.precision)[tile];
+    const TileShape& t = tile_shapes(p.prec)[tile];
     return ((p.d.nx + t.tile_w() - 1) / t.tile_w()) * ((p.d.ny + t.tile_h() - 1) / t.tile_h());
 }
 
 // Enqueue one step (fused step kernel + residual reduction) from buffer `parity`.
 static void enqueue_step(fdlb_problem& p, int parity, int tile) {
     const int nb = nblocks_of(p, tile);
-    if (p.d.precision == FDLB_FP32)
+    if (p.prec == FDLB_FP32)
         launch_step<float>(tile, step_args<float>(p, parity, tile), nb, p.stream);
     else
         launch_step<double>(tile, step_args<double>(p, parity, tile), nb, p.stream);
@@ -493,6 +530,31 @@ static void unfreeze(fdlb_problem& p) {
     p.freeze_on = false;
 }
 
+// Mixed precision: carry the current float state over to double in place (the widened
+// values are exact), then recompute its moments and wall fluxes with the double kernels so
+// that the next step sees exactly what a double run from this state would.
+void promote(fdlb_problem& p) {
+    require_seeded(p);
+    if (p.d.precision != FDLB_MIXED) throw Error(FDLB_EINVAL, "only a FDLB_MIXED problem changes precision");
+    if (p.prec == FDLB_FP64) return;
+    const int par = p.parity;
+    const int64_t n = (int64_t)p.q * p.plane;
+    launch_widen((const float*)pop_buf(p, par), (double*)pop_buf(p, par ^ 1), n, p.stream);
+    launch_copy(pop_buf(p, par), pop_buf(p, par ^ 1), (size_t)n * sizeof(double), p.stream);
+    set_active(p, FDLB_FP64);
+    refresh_moments(p);
+    FDLB_HIP(hipStreamSynchronize(p.stream));
+}
+
+bool MixedSwitch::update(double r, int64_t step) {
+    if (!on) return false;
+    if (r < 0.9 * best) {
+        best = r;
+        best_step = step;
+    }
+    return r < FDLB_MIXED_SWITCH_R || step - best_step >= FDLB_MIXED_STALL_STEPS;
+}
+
 void step(fdlb_problem& p, int64_t n) {
     require_seeded(p);
     if (n < 0) throw Error(FDLB_EINVAL, "nsteps must be >= 0");
@@ -511,7 +573,7 @@ void step_timed(fdlb_problem& p, int64_t n, double* ms_step, double* ms_reduce) 
         const int nb = nblocks_of(p, p.tile);
         FDLB_HIP(hipEventRecord(ev[0], p.stream));
         for (int64_t i = 0; i < n; ++i) {
-            if (p.d.precision == FDLB_FP32)
+            if (p.prec == FDLB_FP32)
                 launch_step<float>(p.tile, step_args<float>(p, p.parity, p.tile), nb, p.stream);
             else
                 launch_step<double>(p.tile, step_args<double>(p, p.parity, p.tile), nb, p.stream);
@@ -540,7 +602,7 @@ void step_timed(fdlb_problem& p, int64_t n, double* ms_step, double* ms_reduce) 
 
 // Replay k steps as one captured graph (k even keeps the buffer parity).
 static void enqueue_graph(fdlb_problem& p, int k) {
-    auto key = std::make_tuple(k, p.tile, p.parity);
+    auto key = std::make_tuple(k, p.prec, p.tile, p.parity);
     auto it = p.graphs.find(key);
     if (it == p.graphs.end()) {
         hipGraph_t g;
@@ -595,6 +657,8 @@ int solve_steady(fdlb_problem& p, double tol, int64_t max_steps, int32_t check_e
                             hipMemcpyHostToDevice, p.stream));
     FDLB_HIP(hipStreamSynchronize(p.stream));
     p.freeze_on = true;
+    MixedSwitch sw(p.d.precision == FDLB_MIXED && p.prec == FDLB_FP32 && tol < FDLB_MIXED_SWITCH_R, base);
+    double fp32_until = p.prec == FDLB_FP32 ? -1.0 : base;  // step count where the float phase ended
     const auto t0 = std::chrono::steady_clock::now();
     int64_t launched = 0;
     int status = FDLB_ENOTCONVERGED;
@@ -614,11 +678,16 @@ int solve_steady(fdlb_problem& p, double tol, int64_t max_steps, int32_t check_e
             status = FDLB_OK;
             break;
         }
+        if (p.prec == FDLB_FP32 && sw.update(p.pinned[CTRL_LAST_R], (int64_t)p.pinned[CTRL_STEP])) {
+            promote(p);
+            fp32_until = p.pinned[CTRL_STEP];
+        }
     }
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     // The device may have stopped inside the last chunk: its step counter says where.
     const int64_t done = (int64_t)(p.pinned[CTRL_STEP] - base);
     p.parity = (int)((int64_t)p.pinned[CTRL_STEP] & 1);
+    const int64_t done32 = fp32_until < 0 ? done : (int64_t)(fp32_until - base);
     if (rep) {
         rep->steps = done;
         rep->first_below = status == FDLB_OK ? (int64_t)(p.pinned[CTRL_FIRST_BELOW] - base) : -1;
@@ -626,9 +695,12 @@ int solve_steady(fdlb_problem& p, double tol, int64_t max_steps, int32_t check_e
         rep->wall_s = wall;
         const double upd = (double)done * (double)p.plane * p.q;
         rep->updates_per_s = wall > 0 ? upd / wall : 0;
-        rep->bytes_per_s = wall > 0 ? upd * 2.0 * (double)p.elem / wall : 0;
+        const double cell_q = (double)p.plane * p.q;
+        const double bytes = cell_q * (8.0 * (double)done32 + 16.0 * (double)(done - done32));
+        rep->bytes_per_s = wall > 0 ? bytes / wall : 0;
         rep->status = status;
         rep->history_len = hlen;
+        rep->steps_fp32 = done32;
     }
     if (status == FDLB_EDIVERGED) {
         throw Error(FDLB_EDIVERGED, "solve diverged at step " + std::to_string((int64_t)(p.pinned[CTRL_DIVERGED] - base)) +
@@ -642,7 +714,7 @@ int solve_steady(fdlb_problem& p, double tol, int64_t max_steps, int32_t check_e
 // ---------------------------------------------------------------------------
 void moments(fdlb_problem& p, double* rho, double* ux, double* uy, double* pxy) {
     require_seeded(p);
-    if (p.d.precision == FDLB_FP32)
+    if (p.prec == FDLB_FP32)
         launch_post<float>((const float*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, p.omega, io(p), p.stream);
     else
         launch_post<double>((const double*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, p.omega, io(p),
@@ -660,7 +732,7 @@ void wall_profile(fdlb_problem& p, int wall, double* rho, double* ut, double* px
     if (wall < 0 || wall > 3) throw Error(FDLB_EINVAL, "wall index must be 0..3");
     if (!p.wall[wall].active) throw Error(FDLB_EINVAL, "that wall is absent (periodic axis)");
     const int n = (wall == BOTTOM || wall == TOP) ? p.d.nx : p.d.ny;
-    if (p.d.precision == FDLB_FP32)
+    if (p.prec == FDLB_FP32)
         launch_wall_profile<float>((const float*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, wall,
                                    &p.wall[wall], p.omega, io(p), p.stream);
     else
@@ -682,7 +754,7 @@ void set_tile(fdlb_problem& p, int tile) {
         p.tile = heuristic_tile(p);
         return;
     }
-    const auto& shapes = tile_shapes(p.d.precision);
+    const auto& shapes = tile_shapes(p.prec);
     if (tile >= (int)shapes.size()) throw Error(FDLB_EINVAL, "tile index out of range");
     if (!tile_fits(shapes[tile], p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y))
         throw Error(FDLB_EINVAL, "tile shape does not fit this grid");
@@ -693,7 +765,8 @@ void set_tile(fdlb_problem& p, int tile) {
 double autotune(fdlb_problem& p, int steps) {
     require_bound(p);
     if (steps < 1) throw Error(FDLB_EINVAL, "steps must be >= 1");
-    const auto& shapes = tile_shapes(p.d.precision);
+    restart_precision(p);  // a mixed-precision problem tunes its float phase
+    const auto& shapes = tile_shapes(p.prec);
     hipEvent_t e0, e1;
     FDLB_HIP(hipEventCreate(&e0));
     FDLB_HIP(hipEventCreate(&e1));
