@@ -12,9 +12,12 @@ updates per second.  `roofline` prices the fused step kernel against the HBM
 peak using its algorithmic bytes (every population read once and written once,
 plus the per-cell moments) and its own average duration from HIP events on the
 library's stream.  Extra fields: the time to residual 1e-8 of the 128 x 128
-cavity in FP32 versus plain FP64, the Couette time to 1e-10 in FP64, and the
-measured copy bandwidth.  `cpu_baseline` times the FP64 CPU oracle on a bounded
-sample of the same workload.
+cavity in FP32, mixed precision and plain FP64; the Couette time to 1e-10 in
+FP64; the 64-cavity sweep (Kn log-uniform in [0.01, 10], N in {64..192}, 8^2 or
+12^2 velocities) solved to 1e-8 as one mixed-precision batch versus plain FP64
+single-instance solves of the same cases; and the measured copy bandwidth.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -54,20 +57,32 @@ def measured_traffic(per_launch_bytes_alg: float):
     return d.get("hbm_bytes_per_launch")
 
 
+def eps_u(ux, uy, uxr, uyr):
+    import numpy as np
+    return float(np.hypot(ux - uxr, uy - uyr).max() / np.hypot(uxr, uyr).max())
+
+
 def time_to_residual(F, W):
-    """Plain FP64 and FP32 solves of the 128^2 cavity to R < 1e-8 and the Couette case to 1e-10."""
+    """FP32, mixed and plain FP64 solves of the 128^2 cavity to R < 1e-8 and the Couette case
+    to 1e-10.  The error of each cavity result is stated against the FP64 one."""
     out = {}
     c2 = W.C2
-    for prec, graph in (("fp32", True), ("fp64", True), ("fp64", False)):
+    ref = None
+    for prec, graph in (("fp64", True), ("fp64", False), ("fp32", True), ("mixed", True)):
         p = F.Problem(c2, precision=prec)
         p.init_equilibrium()
         p.solve(1e-8, 400, check_every=200, use_graph=graph)  # warm-up (graph capture)
         p.init_equilibrium()
         rep = p.solve(1e-8, 200000, check_every=200, use_graph=graph)
         key = f"cavity128_q64_{prec}{'_graph' if graph else ''}"
-        out[key] = {"wall_s": round(rep["wall_s"], 4), "steps": rep["steps"],
-                    "first_below": rep["first_below"], "updates_per_s": rep["updates_per_s"]}
-        log(f"  {key}: {rep['wall_s']:.3f} s, {rep['steps']} steps")
+        rho, ux, uy, _ = p.moments()
+        if ref is None:
+            ref = (rho, ux, uy)
+        out[key] = {"wall_s": round(rep["wall_s"], 4), "steps": rep["steps"], "steps_fp32": rep["steps_fp32"],
+                    "first_below": rep["first_below"], "updates_per_s": rep["updates_per_s"],
+                    "eps_u_vs_fp64": eps_u(ux, uy, ref[1], ref[2]),
+                    "eps_rho_vs_fp64": float(abs(rho - ref[0]).max())}
+        log(f"  {key}: {rep['wall_s']:.3f} s, {rep['steps']} steps ({rep['steps_fp32']} in float)")
         p.close()
     p = F.Problem(W.C1, precision="fp64")
     p.init_equilibrium()
@@ -78,6 +93,54 @@ def time_to_residual(F, W):
                                         "first_below": rep["first_below"]}
     log(f"  couette: {rep['wall_s']:.3f} s, {rep['steps']} steps")
     p.close()
+    return out
+
+
+def sweep_c3(F, W, torch):
+    """The 64-cavity sweep to R < 1e-8: one mixed-precision batch (autotuned float tile,
+    graph-captured chunks) against plain FP64 single-instance solves of the same cases (each
+    with its graph captured beforehand, outside the timing).  Error of every batch member
+    against its FP64 solution, at the same tolerance."""
+    cases = W.c3_instances()
+    solo_wall, solo_steps, ref = 0.0, [], []
+    for c in cases:
+        p = F.Problem(c, precision="fp64")
+        p.init_equilibrium()
+        p.solve(1e-8, 400, check_every=200)  # graph capture
+        p.init_equilibrium()
+        rep = p.solve(1e-8, 200000, check_every=200)
+        solo_wall += rep["wall_s"]
+        solo_steps.append(rep["steps"])
+        if rep["status"] != 0:
+            raise RuntimeError(f"{c.name}: plain FP64 solve did not converge")
+        ref.append(p.moments()[:3])
+        p.close()
+    log(f"  plain FP64, one instance at a time: {solo_wall:.2f} s, {sum(solo_steps)} steps")
+    b = F.Batch(cases, precision="mixed")
+    ms = b.autotune(steps=3)
+    for i in range(len(cases)):
+        b.init_equilibrium(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, reps = b.solve(1e-8, 200000, check_every=200)
+    wall = time.perf_counter() - t0
+    eu, er = 0.0, 0.0
+    for i in range(len(cases)):
+        rho, ux, uy, _ = b.moments(i)
+        eu = max(eu, eps_u(ux, uy, ref[i][1], ref[i][2]))
+        er = max(er, float(abs(rho - ref[i][0]).max()))
+    steps = [r["steps"] for r in reps]
+    f32 = [r["steps_fp32"] for r in reps]
+    log(f"  mixed batch: {wall:.2f} s (status {status}), {sum(steps)} steps of which {sum(f32)} in float; "
+        f"max eps_u vs FP64 {eu:.2e}")
+    out = {"instances": len(cases), "tol": 1e-8,
+           "plain_fp64_solo": {"wall_s": round(solo_wall, 3), "steps": sum(solo_steps)},
+           "mixed_batch": {"wall_s": round(wall, 3), "status": status, "steps": sum(steps),
+                           "steps_fp32": sum(f32), "converged": sum(r["status"] == 0 for r in reps),
+                           "tile": F.tile_describe("fp32", b.tile), "autotune_ms_per_step": round(ms, 4),
+                           "max_eps_u_vs_fp64": eu, "max_eps_rho_vs_fp64": er},
+           "speedup_vs_plain_fp64": round(solo_wall / wall, 3)}
+    b.close()
     return out
 
 
@@ -125,6 +188,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 64-cavity batch versus plain FP64 runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU, "
@@ -143,7 +207,8 @@ def main():
         log(f"[bench] autotuned tile {p.tile} ({F.tile_describe('fp32', p.tile)}): {ms:.3f} ms/step")
     elif args.tile >= 0:
         p.set_tile(args.tile)
-    tile_desc = F.tile_describe("fp32", p.tile)
+    tile_index = p.tile
+    tile_desc = F.tile_describe("fp32", tile_index)
     p.init_equilibrium()
     p.step(args.warmup)
     torch.cuda.synchronize()
@@ -170,8 +235,8 @@ def main():
     ms_per_step = ms_total / args.steps
     value = updates_per_step * args.steps / (ms_total * 1e-3)
     # algorithmic bytes of one step-kernel launch: populations read + written (4 B each),
-    # per-cell moments read + written (3 + 3 floats), wall fluxes (4 walls x N doubles, in + out)
-    alg_bytes = updates_per_step * 8 + cells * 6 * 4 + 2 * 4 * max(case.nx, case.ny) * 8
+    # per-cell moments read + written (3 + 3 doubles), wall fluxes (4 walls x N doubles, in + out)
+    alg_bytes = updates_per_step * 8 + cells * 6 * 8 + 2 * 4 * max(case.nx, case.ny) * 8
     avg_kernel_s = ms_step_k * 1e-3 / args.steps
     achieved = alg_bytes / avg_kernel_s / 1e9
     traffic = measured_traffic(alg_bytes)
@@ -189,6 +254,9 @@ def main():
         log("[bench] time to residual:")
         extra["time_to_residual"] = time_to_residual(F, W)
     p.close()
+    if not args.no_sweep:
+        log("[bench] 64-cavity sweep to 1e-8:")
+        extra["sweep64"] = sweep_c3(F, W, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -202,7 +270,7 @@ def main():
             "data": "synthetic",
             "config": {"workload": case.name, "nx": case.nx, "ny": case.ny, "q": q, "kn": case.kn,
                        "lid_u": case.wall_u[1], "velocities": "half-range Gauss-Hermite 8 per half, tensor",
-                       "tile": tile_desc},
+                       "tile": tile_desc, "tile_index": tile_index},
             "roofline": roofline, "cpu_baseline": cpu, **extra}
     print(json.dumps(line), flush=True)
 

@@ -55,6 +55,9 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch first: the library then binds to the HIP runtime torch has loaded, so that one
+    # runtime (one view of the devices, streams and allocations) serves the process.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     dp, vp, i64, i32 = C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_int32
     fp = C.POINTER(C.c_float)
