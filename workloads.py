@@ -148,3 +148,28 @@ def random_noise(q: int, nx: int, ny: int, seed: int) -> np.ndarray:
 def with_(case: Case, **kw) -> Case:
     """Copy of a case with some fields replaced."""
     return replace(case, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Warm-start network: seeded parameters and samples (inputs only; no arithmetic of the method).
+# ---------------------------------------------------------------------------
+
+def mlp_params(seed: int, width: int = 128, hidden: int = 4, scale: float = 1.0) -> np.ndarray:
+    """Flat parameter vector, layer by layer (W row-major by output, then b): weights uniform in
+    +-scale*sqrt(6 / (fan_in + fan_out)), biases uniform in +-0.1."""
+    rng = np.random.default_rng(seed)
+    shapes = [(width, 3)] + [(width, width)] * (hidden - 1) + [(3, width)]
+    parts = []
+    for o, i in shapes:
+        lim = scale * np.sqrt(6.0 / (i + o))
+        parts.append(rng.uniform(-lim, lim, size=o * i))
+        parts.append(rng.uniform(-0.1, 0.1, size=o))
+    return np.concatenate(parts)
+
+
+def mlp_samples(n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Encoded inputs in [-1, 1]^3 and smooth targets of order one, shape (n, 3) each."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, size=(n, 3))
+    t = np.stack([np.sin(2 * a[:, 1]) * a[:, 0], a[:, 2] ** 2 - 0.3, np.cos(a[:, 0] + a[:, 1])], axis=1)
+    return a, t
