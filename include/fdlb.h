@@ -341,6 +341,81 @@ int fdlb_batch_state_download(fdlb_batch *b, int i, double *f_host);
 int fdlb_batch_set_tile(fdlb_batch *b, int tile);
 int fdlb_batch_get_tile(const fdlb_batch *b);
 int fdlb_batch_autotune(fdlb_batch *b, int steps, double *best_ms_per_step);
+/*
+ * FDLB_MIXED batches: each instance leaves float on its own (see FDLB_MIXED_SWITCH_R); while
+ * some instances run in float and others in double, every step launches the two groups one
+ * after the other.  The tile calls above act on the float group; the double group uses the
+ * built-in choice.  fdlb_batch_active_precision gives instance i's current precision.
+ */
+int fdlb_batch_active_precision(const fdlb_batch *b, int i);
+
+/* ---- learned warm start ----------------------------------------------------------------- */
+
+/*
+ * A small network maps (Kn, x, y) to the steady fields (rho, u_x, u_y) of a problem; its
+ * prediction seeds the state at equilibrium (Eqs. 3, 5, via fdlb_init_equilibrium_dev with
+ * mass renormalisation) and the solver then iterates to the tolerance as usual, so the
+ * network only changes where the iteration starts.
+ *
+ * Network: inputs a = ((log10 Kn + 0.5) / 1.5, 2x - 1, 2y - 1) (cell centres on the unit
+ * square; Kn in [0.01, 10] maps to [-1, 1]); hidden layers of width 128 with tanh; outputs
+ * y = ((rho - 1) / u_w, u_x / u_w, u_y / u_w), u_w the fastest wall speed (the linearised
+ * problem is linear in u_w).  Parameters: one float vector, layer by layer, W_l row-major
+ * by output then b_l (W_0: 128 x 3, hidden W_l: 128 x 128, W_L: 3 x 128); 50,435 of them
+ * for four hidden layers.  The 128 x 128 products use bf16 operands with fp32
+ * accumulation on the matrix cores; everything else is fp32.  Loss: mean squared error
+ * over samples and outputs.  Optimiser: Adam with bias correction.
+ */
+typedef struct fdlb_mlp fdlb_mlp; /* opaque host handle */
+
+/* hidden_layers 1..8; max_batch (samples per training step) 1..2^22.  Host only. */
+int fdlb_mlp_create(int hidden_layers, int64_t max_batch, fdlb_mlp **out);
+void fdlb_mlp_destroy(fdlb_mlp *m);
+int64_t fdlb_mlp_param_count(const fdlb_mlp *m);
+size_t fdlb_mlp_workspace_bytes(const fdlb_mlp *m); /* activations, partial gradients, bf16 weights */
+
+/* Glorot-uniform weights (bound sqrt(6 / (fan_in + fan_out)), splitmix64 stream from
+ * `seed`) and zero biases into a caller host array of fdlb_mlp_param_count floats. */
+int fdlb_mlp_init_params(const fdlb_mlp *m, uint64_t seed, float *host_params);
+
+/*
+ * Caller-owned device buffers: parameters, gradient, Adam first and second moments
+ * (param_count floats each; the moments must be zero before Adam step 1) and the workspace
+ * (256-byte aligned).  Every call below is asynchronous on `stream` unless it says otherwise.
+ */
+int fdlb_mlp_bind(fdlb_mlp *m, float *d_params, float *d_grad, float *d_adam_m, float *d_adam_v,
+                  void *d_workspace, void *stream);
+
+/* Inference: d_out[n][3] = network(d_in[n][3]) for any n >= 0. */
+int fdlb_mlp_forward(fdlb_mlp *m, const float *d_in, int64_t n, float *d_out);
+
+/*
+ * One training evaluation: forward pass, loss and gradient (written to the bound gradient
+ * buffer) of the mean squared error over n samples (1 <= n <= max_batch).  Sample g is row
+ * d_rows[g] of d_in[.][3] and d_target[.][3] (d_rows may be NULL: row g).
+ */
+int fdlb_mlp_backward(fdlb_mlp *m, const float *d_in, const float *d_target, const int32_t *d_rows, int64_t n);
+/* Loss of the last fdlb_mlp_backward (synchronous). */
+int fdlb_mlp_last_loss(fdlb_mlp *m, double *loss);
+
+/* Adam update of the parameters from the bound gradient; step counts from 1. */
+int fdlb_mlp_adam_step(fdlb_mlp *m, double lr, double beta1, double beta2, double eps, int64_t step);
+
+/*
+ * Predicted fields of an nx x ny problem with Knudsen number kn and fastest wall speed
+ * u_w, into device arrays of nx ny floats ([y][x]): rho = 1 + u_w y_0, u = u_w (y_1, y_2).
+ */
+int fdlb_mlp_predict_fields(fdlb_mlp *m, double kn, int nx, int ny, double u_w, float *d_rho, float *d_ux,
+                            float *d_uy);
+
+/*
+ * Training samples from the current state of a problem (or instance i of a batch): for every
+ * cell ([y][x] order) the network input and the target fields as defined above, into device
+ * arrays of nx ny x 3 floats each.  FDLB_EINVAL for Kn = INFINITY or no moving wall.
+ * Asynchronous on the problem's stream.
+ */
+int fdlb_field_samples(fdlb_problem *p, float *d_in, float *d_target);
+int fdlb_batch_field_samples(fdlb_batch *b, int i, float *d_in, float *d_target);
 
 /* ---- measurement helpers ------------------------------------------------------------ */
 

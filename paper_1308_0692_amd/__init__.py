@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (BOTTOM, LEFT, RIGHT, TOP, FdlbError, check, desc_from_case, make_desc,
                    quad_full_range, quad_half_range, tile_count, tile_describe)
 
-__all__ = ["Problem", "Batch", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
+__all__ = ["Problem", "Batch", "Mlp", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
            "RIGHT", "tile_count", "tile_describe", "stream_copy"]
 
 
@@ -161,6 +161,18 @@ class Problem:
         check(_lib.lib.fdlb_wall_profile(self._h, int(wall), *[_lib._dp(a) for a in out]))
         return tuple(out)
 
+    def field_samples(self):
+        """(inputs, targets) of the warm-start network from the current state: device float32
+        tensors of shape (ny * nx, 3) each (fdlb_field_samples)."""
+        torch = _torch()
+        n = self.nx * self.ny
+        a = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+        t = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+        self._stream.wait_stream(torch.cuda.current_stream(self.device))
+        check(_lib.lib.fdlb_field_samples(self._h, C.c_void_p(a.data_ptr()), C.c_void_p(t.data_ptr())))
+        torch.cuda.current_stream(self.device).wait_stream(self._stream)
+        return a, t
+
     # -- precision ----------------------------------------------------------------------
     @property
     def active_precision(self) -> str:
@@ -276,6 +288,19 @@ class Batch:
         check(_lib.lib.fdlb_batch_state_download(self._h, int(i), _lib._dp(f)))
         return f
 
+    def field_samples(self, i: int, out_in=None, out_target=None):
+        """Warm-start samples of instance i (see Problem.field_samples); optionally into given
+        contiguous float32 device tensors of shape (ny * nx, 3)."""
+        torch = _torch()
+        nx, ny = self.shapes[i]
+        a = out_in if out_in is not None else torch.empty((nx * ny, 3), dtype=torch.float32, device=self.device)
+        t = out_target if out_target is not None else torch.empty_like(a)
+        assert a.is_contiguous() and t.is_contiguous() and a.numel() == t.numel() == 3 * nx * ny
+        self._stream.wait_stream(torch.cuda.current_stream(self.device))
+        check(_lib.lib.fdlb_batch_field_samples(self._h, int(i), C.c_void_p(a.data_ptr()), C.c_void_p(t.data_ptr())))
+        torch.cuda.current_stream(self.device).wait_stream(self._stream)
+        return a, t
+
     def active_precision(self, i: int) -> str:
         return _lib.PRECISION_NAMES[check(_lib.lib.fdlb_batch_active_precision(self._h, int(i)), allow=(0, 1))]
 
@@ -295,6 +320,103 @@ class Batch:
         if getattr(self, "_h", None):
             self._stream.synchronize()
             _lib.lib.fdlb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The warm-start network (fdlb_mlp_*): parameters, gradient and Adam moments in device
+    float32 tensors owned here, all arithmetic in the library's kernels."""
+
+    def __init__(self, hidden: int = 4, max_batch: int = 8192, seed: int = 0, device="cuda:0", stream=None,
+                 params=None):
+        torch = _torch()
+        h = C.c_void_p()
+        check(_lib.lib.fdlb_mlp_create(int(hidden), int(max_batch), C.byref(h)))
+        self._h = h
+        self.hidden, self.max_batch, self.device = hidden, max_batch, device
+        self.param_count = int(_lib.lib.fdlb_mlp_param_count(h))
+        if params is None:
+            host = np.empty(self.param_count, dtype=np.float32)
+            check(_lib.lib.fdlb_mlp_init_params(h, C.c_uint64(seed),
+                                                host.ctypes.data_as(C.POINTER(C.c_float))))
+            params = host
+        self.params = torch.as_tensor(np.asarray(params, dtype=np.float32)).to(device).contiguous()
+        assert self.params.numel() == self.param_count
+        self.grad = torch.zeros_like(self.params)
+        self.adam_m = torch.zeros_like(self.params)
+        self.adam_v = torch.zeros_like(self.params)
+        self._work_t, self._work = _alloc(_lib.lib.fdlb_mlp_workspace_bytes(h), device)
+        self._stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        torch.cuda.current_stream(device).synchronize()   # parameter upload and zeroed moments
+        check(_lib.lib.fdlb_mlp_bind(h, *[C.c_void_p(t.data_ptr()) for t in
+                                          (self.params, self.grad, self.adam_m, self.adam_v)],
+                                     C.c_void_p(self._work), C.c_void_p(self._stream.cuda_stream)))
+        self.step_count = 0
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def _enter(self, *tensors):
+        torch = _torch()
+        for t in tensors:
+            if t is not None:
+                assert t.is_cuda and t.is_contiguous() and t.dtype in (torch.float32, torch.int32)
+        self._stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch = _torch()
+        torch.cuda.current_stream(self.device).wait_stream(self._stream)
+
+    def forward(self, x):
+        torch = _torch()
+        self._enter(x)
+        y = torch.empty((x.shape[0], 3), dtype=torch.float32, device=self.device)
+        check(_lib.lib.fdlb_mlp_forward(self._h, C.c_void_p(x.data_ptr()), int(x.shape[0]), C.c_void_p(y.data_ptr())))
+        self._leave()
+        return y
+
+    def backward(self, x, t, rows=None, n: Optional[int] = None):
+        """Gradient of the mean squared error into self.grad (asynchronous).  rows: optional
+        int32 device tensor selecting the samples (n of them, default all rows)."""
+        self._enter(x, t, rows)
+        n = int(n if n is not None else (rows.numel() if rows is not None else x.shape[0]))
+        rp = C.c_void_p(rows.data_ptr()) if rows is not None else None
+        check(_lib.lib.fdlb_mlp_backward(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), rp, n))
+        self._leave()
+
+    def last_loss(self) -> float:
+        v = C.c_double()
+        check(_lib.lib.fdlb_mlp_last_loss(self._h, C.byref(v)))
+        return v.value
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self._enter()
+        self.step_count += 1
+        check(_lib.lib.fdlb_mlp_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps),
+                                          int(self.step_count)))
+        self._leave()
+
+    def predict_fields(self, kn: float, nx: int, ny: int, u_w: float):
+        """Device float32 (rho, ux, uy), each of shape (ny, nx)."""
+        torch = _torch()
+        out = [torch.empty((ny, nx), dtype=torch.float32, device=self.device) for _ in range(3)]
+        self._enter()
+        check(_lib.lib.fdlb_mlp_predict_fields(self._h, float(kn), int(nx), int(ny), float(u_w),
+                                               *[C.c_void_p(o.data_ptr()) for o in out]))
+        self._leave()
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._stream.synchronize()
+            _lib.lib.fdlb_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -108,6 +108,19 @@ def _load():
         "fdlb_batch_get_tile": (C.c_int, [vp]),
         "fdlb_batch_autotune": (C.c_int, [vp, C.c_int, dp]),
         "fdlb_batch_active_precision": (C.c_int, [vp, C.c_int]),
+        "fdlb_mlp_create": (C.c_int, [C.c_int, i64, C.POINTER(vp)]),
+        "fdlb_mlp_destroy": (None, [vp]),
+        "fdlb_mlp_param_count": (i64, [vp]),
+        "fdlb_mlp_workspace_bytes": (C.c_size_t, [vp]),
+        "fdlb_mlp_init_params": (C.c_int, [vp, C.c_uint64, fp]),
+        "fdlb_mlp_bind": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "fdlb_mlp_forward": (C.c_int, [vp, vp, i64, vp]),
+        "fdlb_mlp_backward": (C.c_int, [vp, vp, vp, vp, i64]),
+        "fdlb_mlp_last_loss": (C.c_int, [vp, dp]),
+        "fdlb_mlp_adam_step": (C.c_int, [vp, C.c_double, C.c_double, C.c_double, C.c_double, i64]),
+        "fdlb_mlp_predict_fields": (C.c_int, [vp, C.c_double, C.c_int, C.c_int, C.c_double, vp, vp, vp]),
+        "fdlb_field_samples": (C.c_int, [vp, vp, vp]),
+        "fdlb_batch_field_samples": (C.c_int, [vp, C.c_int, vp, vp]),
         "fdlb_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

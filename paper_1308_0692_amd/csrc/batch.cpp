@@ -22,6 +22,7 @@
 
 namespace fdlb {
 void promote(fdlb_problem& p);
+void field_samples(fdlb_problem& p, float* in, float* target);
 void build_problem(fdlb_problem& p, const fdlb_problem_desc& d);
 void bind(fdlb_problem& p, void* d_state, void* d_work, void* stream);
 void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, const double* uy, int renorm);
@@ -495,7 +496,7 @@ double batch_autotune(fdlb_batch& b, int steps) {
 
 // ---- C ABI -------------------------------------------------------------------------------
 namespace fdlb {
-int guard_batch(const std::function<int()>& f);
+int guard_call(const std::function<int()>& f);
 }
 
 using namespace fdlb;
@@ -503,7 +504,7 @@ using namespace fdlb;
 extern "C" {
 
 int fdlb_batch_create(const fdlb_problem_desc* descs, int n, fdlb_batch** out) {
-    return guard_batch([&] {
+    return guard_call([&] {
         if (!out) throw Error(FDLB_EINVAL, "NULL output handle");
         *out = nullptr;
         auto b = std::make_unique<fdlb_batch>();
@@ -524,7 +525,7 @@ static fdlb_batch& bh(fdlb_batch* b) {
 }
 
 int fdlb_batch_bind(fdlb_batch* b, void* d_state, void* d_workspace, void* stream) {
-    return guard_batch([&] {
+    return guard_call([&] {
         batch_bind(bh(b), d_state, d_workspace, stream);
         return FDLB_OK;
     });
@@ -532,7 +533,7 @@ int fdlb_batch_bind(fdlb_batch* b, void* d_state, void* d_workspace, void* strea
 
 int fdlb_batch_init_equilibrium(fdlb_batch* b, int i, const double* rho, const double* ux, const double* uy,
                                 int renormalize_mass) {
-    return guard_batch([&] {
+    return guard_call([&] {
         batch_init_equilibrium(bh(b), i, rho, ux, uy, renormalize_mass);
         return FDLB_OK;
     });
@@ -540,7 +541,7 @@ int fdlb_batch_init_equilibrium(fdlb_batch* b, int i, const double* rho, const d
 
 int fdlb_batch_init_equilibrium_dev(fdlb_batch* b, int i, const float* d_rho, const float* d_ux, const float* d_uy,
                                     int renormalize_mass) {
-    return guard_batch([&] {
+    return guard_call([&] {
         batch_init_equilibrium_dev(bh(b), i, d_rho, d_ux, d_uy, renormalize_mass);
         return FDLB_OK;
     });
@@ -548,25 +549,32 @@ int fdlb_batch_init_equilibrium_dev(fdlb_batch* b, int i, const float* d_rho, co
 
 int fdlb_batch_solve(fdlb_batch* b, double tol, int64_t max_steps, int32_t check_every, int32_t use_graph,
                      fdlb_report* reports) {
-    return guard_batch([&] { return batch_solve(bh(b), tol, max_steps, check_every, use_graph, reports); });
+    return guard_call([&] { return batch_solve(bh(b), tol, max_steps, check_every, use_graph, reports); });
 }
 
 int fdlb_batch_moments(fdlb_batch* b, int i, double* rho, double* ux, double* uy, double* pxy) {
-    return guard_batch([&] {
+    return guard_call([&] {
         batch_moments(bh(b), i, rho, ux, uy, pxy);
         return FDLB_OK;
     });
 }
 
 int fdlb_batch_state_download(fdlb_batch* b, int i, double* f_host) {
-    return guard_batch([&] {
+    return guard_call([&] {
         batch_state_download(bh(b), i, f_host);
         return FDLB_OK;
     });
 }
 
+int fdlb_batch_field_samples(fdlb_batch* b, int i, float* d_in, float* d_target) {
+    return guard_call([&] {
+        field_samples(inst(bh(b), i), d_in, d_target);
+        return FDLB_OK;
+    });
+}
+
 int fdlb_batch_set_tile(fdlb_batch* b, int tile) {
-    return guard_batch([&] {
+    return guard_call([&] {
         batch_set_tile(bh(b), tile);
         return FDLB_OK;
     });
@@ -580,7 +588,7 @@ int fdlb_batch_active_precision(const fdlb_batch* b, int i) {
 }
 
 int fdlb_batch_autotune(fdlb_batch* b, int steps, double* best_ms_per_step) {
-    return guard_batch([&] {
+    return guard_call([&] {
         const double ms = batch_autotune(bh(b), steps);
         if (best_ms_per_step) *best_ms_per_step = ms;
         return FDLB_OK;

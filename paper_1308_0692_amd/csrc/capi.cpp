@@ -28,6 +28,7 @@ void wall_profile(fdlb_problem& p, int wall, double* rho, double* ut, double* px
 void set_tile(fdlb_problem& p, int tile);
 double autotune(fdlb_problem& p, int steps);
 void promote(fdlb_problem& p);
+void field_samples(fdlb_problem& p, float* in, float* target);
 
 static thread_local std::string g_last_error;
 
@@ -55,7 +56,7 @@ static int guard(F&& f) {
     }
 }
 
-int guard_batch(const std::function<int()>& f) { return guard(f); }
+int guard_call(const std::function<int()>& f) { return guard(f); }
 
 static fdlb_problem& handle(fdlb_problem* p) {
     if (!p) throw Error(FDLB_EINVAL, "NULL problem handle");
@@ -256,6 +257,13 @@ int fdlb_autotune(fdlb_problem* p, int steps, double* best_ms_per_step) {
     return guard([&] {
         const double ms = autotune(handle(p), steps);
         if (best_ms_per_step) *best_ms_per_step = ms;
+        return FDLB_OK;
+    });
+}
+
+int fdlb_field_samples(fdlb_problem* p, float* d_in, float* d_target) {
+    return guard([&] {
+        field_samples(handle(p), d_in, d_target);
         return FDLB_OK;
     });
 }

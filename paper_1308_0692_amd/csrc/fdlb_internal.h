@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <map>
 #include <tuple>
@@ -149,6 +150,45 @@ void launch_from_raw(const double* f, const double* w_nat, int a0, int a1, int64
 void launch_mass_scale(const float* frho, int64_t cells, double* scale_out, hipStream_t stream);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 void launch_widen(const float* src, double* dst, int64_t n, hipStream_t stream);
+
+// Warm-start network (mlp.hip / mlp.cpp).
+constexpr int MLP_WIDTH = 128;     // hidden width (the matrix-core tiles assume it)
+constexpr int MLP_TILE = 64;       // samples per block
+constexpr int MLP_MAX_HIDDEN = 8;  // hidden layers
+
+struct MlpArgs {
+    const float* params;        // flat: W_0, b_0, ..., W_L, b_L (W row-major by output)
+    const uint16_t* wbf;        // bf16 hidden-to-hidden weights [hidden-1][128][128], [o][i]
+    const uint16_t* wbfT;       // same, transposed, [i][o]
+    const float* in;            // [.][3] encoded inputs (unless cells_nx > 0)
+    const int32_t* rows;        // optional: sample g reads row rows[g] of in and target
+    const float* target;        // [.][3]
+    float* out;                 // [n][3] outputs (sample order)
+    float* act;                 // [hidden][n_cap][128] fp32 activations (training)
+    float* partial;             // [blocks][P] per-block gradients
+    double* loss_part;          // [blocks] per-block squared errors
+    float *f_rho, *f_ux, *f_uy; // field outputs: rho = 1 + u_w y0, u = u_w (y1, y2)
+    int64_t n, n_cap;
+    int32_t hidden, P;
+    int32_t off_w[MLP_MAX_HIDDEN + 1], off_b[MLP_MAX_HIDDEN + 1];
+    int32_t cells_nx, cells_ny; // > 0: inputs are the cells of this grid
+    float kn_feat;              // encoded log10 Kn for cell inputs
+    float u_w;
+    float inv_3n;               // 1 / (3 n)
+    int32_t pad;
+};
+
+void launch_mlp_weights_bf16(const MlpArgs& a, uint16_t* wbf, uint16_t* wbfT, hipStream_t s);
+void launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s);
+void launch_mlp_backward(const MlpArgs& a, hipStream_t s);
+void launch_mlp_reduce(const float* partial, int nblocks, int P, float* grad, const double* loss_part, double inv_3n,
+                       double* loss, hipStream_t s);
+void launch_mlp_adam(float* p, const float* g, float* m, float* v, int P, float lr, float b1, float b2, float eps,
+                     float c1, float c2, hipStream_t s);
+void launch_field_samples(const double* post, int nx, int ny, float kn_feat, double inv_uw, float* in, float* target,
+                          hipStream_t s);
+// Encoded Knudsen-number input of the network: (log10 Kn + 0.5) / 1.5 maps [0.01, 10] to [-1, 1].
+inline float mlp_kn_feature(double kn) { return (float)((std::log10(kn) + 0.5) / 1.5); }
 
 // Control block layout (doubles) written by the reduce kernel.
 enum CtrlSlot {

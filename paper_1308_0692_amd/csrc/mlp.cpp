@@ -1,0 +1,264 @@
+// Host runtime of the warm-start network: layout of the parameter vector and the workspace,
+// parameter initialisation, and the training / inference entry points of include/fdlb.h.
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+
+#include "fdlb_internal.h"
+
+struct fdlb_mlp {
+    int hidden = 4;
+    int P = 0;
+    int64_t max_batch = 0;
+    int nblk = 0;  // blocks of a full training batch
+    int32_t off_w[fdlb::MLP_MAX_HIDDEN + 1]{}, off_b[fdlb::MLP_MAX_HIDDEN + 1]{};
+    size_t off_wbf = 0, off_wbfT = 0, off_act = 0, off_out = 0, off_part = 0, off_lossp = 0, off_loss = 0;
+    size_t work_bytes = 0;
+    float *params = nullptr, *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+    char* work = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    bool have_loss = false;
+    double* pinned = nullptr;
+    ~fdlb_mlp() {
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+namespace fdlb {
+int guard_call(const std::function<int()>& f);
+
+namespace {
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+fdlb_mlp& mh(fdlb_mlp* m) {
+    if (!m) throw Error(FDLB_EINVAL, "NULL network handle");
+    return *m;
+}
+void require_bound(const fdlb_mlp& m) {
+    if (!m.bound) throw Error(FDLB_ESTATE, "network is not bound to device memory (call fdlb_mlp_bind)");
+}
+
+MlpArgs base_args(fdlb_mlp& m) {
+    MlpArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.params = m.params;
+    a.wbf = (const uint16_t*)(m.work + m.off_wbf);
+    a.wbfT = (const uint16_t*)(m.work + m.off_wbfT);
+    a.hidden = m.hidden;
+    a.P = m.P;
+    for (int l = 0; l <= m.hidden; ++l) {
+        a.off_w[l] = m.off_w[l];
+        a.off_b[l] = m.off_b[l];
+    }
+    return a;
+}
+
+// Refresh the bf16 copies of the hidden weights from the current parameters.
+void refresh_bf16(fdlb_mlp& m, const MlpArgs& a) {
+    launch_mlp_weights_bf16(a, (uint16_t*)(m.work + m.off_wbf), (uint16_t*)(m.work + m.off_wbfT), m.stream);
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): a counter-based 64-bit generator.
+uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+}  // namespace
+
+void mlp_create(fdlb_mlp& m, int hidden, int64_t max_batch) {
+    if (hidden < 1 || hidden > MLP_MAX_HIDDEN) throw Error(FDLB_EINVAL, "hidden layers must be 1..8");
+    if (max_batch < 1 || max_batch > ((int64_t)1 << 22)) throw Error(FDLB_EINVAL, "max_batch must be 1..2^22");
+    m.hidden = hidden;
+    m.max_batch = max_batch;
+    int k = 0;
+    for (int l = 0; l <= hidden; ++l) {
+        const int out = l == hidden ? 3 : MLP_WIDTH;
+        const int in = l == 0 ? 3 : MLP_WIDTH;
+        m.off_w[l] = k;
+        k += out * in;
+        m.off_b[l] = k;
+        k += out;
+    }
+    m.P = k;
+    m.nblk = (int)((max_batch + MLP_TILE - 1) / MLP_TILE);
+    const size_t wsz = (size_t)(hidden - 1) * MLP_WIDTH * MLP_WIDTH * sizeof(uint16_t);
+    size_t off = 0;
+    m.off_wbf = off;
+    off += align256(wsz);
+    m.off_wbfT = off;
+    off += align256(wsz);
+    m.off_act = off;
+    off += align256((size_t)hidden * max_batch * MLP_WIDTH * sizeof(float));
+    m.off_out = off;
+    off += align256((size_t)max_batch * 3 * sizeof(float));
+    m.off_part = off;
+    off += align256((size_t)m.nblk * m.P * sizeof(float));
+    m.off_lossp = off;
+    off += align256((size_t)m.nblk * sizeof(double));
+    m.off_loss = off;
+    off += 256;
+    m.work_bytes = off;
+}
+
+}  // namespace fdlb
+
+using namespace fdlb;
+
+extern "C" {
+
+int fdlb_mlp_create(int hidden_layers, int64_t max_batch, fdlb_mlp** out) {
+    return guard_call([&] {
+        if (!out) throw Error(FDLB_EINVAL, "NULL output handle");
+        *out = nullptr;
+        auto m = std::make_unique<fdlb_mlp>();
+        mlp_create(*m, hidden_layers, max_batch);
+        *out = m.release();
+        return FDLB_OK;
+    });
+}
+
+void fdlb_mlp_destroy(fdlb_mlp* m) { delete m; }
+
+int64_t fdlb_mlp_param_count(const fdlb_mlp* m) { return m ? m->P : FDLB_EINVAL; }
+size_t fdlb_mlp_workspace_bytes(const fdlb_mlp* m) { return m ? m->work_bytes : 0; }
+
+int fdlb_mlp_init_params(const fdlb_mlp* m, uint64_t seed, float* host_params) {
+    return guard_call([&] {
+        if (!m || !host_params) throw Error(FDLB_EINVAL, "NULL argument");
+        uint64_t ctr = seed * 0x100000001b3ull;
+        for (int l = 0; l <= m->hidden; ++l) {
+            const int out = l == m->hidden ? 3 : MLP_WIDTH;
+            const int in = l == 0 ? 3 : MLP_WIDTH;
+            const double lim = std::sqrt(6.0 / (in + out));
+            for (int e = 0; e < out * in; ++e) {
+                const double u = (double)(splitmix64(ctr++) >> 11) * 0x1.0p-53;
+                host_params[m->off_w[l] + e] = (float)(lim * (2.0 * u - 1.0));
+            }
+            for (int e = 0; e < out; ++e) host_params[m->off_b[l] + e] = 0.0f;
+        }
+        return FDLB_OK;
+    });
+}
+
+int fdlb_mlp_bind(fdlb_mlp* m, float* d_params, float* d_grad, float* d_adam_m, float* d_adam_v, void* d_workspace,
+                  void* stream) {
+    return guard_call([&] {
+        fdlb_mlp& M = mh(m);
+        if (!d_params || !d_grad || !d_adam_m || !d_adam_v || !d_workspace)
+            throw Error(FDLB_EINVAL, "device buffers must not be NULL");
+        if ((uintptr_t)d_workspace & 255) throw Error(FDLB_EINVAL, "workspace must be 256-byte aligned");
+        if (((uintptr_t)d_params | (uintptr_t)d_grad | (uintptr_t)d_adam_m | (uintptr_t)d_adam_v) & 3)
+            throw Error(FDLB_EINVAL, "parameter buffers must be 4-byte aligned");
+        M.params = d_params;
+        M.grad = d_grad;
+        M.adam_m = d_adam_m;
+        M.adam_v = d_adam_v;
+        M.work = (char*)d_workspace;
+        M.stream = (hipStream_t)stream;
+        if (!M.pinned) FDLB_HIP(hipHostMalloc((void**)&M.pinned, 8 * sizeof(double), hipHostMallocDefault));
+        M.bound = true;
+        M.have_loss = false;
+        return FDLB_OK;
+    });
+}
+
+int fdlb_mlp_forward(fdlb_mlp* m, const float* d_in, int64_t n, float* d_out) {
+    return guard_call([&] {
+        fdlb_mlp& M = mh(m);
+        require_bound(M);
+        if (n < 0) throw Error(FDLB_EINVAL, "n must be >= 0");
+        if (n > 0 && (!d_in || !d_out)) throw Error(FDLB_EINVAL, "NULL input or output");
+        MlpArgs a = base_args(M);
+        a.in = d_in;
+        a.out = d_out;
+        a.n = n;
+        refresh_bf16(M, a);
+        launch_mlp_forward(a, false, M.stream);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_mlp_backward(fdlb_mlp* m, const float* d_in, const float* d_target, const int32_t* d_rows, int64_t n) {
+    return guard_call([&] {
+        fdlb_mlp& M = mh(m);
+        require_bound(M);
+        if (n < 1 || n > M.max_batch) throw Error(FDLB_EINVAL, "n must be 1..max_batch");
+        if (!d_in || !d_target) throw Error(FDLB_EINVAL, "NULL input or target");
+        MlpArgs a = base_args(M);
+        a.in = d_in;
+        a.target = d_target;
+        a.rows = d_rows;
+        a.n = n;
+        a.n_cap = M.max_batch;
+        a.out = (float*)(M.work + M.off_out);
+        a.act = (float*)(M.work + M.off_act);
+        a.partial = (float*)(M.work + M.off_part);
+        a.loss_part = (double*)(M.work + M.off_lossp);
+        a.inv_3n = (float)(1.0 / (3.0 * (double)n));
+        refresh_bf16(M, a);
+        launch_mlp_forward(a, true, M.stream);
+        launch_mlp_backward(a, M.stream);
+        const int nb = (int)((n + MLP_TILE - 1) / MLP_TILE);
+        launch_mlp_reduce(a.partial, nb, M.P, M.grad, a.loss_part, 1.0 / (3.0 * (double)n),
+                          (double*)(M.work + M.off_loss), M.stream);
+        M.have_loss = true;
+        return FDLB_OK;
+    });
+}
+
+int fdlb_mlp_last_loss(fdlb_mlp* m, double* loss) {
+    return guard_call([&] {
+        fdlb_mlp& M = mh(m);
+        require_bound(M);
+        if (!loss) throw Error(FDLB_EINVAL, "NULL output");
+        if (!M.have_loss) throw Error(FDLB_ESTATE, "no backward pass since binding");
+        FDLB_HIP(hipMemcpyAsync(M.pinned, M.work + M.off_loss, sizeof(double), hipMemcpyDeviceToHost, M.stream));
+        FDLB_HIP(hipStreamSynchronize(M.stream));
+        *loss = M.pinned[0];
+        return FDLB_OK;
+    });
+}
+
+int fdlb_mlp_adam_step(fdlb_mlp* m, double lr, double beta1, double beta2, double eps, int64_t step) {
+    return guard_call([&] {
+        fdlb_mlp& M = mh(m);
+        require_bound(M);
+        if (step < 1) throw Error(FDLB_EINVAL, "step counts from 1");
+        if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+            throw Error(FDLB_EINVAL, "bad Adam hyper-parameters");
+        const double c1 = 1.0 / (1.0 - std::pow(beta1, (double)step));
+        const double c2 = 1.0 / (1.0 - std::pow(beta2, (double)step));
+        launch_mlp_adam(M.params, M.grad, M.adam_m, M.adam_v, M.P, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                        (float)c1, (float)c2, M.stream);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_mlp_predict_fields(fdlb_mlp* m, double kn, int nx, int ny, double u_w, float* d_rho, float* d_ux,
+                            float* d_uy) {
+    return guard_call([&] {
+        fdlb_mlp& M = mh(m);
+        require_bound(M);
+        if (!(kn > 0) || !std::isfinite(kn)) throw Error(FDLB_EINVAL, "kn must be positive and finite");
+        if (nx < 1 || ny < 1) throw Error(FDLB_EINVAL, "nx and ny must be >= 1");
+        if (!d_rho || !d_ux || !d_uy) throw Error(FDLB_EINVAL, "NULL output field");
+        MlpArgs a = base_args(M);
+        a.n = (int64_t)nx * ny;
+        a.cells_nx = nx;
+        a.cells_ny = ny;
+        a.kn_feat = mlp_kn_feature(kn);
+        a.u_w = (float)u_w;
+        a.f_rho = d_rho;
+        a.f_ux = d_ux;
+        a.f_uy = d_uy;
+        refresh_bf16(M, a);
+        launch_mlp_forward(a, false, M.stream);
+        return FDLB_OK;
+    });
+}
+
+}  // extern "C"

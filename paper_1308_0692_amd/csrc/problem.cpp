@@ -746,6 +746,24 @@ void wall_profile(fdlb_problem& p, int wall, double* rho, double* ut, double* px
     FDLB_HIP(hipStreamSynchronize(p.stream));
 }
 
+// Training samples of the warm-start network from the current state: per cell the encoded
+// input (Kn, x, y) and the fields scaled by the fastest wall speed.  Asynchronous.
+void field_samples(fdlb_problem& p, float* in, float* target) {
+    require_seeded(p);
+    if (!in || !target) throw Error(FDLB_EINVAL, "NULL output array");
+    if (!std::isfinite(p.d.kn)) throw Error(FDLB_EINVAL, "samples need a finite Kn");
+    double uw = 0;
+    for (int w = 0; w < 4; ++w)
+        if (p.wall[w].active) uw = std::max(uw, std::fabs(p.wall[w].u));
+    if (!(uw > 0)) throw Error(FDLB_EINVAL, "samples need a moving wall (the fields are scaled by its speed)");
+    if (p.prec == FDLB_FP32)
+        launch_post<float>((const float*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, p.omega, io(p), p.stream);
+    else
+        launch_post<double>((const double*)pop_buf(p, p.parity), vel64(p), p.q, p.d.nx, p.d.ny, p.omega, io(p),
+                            p.stream);
+    launch_field_samples(io(p), p.d.nx, p.d.ny, mlp_kn_feature(p.d.kn), 1.0 / uw, in, target, p.stream);
+}
+
 // ---------------------------------------------------------------------------
 // Tiles.
 // ---------------------------------------------------------------------------

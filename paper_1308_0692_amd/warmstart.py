@@ -1,0 +1,100 @@
+"""Learned warm start of steady solves (fdlb_mlp_* and fdlb_field_samples).
+
+The solver generates its own training data: a batch of cavities with Knudsen numbers
+spread over the range of interest is solved to the tolerance, and every cell of every
+solution becomes a sample (inputs: encoded log10 Kn and cell centre; targets: the fields
+scaled by the lid speed).  The network is trained with Adam on shuffled minibatches.  A new
+problem is then seeded at equilibrium with the predicted fields (mass renormalised) and
+solved as usual: the solver decides convergence, the network only moves the start.
+
+Marshalling only: solves, sample extraction, forward, backward and Adam run in the
+library's kernels; numpy draws the shuffling permutations.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Iterable, Optional
+
+import numpy as np
+
+from . import Batch, Mlp, Problem, _lib
+
+
+def cavity_desc(n: int, kn: float, u_w: float = 0.01, order: int = 4, precision: str = "mixed",
+                cfl: float = 0.9) -> _lib.ProblemDesc:
+    """Lid-driven square cavity: lid (top wall) moving at +u_w, the other walls at rest."""
+    return _lib.make_desc(n, n, False, False, (0.0, u_w, 0.0, 0.0), kn, ("half", order), ("half", order), cfl,
+                          precision)
+
+
+def generate(kns: Iterable[float], n: int = 64, order: int = 4, u_w: float = 0.01, tol: float = 1e-8,
+             precision: str = "mixed", check_every: int = 200, max_steps: int = 400000, device="cuda:0"):
+    """Solve one cavity per Kn (as one batch) and return (inputs, targets, reports): device
+    float32 tensors of shape (len(kns) n^2, 3) and the per-instance solve reports."""
+    import torch
+    kns = [float(k) for k in kns]
+    descs = [cavity_desc(n, kn, u_w, order, precision) for kn in kns]
+    b = Batch(None, descs=descs, device=device)
+    for i in range(len(kns)):
+        b.init_equilibrium(i)
+    t0 = time.perf_counter()
+    status, reps = b.solve(tol, max_steps, check_every=check_every)
+    wall = time.perf_counter() - t0
+    cells = n * n
+    X = torch.empty((len(kns) * cells, 3), dtype=torch.float32, device=device)
+    T = torch.empty_like(X)
+    for i in range(len(kns)):
+        b.field_samples(i, X[i * cells:(i + 1) * cells], T[i * cells:(i + 1) * cells])
+    torch.cuda.synchronize(device)
+    b.close()
+    return X, T, {"status": status, "wall_s": wall, "reports": reps}
+
+
+def train(net: Mlp, X, T, epochs: int, batch: int, lr: float = 3e-3, lr_final: float = 1e-5, seed: int = 0,
+          log=None):
+    """Adam on shuffled minibatches with a cosine decay of the learning rate from lr to lr_final.
+    Returns the last minibatch loss of every epoch."""
+    import torch
+    N = X.shape[0]
+    if batch > net.max_batch:
+        raise ValueError("batch exceeds the network's max_batch")
+    rng = np.random.default_rng(seed)
+    steps = epochs * math.ceil(N / batch)
+    s = 0
+    losses = []
+    for e in range(epochs):
+        perm = torch.as_tensor(rng.permutation(N).astype(np.int32)).to(X.device)
+        for k in range(0, N, batch):
+            rows = perm[k:k + batch]
+            net.backward(X, T, rows=rows)
+            frac = s / max(1, steps - 1)
+            net.adam_step(lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * frac)))
+            s += 1
+        losses.append(net.last_loss())
+        if log and (e % max(1, epochs // 10) == 0 or e == epochs - 1):
+            log(f"epoch {e}: minibatch loss {losses[-1]:.3e}")
+    return losses
+
+
+def evaluate(net: Mlp, X, T) -> float:
+    """Mean squared error over all samples (in chunks of the network's max_batch)."""
+    N = X.shape[0]
+    tot = 0.0
+    for k in range(0, N, net.max_batch):
+        m = min(net.max_batch, N - k)
+        net.backward(X[k:k + m], T[k:k + m])
+        tot += net.last_loss() * m
+    return tot / N
+
+
+def seed(p: Problem, net: Mlp, kn: float, u_w: float):
+    """Seed problem p at equilibrium with the predicted fields (mass renormalised)."""
+    rho, ux, uy = net.predict_fields(kn, p.nx, p.ny, u_w)
+    p.init_equilibrium_dev(rho, ux, uy, renormalize=True)
+
+
+def seed_batch(b: Batch, i: int, net: Mlp, kn: float, u_w: float):
+    nx, ny = b.shapes[i]
+    rho, ux, uy = net.predict_fields(kn, nx, ny, u_w)
+    b.init_equilibrium_dev(i, rho, ux, uy, renormalize=True)

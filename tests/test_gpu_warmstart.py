@@ -1,0 +1,73 @@
+"""The learned warm start end to end: the solver generates its training data, the network
+is trained by the library's kernels, and on held-out Knudsen numbers (and a finer grid than
+the training one) the warm-started solve reaches the tolerance in fewer steps than the
+uniform start, and to the same answer: the oracle's converged solution within the FP32 bar
+(2e-5 on rho and u)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.scheme import Problem as OP
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1308_0692_amd as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def trained(F):
+    from paper_1308_0692_amd import warmstart
+    train_kn = W.c5_training_kn(32, seed=77)
+    X, T, info = warmstart.generate(train_kn, n=32, order=2, tol=1e-8)
+    assert info["status"] == 0
+    net = F.Mlp(seed=1, max_batch=4096)
+    e0 = warmstart.evaluate(net, X, T)
+    warmstart.train(net, X, T, epochs=250, batch=2048, lr=3e-3, seed=2)
+    e1 = warmstart.evaluate(net, X, T)
+    print(f"training loss {e0:.3e} -> {e1:.3e}")
+    assert e1 < 1e-2 * e0
+    return net, train_kn
+
+
+def eps_u(ux, uy, uxr, uyr):
+    return float(np.hypot(ux - uxr, uy - uyr).max() / np.hypot(uxr, uyr).max())
+
+
+def test_warm_start_saves_steps_on_held_out_kn(F, trained):
+    from paper_1308_0692_amd import warmstart
+    net, train_kn = trained
+    held = W.c5_heldout_kn(3, seed=78, training=train_kn)
+    for kn in held:
+        case = W.cavity(48, kn=float(kn), u_w=0.01, order=2)
+        p = F.Problem(case, precision="fp64")
+        p.init_equilibrium()
+        cold = p.solve(1e-8, 400000, check_every=10)
+        warmstart.seed(p, net, float(kn), 0.01)
+        warm = p.solve(1e-8, 400000, check_every=10)
+        assert cold["status"] == 0 and warm["status"] == 0
+        print(f"Kn {kn:.4f}: uniform start {cold['steps']} steps, warm start {warm['steps']} steps")
+        assert warm["steps"] < cold["steps"], (kn, cold["steps"], warm["steps"])
+        if kn > 0.05:   # the oracle's converged reference stays affordable
+            rho, ux, uy, _ = p.moments()
+            op = OP.from_case(case)
+            fo, _, hist = op.solve(op.equilibrium(), 1e-10, 400000)
+            r0, ux0, uy0 = op.moments(fo)
+            assert eps_u(ux, uy, ux0, uy0) <= 2e-5
+            assert float(np.abs(rho - r0).max()) <= 2e-5
+
+
+def test_warm_start_keeps_the_mass(F, trained):
+    from paper_1308_0692_amd import warmstart
+    net, _ = trained
+    case = W.cavity(40, kn=0.5, u_w=0.01, order=2)
+    p = F.Problem(case, precision="mixed")
+    warmstart.seed(p, net, 0.5, 0.01)
+    rho, _, _, _ = p.moments()
+    assert abs(rho.sum() - 40 * 40) <= 1e-7 * 40 * 40
