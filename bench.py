@@ -13,9 +13,12 @@ peak using its algorithmic bytes (every population read once and written once,
 plus the per-cell moments) and its own average duration from HIP events on the
 library's stream.  Extra fields: the time to residual 1e-8 of the 128 x 128
 cavity in FP32, mixed precision and plain FP64; the Couette time to 1e-10 in
-FP64; the 64-cavity sweep (Kn log-uniform in [0.01, 10], N in {64..192}, 8^2 or
-12^2 velocities) solved to 1e-8 as one mixed-precision batch versus plain FP64
-single-instance solves of the same cases; and the measured copy bandwidth.
+FP64; the learned warm start (trained on 2000 solver-generated 64^2 cavities,
+then warm versus uniform starts on held-out Kn at 128^2 and 256^2); the
+64-cavity sweep (Kn log-uniform in [0.01, 10], N in {64..192}, 8^2 or 12^2
+velocities) solved to 1e-8 as one mixed-precision batch, from uniform and from
+warm starts, versus plain FP64 single-instance solves of the same cases; and
+the measured copy bandwidth.
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload.
 """
@@ -96,11 +99,12 @@ def time_to_residual(F, W):
     return out
 
 
-def sweep_c3(F, W, torch):
+def sweep_c3(F, W, torch, net=None):
     """The 64-cavity sweep to R < 1e-8: one mixed-precision batch (autotuned float tile,
     graph-captured chunks) against plain FP64 single-instance solves of the same cases (each
     with its graph captured beforehand, outside the timing).  Error of every batch member
-    against its FP64 solution, at the same tolerance."""
+    against its FP64 solution, at the same tolerance.  With a trained warm-start network the
+    batch is solved a second time from the network's seeds (seeding inside the timing)."""
     cases = W.c3_instances()
     solo_wall, solo_steps, ref = 0.0, [], []
     for c in cases:
@@ -118,28 +122,35 @@ def sweep_c3(F, W, torch):
     log(f"  plain FP64, one instance at a time: {solo_wall:.2f} s, {sum(solo_steps)} steps")
     b = F.Batch(cases, precision="mixed")
     ms = b.autotune(steps=3)
-    for i in range(len(cases)):
-        b.init_equilibrium(i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    status, reps = b.solve(1e-8, 200000, check_every=200)
-    wall = time.perf_counter() - t0
-    eu, er = 0.0, 0.0
-    for i in range(len(cases)):
-        rho, ux, uy, _ = b.moments(i)
-        eu = max(eu, eps_u(ux, uy, ref[i][1], ref[i][2]))
-        er = max(er, float(abs(rho - ref[i][0]).max()))
-    steps = [r["steps"] for r in reps]
-    f32 = [r["steps_fp32"] for r in reps]
-    log(f"  mixed batch: {wall:.2f} s (status {status}), {sum(steps)} steps of which {sum(f32)} in float; "
-        f"max eps_u vs FP64 {eu:.2e}")
     out = {"instances": len(cases), "tol": 1e-8,
-           "plain_fp64_solo": {"wall_s": round(solo_wall, 3), "steps": sum(solo_steps)},
-           "mixed_batch": {"wall_s": round(wall, 3), "status": status, "steps": sum(steps),
-                           "steps_fp32": sum(f32), "converged": sum(r["status"] == 0 for r in reps),
-                           "tile": F.tile_describe("fp32", b.tile), "autotune_ms_per_step": round(ms, 4),
-                           "max_eps_u_vs_fp64": eu, "max_eps_rho_vs_fp64": er},
-           "speedup_vs_plain_fp64": round(solo_wall / wall, 3)}
+           "plain_fp64_solo": {"wall_s": round(solo_wall, 3), "steps": sum(solo_steps)}}
+    for key in ("mixed_batch", "mixed_batch_warm"):
+        if key == "mixed_batch_warm" and net is None:
+            break
+        from paper_1308_0692_amd import warmstart
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, c in enumerate(cases):
+            if key == "mixed_batch":
+                b.init_equilibrium(i)
+            else:
+                warmstart.seed_batch(b, i, net, c.kn, c.wall_u[1])
+        status, reps = b.solve(1e-8, 200000, check_every=200)
+        wall = time.perf_counter() - t0
+        eu, er = 0.0, 0.0
+        for i in range(len(cases)):
+            rho, ux, uy, _ = b.moments(i)
+            eu = max(eu, eps_u(ux, uy, ref[i][1], ref[i][2]))
+            er = max(er, float(abs(rho - ref[i][0]).max()))
+        steps = [r["steps"] for r in reps]
+        f32 = [r["steps_fp32"] for r in reps]
+        log(f"  {key}: {wall:.2f} s (status {status}), {sum(steps)} steps of which {sum(f32)} in float; "
+            f"max eps_u vs FP64 {eu:.2e}")
+        out[key] = {"wall_s": round(wall, 3), "status": status, "steps": sum(steps),
+                    "steps_fp32": sum(f32), "converged": sum(r["status"] == 0 for r in reps),
+                    "tile": F.tile_describe("fp32", b.tile), "autotune_ms_per_step": round(ms, 4),
+                    "max_eps_u_vs_fp64": eu, "max_eps_rho_vs_fp64": er,
+                    "speedup_vs_plain_fp64": round(solo_wall / wall, 3)}
     b.close()
     return out
 
@@ -189,6 +200,11 @@ def main():
     ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-cavity batch versus plain FP64 runs")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip training the warm-start network on 2000 solver-generated 64^2 cavities, the warm "
+                         "versus uniform starts on held-out Kn at 128^2 and 256^2, and the warm-started sweep")
+    ap.add_argument("--heldout", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU, "
@@ -254,9 +270,18 @@ def main():
         log("[bench] time to residual:")
         extra["time_to_residual"] = time_to_residual(F, W)
     p.close()
+    net = None
+    if not args.no_warm_start:
+        from paper_1308_0692_amd import warmstart
+        log("[bench] learned warm start:")
+        train_kn = W.c5_training_kn()
+        res = warmstart.experiment(train_kn, W.c5_heldout_kn(args.heldout, training=train_kn),
+                                   epochs=args.epochs, log=lambda m: log(m))
+        net = res.pop("net")
+        extra["warm_start"] = res
     if not args.no_sweep:
         log("[bench] 64-cavity sweep to 1e-8:")
-        extra["sweep64"] = sweep_c3(F, W, torch)
+        extra["sweep64"] = sweep_c3(F, W, torch, net)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -98,3 +98,76 @@ def seed_batch(b: Batch, i: int, net: Mlp, kn: float, u_w: float):
     nx, ny = b.shapes[i]
     rho, ux, uy = net.predict_fields(kn, nx, ny, u_w)
     b.init_equilibrium_dev(i, rho, ux, uy, renormalize=True)
+
+
+def _eps(a, b):
+    """(eps_u, eps_rho) of fields a = (rho, ux, uy) against b."""
+    eu = float(np.hypot(a[1] - b[1], a[2] - b[2]).max() / np.hypot(b[1], b[2]).max())
+    return eu, float(np.abs(a[0] - b[0]).max())
+
+
+def experiment(train_kn, heldout_kn, train_n: int = 64, order: int = 4, u_w: float = 0.01, grids=(128, 256),
+               epochs: int = 20, batch: int = 8192, lr: float = 3e-3, tol: float = 1e-8, precision: str = "mixed",
+               ref_tol: float = 1e-11, seed_value: int = 0, log=print):
+    """Train on solver-generated cavities, then compare warm and uniform starts on held-out Kn.
+
+    For every held-out Kn and grid: steps and wall time to `tol` from the uniform start and
+    from the network's seed (prediction and seeding included in the warm wall time), and the
+    error of both final states against an FP64 solve of the same problem to `ref_tol`."""
+    import torch
+    out = {"train_count": len(train_kn), "train_n": train_n, "order": order, "epochs": epochs, "batch": batch}
+    t0 = time.perf_counter()
+    X, T, info = generate(train_kn, n=train_n, order=order, u_w=u_w, tol=tol, precision=precision)
+    out["generate_s"] = round(time.perf_counter() - t0, 3)
+    out["generate_solve_s"] = round(info["wall_s"], 3)
+    out["samples"] = int(X.shape[0])
+    log(f"  generated {X.shape[0]} samples from {len(train_kn)} solves in {out['generate_s']:.1f} s")
+    net = Mlp(hidden=4, max_batch=batch, seed=seed_value)
+    t0 = time.perf_counter()
+    losses = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed_value, log=log)
+    torch.cuda.synchronize()
+    out["train_s"] = round(time.perf_counter() - t0, 3)
+    out["train_steps"] = epochs * math.ceil(X.shape[0] / batch)
+    out["final_loss"] = evaluate(net, X, T)
+    log(f"  trained {out['train_steps']} Adam steps in {out['train_s']:.1f} s; loss {out['final_loss']:.3e}")
+    del X, T
+    rows = []
+    for n in grids:
+        for kn in heldout_kn:
+            kn = float(kn)
+            p = Problem(desc=cavity_desc(n, kn, u_w, order, precision))
+            p.init_equilibrium()
+            p.solve(tol, 400, check_every=200)  # graph capture outside the timing
+            p.init_equilibrium()
+            cold = p.solve(tol, 2000000, check_every=200)
+            cold_f = p.moments()[:3]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            seed(p, net, kn, u_w)
+            warm = p.solve(tol, 2000000, check_every=200)
+            warm_wall = time.perf_counter() - t0
+            warm_f = p.moments()[:3]
+            p.close()
+            r = Problem(desc=cavity_desc(n, kn, u_w, order, "fp64"))
+            r.init_equilibrium()
+            ref = r.solve(ref_tol, 4000000, check_every=500)
+            ref_f = r.moments()[:3]
+            r.close()
+            ec, ew = _eps(cold_f, ref_f), _eps(warm_f, ref_f)
+            row = {"n": n, "kn": kn, "cold_steps": cold["steps"], "warm_steps": warm["steps"],
+                   "cold_s": round(cold["wall_s"], 4), "warm_s": round(warm_wall, 4),
+                   "cold_eps_u": ec[0], "warm_eps_u": ew[0], "cold_eps_rho": ec[1], "warm_eps_rho": ew[1],
+                   "ref_status": ref["status"], "status": [cold["status"], warm["status"]]}
+            rows.append(row)
+            log(f"  {n}^2 Kn {kn:.4f}: uniform {cold['steps']} steps {cold['wall_s']:.3f} s, warm {warm['steps']} "
+                f"steps {warm_wall:.3f} s; eps_u vs FP64 {ec[0]:.1e} / {ew[0]:.1e}")
+    out["heldout"] = rows
+    for n in grids:
+        sel = [r for r in rows if r["n"] == n]
+        out[f"grid{n}"] = {"cold_steps": sum(r["cold_steps"] for r in sel), "warm_steps": sum(r["warm_steps"] for r in sel),
+                           "cold_s": round(sum(r["cold_s"] for r in sel), 3),
+                           "warm_s": round(sum(r["warm_s"] for r in sel), 3),
+                           "max_warm_eps_u": max(r["warm_eps_u"] for r in sel),
+                           "max_cold_eps_u": max(r["cold_eps_u"] for r in sel)}
+    out["net"] = net
+    return out
