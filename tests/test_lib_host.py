@@ -129,3 +129,62 @@ def test_tiles_listed_and_heuristic_fits(F):
         for prec in ("fp32", "fp64"):
             p = F.Problem(case, precision=prec, bind=False)
             assert 0 <= p.tile < F.tile_count(prec)
+
+
+def test_mixed_precision_problem_sizes(F):
+    """A mixed-precision problem is sized for double and starts in float (host only)."""
+    case = W.cavity(48, kn=0.2, order=2)
+    m = F.Problem(case, precision="mixed", bind=False)
+    d = F.Problem(case, precision="fp64", bind=False)
+    s = F.Problem(case, precision="fp32", bind=False)
+    assert m.state_bytes == d.state_bytes == 2 * s.state_bytes
+    assert F._lib.lib.fdlb_problem_active_precision(m._h) == F._lib.FP32
+    assert F._lib.lib.fdlb_problem_active_precision(d._h) == F._lib.FP64
+    # switching needs a bound, seeded state
+    assert F._lib.lib.fdlb_promote(m._h) == F._lib.ESTATE
+    assert F._lib.lib.fdlb_promote(s._h) == F._lib.ESTATE
+
+
+def _mlp(F, hidden=4, max_batch=512):
+    h = C.c_void_p()
+    assert F._lib.lib.fdlb_mlp_create(hidden, max_batch, C.byref(h)) == 0
+    return h
+
+
+def test_network_layout_and_initialisation(F):
+    """Parameter count and layout of the warm-start network, Glorot bounds, zero biases and a
+    deterministic stream per seed (host only)."""
+    from oracle import mlp
+    lib = F._lib.lib
+    for hidden in (1, 2, 4, 8):
+        h = _mlp(F, hidden)
+        P = lib.fdlb_mlp_param_count(h)
+        assert P == mlp.param_count(128, hidden)
+        p1 = np.empty(P, dtype=np.float32)
+        p2 = np.empty(P, dtype=np.float32)
+        p3 = np.empty(P, dtype=np.float32)
+        fp = C.POINTER(C.c_float)
+        assert lib.fdlb_mlp_init_params(h, 5, p1.ctypes.data_as(fp)) == 0
+        assert lib.fdlb_mlp_init_params(h, 5, p2.ctypes.data_as(fp)) == 0
+        assert lib.fdlb_mlp_init_params(h, 6, p3.ctypes.data_as(fp)) == 0
+        assert np.array_equal(p1, p2) and not np.array_equal(p1, p3)
+        for (Wm, b), (o, i) in zip(mlp.unpack(p1.astype(np.float64), 128, hidden), mlp.layer_shapes(128, hidden)):
+            lim = math.sqrt(6.0 / (o + i))
+            assert np.abs(Wm).max() <= lim and np.abs(Wm).max() > 0.9 * lim
+            assert abs(Wm.mean()) < 0.1 * lim
+            assert np.all(b == 0)
+        assert lib.fdlb_mlp_workspace_bytes(h) > 0
+        lib.fdlb_mlp_destroy(h)
+
+
+def test_network_argument_errors(F):
+    lib = F._lib.lib
+    h = C.c_void_p()
+    assert lib.fdlb_mlp_create(0, 512, C.byref(h)) == F._lib.EINVAL
+    assert lib.fdlb_mlp_create(9, 512, C.byref(h)) == F._lib.EINVAL
+    assert lib.fdlb_mlp_create(4, 0, C.byref(h)) == F._lib.EINVAL
+    h = _mlp(F)
+    assert lib.fdlb_mlp_forward(h, None, 0, None) == F._lib.ESTATE   # not bound
+    assert lib.fdlb_mlp_adam_step(h, 1e-3, 0.9, 0.999, 1e-8, 1) == F._lib.ESTATE
+    assert lib.fdlb_mlp_param_count(None) == F._lib.EINVAL
+    lib.fdlb_mlp_destroy(h)
