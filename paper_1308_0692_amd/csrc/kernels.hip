@@ -141,10 +141,19 @@ __device__ __forceinline__ double wave_max(double v) {
 // ---------------------------------------------------------------------------
 // The fused time step.
 // ---------------------------------------------------------------------------
+// A problem whose solve has converged or diverged stops being updated (its state stays at
+// the step that met the criterion), when the control block asks for it.
+__device__ __forceinline__ bool frozen(const double* __restrict__ ctrl) {
+    return ctrl[CTRL_FREEZE] != 0.0 && (ctrl[CTRL_FIRST_BELOW] >= 0.0 || ctrl[CTRL_DIVERGED] >= 0.0);
+}
+
 // A block is WX x WPB x WA waves: WX waves side by side along x, WPB stacked along y, each
-// replicated WA times along the velocity index (wave wa takes every WA-th velocity of each
-// quadrant; the partial moments are summed through LDS in a fixed order).  bid/nb: this
-// block's index among the blocks of its problem; part: where its residual partials go.
+// replicated WA times along the velocity index (the partial moments of the WA waves are summed
+// through LDS in a fixed order).  With WA a multiple of 4, wave wa takes the velocities of
+// quadrant wa mod 4 only, every (WA/4)-th one, so that a wave meets one quadrant's first-load
+// latency instead of four; otherwise it takes every WA-th velocity of each quadrant.
+// bid/nb: this block's index among the blocks of its problem; part: where its residual
+// partials go.
 template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT>
 __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, const int nb,
                                           double* __restrict__ part) {
@@ -192,6 +201,9 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
             for (int v = 0; v < VX; ++v) mr[r][v] = mx[r][v] = my[r][v] = T(0);
         }
     }
+    // Checked after the moment loads are issued, so that the control-block read overlaps them
+    // (the whole block takes the same branch: the control block is uniform).
+    if (frozen(A.ctrl)) return;
 
     // Wall emission parameters of this step (Eqs. 8-9): rho_w - 1 and u_w rho_w per wall face.
     const double omega = A.omega_d;
@@ -264,6 +276,10 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
     auto quadrant = [&](auto sxc, auto syc, const int qb, const int qe) {
         constexpr int SX = decltype(sxc)::value;
         constexpr int SY = decltype(syc)::value;
+        constexpr int QI = (SX < 0 ? 1 : 0) + (SY < 0 ? 2 : 0);  // quadrant order of the table
+        constexpr bool QSPLIT = WA % 4 == 0;
+        constexpr int SW = QSPLIT ? WA / 4 : WA;  // stride between this wave's planes
+        if (QSPLIT && (wa & 3) != QI) return;
         // Where the lane-boundary cell's upwind neighbour comes from.
         int xmode, xh;
         if constexpr (SX > 0) {
@@ -343,8 +359,8 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
         // out of a buffer whose load is in flight would have to wait for it).
         constexpr int PD = FDLB_PREFETCH;
         static_assert(PD == 1 || PD == 2, "prefetch distance must be 1 or 2");
-        const int e0 = qb + wa;
-        const int elast = qe - 1 - ((qe - 1 - e0) % WA);  // last plane of this wave (if e0 < qe)
+        const int e0 = qb + (QSPLIT ? (wa >> 2) : wa);
+        const int elast = qe - 1 - ((qe - 1 - e0) % SW);  // last plane of this wave (if e0 < qe)
         auto clampe = [&](const int en) { return en <= elast ? en : elast; };
 
         auto step_one = [&](const int e, const T (&g)[K][VX], const T (&gxh_in)[K], const T (&gyh_in)[VX]) {
@@ -456,26 +472,26 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
             load_plane(e0, b0, b0x, b0y);
             if constexpr (PD == 1) {
                 for (int e = e0;;) {
-                    load_plane(clampe(e + WA), b1, b1x, b1y);
+                    load_plane(clampe(e + SW), b1, b1x, b1y);
                     step_one(e, b0, b0x, b0y);
-                    if ((e += WA) >= qe) break;
-                    load_plane(clampe(e + WA), b0, b0x, b0y);
+                    if ((e += SW) >= qe) break;
+                    load_plane(clampe(e + SW), b0, b0x, b0y);
                     step_one(e, b1, b1x, b1y);
-                    if ((e += WA) >= qe) break;
+                    if ((e += SW) >= qe) break;
                 }
             } else {
                 T b2[K][VX], b2x[K], b2y[VX];
-                load_plane(clampe(e0 + WA), b1, b1x, b1y);
+                load_plane(clampe(e0 + SW), b1, b1x, b1y);
                 for (int e = e0;;) {
-                    load_plane(clampe(e + 2 * WA), b2, b2x, b2y);
+                    load_plane(clampe(e + 2 * SW), b2, b2x, b2y);
                     step_one(e, b0, b0x, b0y);
-                    if ((e += WA) >= qe) break;
-                    load_plane(clampe(e + 2 * WA), b0, b0x, b0y);
+                    if ((e += SW) >= qe) break;
+                    load_plane(clampe(e + 2 * SW), b0, b0x, b0y);
                     step_one(e, b1, b1x, b1y);
-                    if ((e += WA) >= qe) break;
-                    load_plane(clampe(e + 2 * WA), b1, b1x, b1y);
+                    if ((e += SW) >= qe) break;
+                    load_plane(clampe(e + 2 * SW), b1, b1x, b1y);
                     step_one(e, b2, b2x, b2y);
-                    if ((e += WA) >= qe) break;
+                    if ((e += SW) >= qe) break;
                 }
             }
         }
@@ -604,15 +620,9 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
     }
 }
 
-// A problem whose solve has converged or diverged stops being updated (its state stays at
-// the step that met the criterion), when the control block asks for it.
-__device__ __forceinline__ bool frozen(const double* __restrict__ ctrl) {
-    return ctrl[CTRL_FREEZE] != 0.0 && (ctrl[CTRL_FIRST_BELOW] >= 0.0 || ctrl[CTRL_DIVERGED] >= 0.0);
-}
 
 template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT>
 __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR step_kernel(const StepArgs<T> A) {
-    if (frozen(A.ctrl)) return;
     step_body<T, VX, K, LX, WPB, WA, WX, NT>(A, blockIdx.x, gridDim.x, A.partials + 3 * blockIdx.x);
 }
 
@@ -624,7 +634,6 @@ __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR batch_step
     const BlockMap m = map[blockIdx.x];
     if (m.inst < 0) return;  // padding block
     const StepArgs<T> A = args[m.inst];
-    if (frozen(A.ctrl)) return;
     step_body<T, VX, K, LX, WPB, WA, WX, NT>(A, m.local, m.nb, A.partials + 3 * m.local);
 }
 
@@ -926,7 +935,10 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(17, float, 4, 2, 64, 1, 1, 4, 1) \
     X(18, float, 4, 1, 64, 1, 1, 4, 1) \
     X(19, float, 4, 2, 64, 2, 1, 2, 1) \
-    X(20, float, 4, 4, 64, 1, 1, 4, 1)
+    X(20, float, 4, 4, 64, 1, 1, 4, 1) \
+    X(21, float, 1, 1, 64, 1, 16, 1, 0) \
+    X(22, float, 1, 1, 32, 1, 8, 1, 0) \
+    X(23, float, 2, 1, 64, 1, 8, 1, 0)
 
 #define FDLB_TILES_FP64(X)          \
     X(0, double, 2, 2, 64, 4, 1, 1, 1)    \
@@ -942,7 +954,9 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(10, double, 1, 4, 1, 1, 4, 1, 0)    \
     X(11, double, 2, 1, 32, 1, 8, 1, 0) \
     X(12, double, 2, 2, 64, 1, 1, 4, 1) \
-    X(13, double, 2, 1, 64, 1, 1, 4, 1)
+    X(13, double, 2, 1, 64, 1, 1, 4, 1) \
+    X(14, double, 1, 1, 64, 1, 16, 1, 0) \
+    X(15, double, 1, 1, 32, 1, 8, 1, 0)
 
 const std::vector<TileShape>& tile_shapes(int precision) {
 #define FDLB_SHAPE(id, T, VX, K, LX, WPB, WA, WX, NT) TileShape{VX, LX, K, WPB, WA, WX, NT},

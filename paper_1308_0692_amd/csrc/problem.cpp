@@ -51,7 +51,8 @@ bool tile_fits(const TileShape& t, int nx, int ny, bool periodic_x, bool periodi
 
 // Built-in choice of tile shape (the autotuner measures instead).  Among the shapes that fit:
 // a grid with many cells (at least ~8 waves per CU without splitting the velocities) takes the
-// widest vectors and the least idle lanes; a small grid takes the shape with the most waves,
+// widest vectors and the least idle lanes; a small grid takes the shape with the most waves (up
+// to 8 per CU),
 // splitting the velocities over several waves per tile.
 int heuristic_tile_for(int precision, int nx, int ny, bool px, bool py) {
     const auto& shapes = tile_shapes(precision);
@@ -69,7 +70,7 @@ int heuristic_tile_for(int precision, int nx, int ny, bool px, bool py) {
         double score;
         if (small) {
             const double waves = (double)(tx * ty) * t.wpb * t.wa;
-            score = cover / std::min(waves, 8192.0);
+            score = cover / std::min(waves, 2048.0);  // more than 8 waves per CU measured no faster
         } else {
             score = cover * (4.0 / t.vx) * (t.k > 1 ? 1.0 : 1.02);
         }
