@@ -22,6 +22,7 @@
 
 namespace fdlb {
 void promote(fdlb_problem& p);
+double* partials_of(fdlb_problem& p, int parity);
 void field_samples(fdlb_problem& p, float* in, float* target);
 void build_problem(fdlb_problem& p, const fdlb_problem_desc& d);
 void bind(fdlb_problem& p, void* d_state, void* d_work, void* stream);
@@ -36,7 +37,7 @@ struct BatchGroup {
     bool used = false;
     int tile = -1;            // a shape of tile_shapes(prec)
     size_t off_map = 0;       // BlockMap[max_map]
-    size_t off_args = 0;      // StepArgs<T>[2][n]: every member, both parities
+    size_t off_args = 0;      // StepArgs<T>[2 parities][2 (reduces its predecessor)][n]
     int max_map = 0;
     int map_blocks = 0;
 };
@@ -47,7 +48,9 @@ struct fdlb_batch {
     BatchGroup grp[2];              // [0]: float kernels, [1]: double kernels
     std::vector<size_t> state_off, work_off;
     size_t state_bytes = 0, work_bytes = 0;
-    size_t off_rargs = 0;           // batch region inside the workspace arena
+    size_t off_rargs = 0;           // ReduceArgs[2 parities][2: per step, end of chunk][n]
+    bool step_reduce = false;       // some member reduces every step with a kernel of its own
+    bool end_reduce = false;        // some member reduces inline (closed at the end of a chunk)
     char* d_state = nullptr;
     char* d_work = nullptr;
     hipStream_t stream = nullptr;
@@ -125,17 +128,17 @@ void batch_create(fdlb_batch& b, const fdlb_problem_desc* descs, int n) {
         int maxmap = 0;
         for (const TileShape& t : tile_shapes(prec_of_group(g))) {
             int tot = 0;
-            for (auto& p : b.probs) tot += (nblocks_tile(*p, t) + 7) / 8 * 8;
+            for (auto& p : b.probs) tot += (nblocks_tile(*p, t) + 1 + 7) / 8 * 8;  // + reduction block
             maxmap = std::max(maxmap, tot);
         }
         G.max_map = maxmap;
         G.off_map = wo;
         wo += align256((size_t)maxmap * sizeof(BlockMap));
         G.off_args = wo;
-        wo += align256(2 * (size_t)n * (g == 0 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>)));
+        wo += align256(4 * (size_t)n * (g == 0 ? sizeof(StepArgs<float>) : sizeof(StepArgs<double>)));
     }
     b.off_rargs = wo;
-    wo += align256((size_t)n * sizeof(ReduceArgs));
+    wo += align256(4 * (size_t)n * sizeof(ReduceArgs));
     b.state_bytes = so;
     b.work_bytes = wo;
     // Default tiles: the built-in choice for the largest problem if it fits all, else any that does.
@@ -205,9 +208,10 @@ void batch_moments(fdlb_batch& b, int i, double* rho, double* ux, double* uy, do
 void batch_state_download(fdlb_batch& b, int i, double* f) { state_download(inst(b, i), f); }
 
 template <class T>
-static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile) {
+static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile, bool prev) {
     constexpr bool f32 = std::is_same<T, float>::value;
     const TileShape& t = tile_shapes(f32 ? FDLB_FP32 : FDLB_FP64)[tile];
+    const int nb = nblocks_tile(p, t);
     StepArgs<T> a;
     std::memset(&a, 0, sizeof(a));
     char* pop = p.d_state;
@@ -219,7 +223,9 @@ static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile) {
     a.mom_out = (double*)(mom + (size_t)(parity ^ 1) * p.mom_bytes);
     a.phi_in = (const double*)(phi + (size_t)parity * p.phi_bytes);
     a.phi_out = (double*)(phi + (size_t)(parity ^ 1) * p.phi_bytes);
-    a.partials = (double*)(p.d_work + p.off_part);
+    a.partials = partials_of(p, parity);
+    a.prev_partials = partials_of(p, parity ^ 1);
+    a.prev_nb = prev && nb <= INLINE_REDUCE_MAX_BLOCKS ? nb : 0;
     a.ctrl = ctrl_of(p);
     a.vel = (const VelEntry<T>*)(p.d_work + (f32 ? p.off_vel : p.off_vel64));
     for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
@@ -235,27 +241,39 @@ static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile) {
     return a;
 }
 
-// Reduce arguments: each member's partials are laid out by its group's tile.
+// Reduce arguments, by the parity of the step's source buffer: a member with few blocks is
+// reduced inline and closed at the end of a chunk (single-wave order), the others after every
+// step; each member's partials are laid out by its group's tile.
 static void upload_rargs(fdlb_batch& b) {
     const int n = (int)b.probs.size();
-    std::vector<ReduceArgs> ra(n);
-    for (int i = 0; i < n; ++i) {
-        fdlb_problem& p = *b.probs[i];
-        ra[i].partials = (const double*)(p.d_work + p.off_part);
-        ra[i].ctrl = ctrl_of(p);
-        ra[i].nb = member_blocks(b, p);
-        ra[i].pad = 0;
-    }
-    FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_rargs, ra.data(), n * sizeof(ReduceArgs), hipMemcpyHostToDevice, b.stream));
+    std::vector<ReduceArgs> ra(4 * (size_t)n);
+    b.step_reduce = b.end_reduce = false;
+    for (int par = 0; par < 2; ++par)
+        for (int kind = 0; kind < 2; ++kind)
+            for (int i = 0; i < n; ++i) {
+                fdlb_problem& p = *b.probs[i];
+                const int nb = member_blocks(b, p);
+                const bool inl = nb <= INLINE_REDUCE_MAX_BLOCKS;
+                ReduceArgs& r = ra[(size_t)(par * 2 + kind) * n + i];
+                r.partials = partials_of(p, par);
+                r.ctrl = ctrl_of(p);
+                r.nb = (kind == 1) == inl ? nb : 0;
+                r.wave_order = kind;
+                (inl ? b.end_reduce : b.step_reduce) = true;
+            }
+    FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_rargs, ra.data(), ra.size() * sizeof(ReduceArgs), hipMemcpyHostToDevice,
+                            b.stream));
     FDLB_HIP(hipStreamSynchronize(b.stream));
 }
 
 template <class T>
 static void upload_group_args(fdlb_batch& b, int g) {
     const int n = (int)b.probs.size();
-    std::vector<StepArgs<T>> a(2 * n);
+    std::vector<StepArgs<T>> a(4 * (size_t)n);
     for (int par = 0; par < 2; ++par)
-        for (int i = 0; i < n; ++i) a[par * n + i] = batch_step_args<T>(*b.probs[i], par, b.grp[g].tile);
+        for (int prev = 0; prev < 2; ++prev)
+            for (int i = 0; i < n; ++i)
+                a[(size_t)(par * 2 + prev) * n + i] = batch_step_args<T>(*b.probs[i], par, b.grp[g].tile, prev != 0);
     FDLB_HIP(hipMemcpyAsync(b.d_work + b.grp[g].off_args, a.data(), a.size() * sizeof(a[0]), hipMemcpyHostToDevice,
                             b.stream));
     FDLB_HIP(hipStreamSynchronize(b.stream));  // a is a host temporary
@@ -280,6 +298,8 @@ static void upload_map(fdlb_batch& b) {
             if (group_of(*b.probs[i]) != g) continue;
             const int nb = nblocks_tile(*b.probs[i], t);
             for (int l = 0; l < nb; ++l) m.push_back(BlockMap{i, l, nb, 0});
+            // a problem reduced inline gets its reduction block (local == nb)
+            if (nb <= INLINE_REDUCE_MAX_BLOCKS) m.push_back(BlockMap{i, nb, nb, 0});
             while (m.size() % 8) m.push_back(BlockMap{-1, 0, 0, 0});
         }
         G.map_blocks = (int)m.size();
@@ -292,26 +312,38 @@ static void upload_map(fdlb_batch& b) {
     ++b.map_version;
 }
 
-static void enqueue_batch_step(fdlb_batch& b, int parity) {
+// One batch step from source parity `parity`; prev: the members that reduce inline reduce
+// their previous step in this launch.
+static void enqueue_batch_step(fdlb_batch& b, int parity, bool prev) {
     const int n = (int)b.probs.size();
+    const size_t v = (size_t)(parity * 2 + (prev ? 1 : 0)) * n;
     for (int g = 0; g < 2; ++g) {
         const BatchGroup& G = b.grp[g];
         if (!G.used || G.map_blocks == 0) continue;
         const BlockMap* map = (const BlockMap*)(b.d_work + G.off_map);
         if (g == 0)
-            launch_batch_step<float>(G.tile, map, (const StepArgs<float>*)(b.d_work + G.off_args) + (size_t)parity * n,
-                                     G.map_blocks, b.stream);
+            launch_batch_step<float>(G.tile, map, (const StepArgs<float>*)(b.d_work + G.off_args) + v, G.map_blocks,
+                                     b.stream);
         else
-            launch_batch_step<double>(G.tile, map,
-                                      (const StepArgs<double>*)(b.d_work + G.off_args) + (size_t)parity * n,
+            launch_batch_step<double>(G.tile, map, (const StepArgs<double>*)(b.d_work + G.off_args) + v,
                                       G.map_blocks, b.stream);
     }
-    launch_batch_reduce((const ReduceArgs*)(b.d_work + b.off_rargs), n, b.stream);
+    if (b.step_reduce)
+        launch_batch_reduce((const ReduceArgs*)(b.d_work + b.off_rargs) + (size_t)(parity * 2) * n, n, b.stream);
+}
+
+static void enqueue_batch_steps(fdlb_batch& b, int k, int parity) {
+    const int n = (int)b.probs.size();
+    for (int i = 0; i < k; ++i) enqueue_batch_step(b, parity ^ (i & 1), i > 0);
+    if (k > 0 && b.end_reduce) {
+        const int last = parity ^ ((k - 1) & 1);
+        launch_batch_reduce((const ReduceArgs*)(b.d_work + b.off_rargs) + (size_t)(last * 2 + 1) * n, n, b.stream);
+    }
 }
 
 static void enqueue_batch_chunk(fdlb_batch& b, int k, int parity, bool graph) {
     if (!graph) {
-        for (int i = 0; i < k; ++i) enqueue_batch_step(b, parity ^ (i & 1));
+        enqueue_batch_steps(b, k, parity);
         return;
     }
     auto key = std::make_tuple(k, parity, b.map_version, b.grp[0].tile, b.grp[1].tile);
@@ -329,7 +361,7 @@ static void enqueue_batch_chunk(fdlb_batch& b, int k, int parity, bool graph) {
         hipGraph_t g;
         FDLB_HIP(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
         try {
-            for (int i = 0; i < k; ++i) enqueue_batch_step(b, parity ^ (i & 1));
+            enqueue_batch_steps(b, k, parity);
         } catch (...) {
             hipGraph_t dummy;
             (void)hipStreamEndCapture(b.stream, &dummy);

@@ -60,13 +60,14 @@ struct StepArgs {
     double* mom_out;      // same for dst
     const double* phi_in; // [4][L]: sum over arriving half of |xi_n| h at each wall cell of src
     double* phi_out;
-    double* partials;     // [nblocks][3]: sum |du|^2, sum |u|^2, max |u|^2
-    const double* ctrl;   // control block (freeze flags)
+    double* partials;     // [nblocks][3]: sum |du|^2, sum |u|^2, max |u|^2 of this step
+    const double* prev_partials;  // the previous step's, reduced here when prev_nb > 0
+    double* ctrl;         // control block (freeze flags; block 0 records the previous step)
     const VelEntry<T>* vel;
     int32_t quad_begin[5];
     int32_t nx, ny, L;
     int32_t tiles_x, tiles_y;
-    int32_t pad0;
+    int32_t prev_nb;      // blocks of the previous step whose partials are still unreduced, or 0
     int64_t plane;        // nx * ny
     T omega;              // dt / Kn in the storage type
     T pad1;
@@ -99,9 +100,14 @@ struct BlockMap {
 struct ReduceArgs {
     const double* partials;
     double* ctrl;
-    int32_t nb;     // <= 0: skip
-    int32_t pad;
+    int32_t nb;          // <= 0: skip
+    int32_t wave_order;  // 1: sum in the single-wave order of the inline reduction
 };
+
+// Residual partials of a launch with at most this many blocks are reduced inside the next step
+// kernel (every wave of it sums them in the same order) instead of by a kernel of their own;
+// one single-wave reduction closes every chunk of steps.
+constexpr int INLINE_REDUCE_MAX_BLOCKS = 1024;
 
 // When a FDLB_MIXED state leaves float during a steady solve: at a host check whose residual
 // is below FDLB_MIXED_SWITCH_R, or once the lowest residual seen has not dropped by 10 % for
@@ -123,6 +129,7 @@ bool tile_fits(const TileShape& t, int nx, int ny, bool periodic_x, bool periodi
 template <class T>
 void launch_step(int tile, const StepArgs<T>& a, int nblocks, hipStream_t stream);
 void launch_reduce(const double* partials, int nblocks, double* ctrl, int64_t inc, hipStream_t stream);
+void launch_reduce_wave(const double* partials, int nblocks, double* ctrl, hipStream_t stream);
 template <class T>
 void launch_batch_step(int tile, const BlockMap* map, const StepArgs<T>* args, int nblocks, hipStream_t stream);
 void launch_batch_reduce(const ReduceArgs* ra, int n, hipStream_t stream);

@@ -136,6 +136,23 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// The three residual sums of a step from its block partials, in one fixed order (lane l adds
+// blocks l, l + 64, ...; then an xor butterfly, whose pairwise sums are the same on both lanes
+// of a pair), so that every wave that calls it gets bit-identical totals.
+__device__ __forceinline__ void wave_partials(const double* __restrict__ pp, int nb, double& num, double& den,
+                                              double& umax2) {
+    const int lane = threadIdx.x & 63;
+    double a = 0.0, b = 0.0, m = 0.0;
+    for (int i = lane; i < nb; i += 64) {
+        a += pp[3 * i];
+        b += pp[3 * i + 1];
+        m = fmax(m, pp[3 * i + 2]);
+    }
+    num = wave_sum(a);
+    den = wave_sum(b);
+    umax2 = wave_max(m);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -146,6 +163,28 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ __forceinline__ bool frozen(const double* __restrict__ ctrl) {
     return ctrl[CTRL_FREEZE] != 0.0 && (ctrl[CTRL_FIRST_BELOW] >= 0.0 || ctrl[CTRL_DIVERGED] >= 0.0);
 }
+
+// Residual of a step from its sums: R = sqrt(sum |du|^2 / sum |u|^2).
+__device__ __forceinline__ double residual_of(double num, double den) {
+    if (den > 0.0) return sqrt(num / den);
+    return num > 0.0 ? __builtin_huge_val() : 0.0;
+}
+__device__ __forceinline__ bool runaway(double R, double umax2) { return !(R <= 1e300) || !(umax2 <= 0.25); }
+
+// Step bookkeeping in the control block (one thread): counter, residual, ring, first step
+// below the tolerance, first runaway step.
+__device__ __forceinline__ void record_step(double* __restrict__ ctrl, double num, double den, double umax2,
+                                            int64_t inc) {
+    const double R = residual_of(num, den);
+    const double step = ctrl[CTRL_STEP] + (double)inc;
+    ctrl[CTRL_STEP] = step;
+    ctrl[CTRL_LAST_R] = R;
+    ctrl[CTRL_MAXU] = sqrt(umax2);
+    ctrl[CTRL_RING + ((int64_t)step - 1) % CTRL_RING_LEN] = R;
+    if (R < ctrl[CTRL_TOL] && ctrl[CTRL_FIRST_BELOW] < 0.0) ctrl[CTRL_FIRST_BELOW] = step;
+    if (runaway(R, umax2) && ctrl[CTRL_DIVERGED] < 0.0) ctrl[CTRL_DIVERGED] = step;
+}
+
 
 // A block is WX x WPB x WA waves: WX waves side by side along x, WPB stacked along y, each
 // replicated WA times along the velocity index (the partial moments of the WA waves are summed
@@ -621,9 +660,27 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
 }
 
 
+// The reduction block of a launch that reduces its predecessor's residual partials inline: one
+// extra block, running beside the tiles, sums them (single-wave order) and records the previous
+// step.  Nothing waits for it inside the launch.  If that step met a steady solve's criterion,
+// the tiles of this launch still compute one more step into the other buffer, which is never
+// read: the state of the recorded step stays intact and every later launch is frozen.
+template <class T>
+__device__ __forceinline__ void reduce_previous(const StepArgs<T>& A) {
+    if (threadIdx.x >= 64 || frozen(A.ctrl)) return;
+    double num, den, um;
+    wave_partials(A.prev_partials, A.prev_nb, num, den, um);
+    if (threadIdx.x == 0) record_step(A.ctrl, num, den, um, 1);
+}
+
 template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT>
 __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR step_kernel(const StepArgs<T> A) {
-    step_body<T, VX, K, LX, WPB, WA, WX, NT>(A, blockIdx.x, gridDim.x, A.partials + 3 * blockIdx.x);
+    const int nb = (int)gridDim.x - (A.prev_nb > 0 ? 1 : 0);  // the last block reduces, if any
+    if ((int)blockIdx.x == nb) {
+        reduce_previous(A);
+        return;
+    }
+    step_body<T, VX, K, LX, WPB, WA, WX, NT>(A, blockIdx.x, nb, A.partials + 3 * blockIdx.x);
 }
 
 // Many problems in one launch: block g works on tile map[g].local of problem map[g].inst.
@@ -634,6 +691,10 @@ __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR batch_step
     const BlockMap m = map[blockIdx.x];
     if (m.inst < 0) return;  // padding block
     const StepArgs<T> A = args[m.inst];
+    if (m.local == m.nb) {  // the problem's reduction block
+        if (A.prev_nb > 0) reduce_previous(A);
+        return;
+    }
     step_body<T, VX, K, LX, WPB, WA, WX, NT>(A, m.local, m.nb, A.partials + 3 * m.local);
 }
 
@@ -661,20 +722,17 @@ __device__ __forceinline__ void reduce_body(const double* __restrict__ partials,
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double num = s[0][0], den = s[1][0], umax2 = s[2][0];
-        double R;
-        if (den > 0.0) R = sqrt(num / den);
-        else R = (num > 0.0) ? __builtin_huge_val() : 0.0;
-        const double step = ctrl[CTRL_STEP] + (double)inc;
-        ctrl[CTRL_STEP] = step;
-        ctrl[CTRL_LAST_R] = R;
-        ctrl[CTRL_MAXU] = sqrt(umax2);
-        ctrl[CTRL_RING + ((int64_t)step - 1) % CTRL_RING_LEN] = R;
-        if (R < ctrl[CTRL_TOL] && ctrl[CTRL_FIRST_BELOW] < 0.0) ctrl[CTRL_FIRST_BELOW] = step;
-        const bool bad = !(R <= 1e300) || !(umax2 <= 0.25);
-        if (bad && ctrl[CTRL_DIVERGED] < 0.0) ctrl[CTRL_DIVERGED] = step;
-    }
+    if (threadIdx.x == 0) record_step(ctrl, s[0][0], s[1][0], s[2][0], inc);
+}
+
+// The closing reduction of a chunk whose steps reduced their predecessors inline: the same
+// single-wave order, run by wave 0 of the block.
+__device__ __forceinline__ void reduce_wave_body(const double* __restrict__ partials, int nblocks,
+                                                 double* __restrict__ ctrl) {
+    if (threadIdx.x >= 64) return;
+    double num, den, um;
+    wave_partials(partials, nblocks, num, den, um);
+    if (threadIdx.x == 0) record_step(ctrl, num, den, um, 1);
 }
 
 __global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ partials, int nblocks,
@@ -683,11 +741,18 @@ __global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ 
     reduce_body(partials, nblocks, ctrl, inc);
 }
 
+__global__ void __launch_bounds__(64) reduce_wave_kernel(const double* __restrict__ partials, int nblocks,
+                                                         double* __restrict__ ctrl) {
+    if (frozen(ctrl)) return;
+    reduce_wave_body(partials, nblocks, ctrl);
+}
+
 // One block per problem of a batch.
 __global__ void __launch_bounds__(256) batch_reduce_kernel(const ReduceArgs* __restrict__ ra) {
     const ReduceArgs r = ra[blockIdx.x];
     if (r.nb <= 0 || frozen(r.ctrl)) return;
-    reduce_body(r.partials, r.nb, r.ctrl, 1);
+    if (r.wave_order) reduce_wave_body(r.partials, r.nb, r.ctrl);
+    else reduce_body(r.partials, r.nb, r.ctrl, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -936,9 +1001,8 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(18, float, 4, 1, 64, 1, 1, 4, 1) \
     X(19, float, 4, 2, 64, 2, 1, 2, 1) \
     X(20, float, 4, 4, 64, 1, 1, 4, 1) \
-    X(21, float, 1, 1, 64, 1, 16, 1, 0) \
-    X(22, float, 1, 1, 32, 1, 8, 1, 0) \
-    X(23, float, 2, 1, 64, 1, 8, 1, 0)
+    X(21, float, 1, 1, 32, 1, 8, 1, 0) \
+    X(22, float, 2, 1, 64, 1, 8, 1, 0)
 
 #define FDLB_TILES_FP64(X)          \
     X(0, double, 2, 2, 64, 4, 1, 1, 1)    \
@@ -955,8 +1019,7 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(11, double, 2, 1, 32, 1, 8, 1, 0) \
     X(12, double, 2, 2, 64, 1, 1, 4, 1) \
     X(13, double, 2, 1, 64, 1, 1, 4, 1) \
-    X(14, double, 1, 1, 64, 1, 16, 1, 0) \
-    X(15, double, 1, 1, 32, 1, 8, 1, 0)
+    X(14, double, 1, 1, 32, 1, 8, 1, 0)
 
 const std::vector<TileShape>& tile_shapes(int precision) {
 #define FDLB_SHAPE(id, T, VX, K, LX, WPB, WA, WX, NT) TileShape{VX, LX, K, WPB, WA, WX, NT},
@@ -1030,6 +1093,11 @@ void launch_batch_step<double>(int tile, const BlockMap* map, const StepArgs<dou
 
 void launch_batch_reduce(const ReduceArgs* ra, int n, hipStream_t stream) {
     hipLaunchKernelGGL(batch_reduce_kernel, dim3(n), dim3(256), 0, stream, ra);
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_reduce_wave(const double* partials, int nblocks, double* ctrl, hipStream_t stream) {
+    hipLaunchKernelGGL(reduce_wave_kernel, dim3(1), dim3(64), 0, stream, partials, nblocks, ctrl);
     FDLB_HIP(hipGetLastError());
 }
 

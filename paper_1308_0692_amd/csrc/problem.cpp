@@ -52,8 +52,7 @@ bool tile_fits(const TileShape& t, int nx, int ny, bool periodic_x, bool periodi
 // Built-in choice of tile shape (the autotuner measures instead).  Among the shapes that fit:
 // a grid with many cells (at least ~8 waves per CU without splitting the velocities) takes the
 // widest vectors and the least idle lanes; a small grid takes the shape with the most waves (up
-// to 8 per CU),
-// splitting the velocities over several waves per tile.
+// to 8 per CU), splitting the velocities over several waves per tile.
 int heuristic_tile_for(int precision, int nx, int ny, bool px, bool py) {
     const auto& shapes = tile_shapes(precision);
     const double cells = (double)nx * ny;
@@ -191,8 +190,8 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     p.phi_bytes = align256(4 * (size_t)p.L * sizeof(double));
     p.off_phi = off;
     off += 2 * p.phi_bytes;
-    p.off_part = off;
-    off += align256((size_t)maxb * 3 * sizeof(double));
+    p.off_part = off;  // residual partials, one region per buffer parity
+    off += 2 * align256((size_t)maxb * 3 * sizeof(double));
     p.off_ctrl = off;
     off += align256(CTRL_DOUBLES * sizeof(double));
     p.off_vel = off;
@@ -293,6 +292,11 @@ static double* phi_buf(fdlb_problem& p, int parity) {
     return (double*)(p.d_work + p.off_phi + (size_t)parity * p.phi_bytes);
 }
 static double* ctrl(fdlb_problem& p) { return (double*)(p.d_work + p.off_ctrl); }
+// Residual partials of the step that reads population buffer `parity`.
+double* partials_of(fdlb_problem& p, int parity) {
+    return (double*)(p.d_work + p.off_part + (size_t)parity * align256((size_t)p.max_blocks * 3 * sizeof(double)));
+}
+static double* part_buf(fdlb_problem& p, int parity) { return partials_of(p, parity); }
 static const VelEntry<double>* vel64(fdlb_problem& p) { return (const VelEntry<double>*)(p.d_work + p.off_vel64); }
 static double* io(fdlb_problem& p) { return (double*)(p.d_work + p.off_io); }
 
@@ -471,8 +475,11 @@ void checkpoint_load(fdlb_problem& p, const void* host) {
 // ---------------------------------------------------------------------------
 // Time marching.
 // ---------------------------------------------------------------------------
+static int nblocks_of(const fdlb_problem& p, int tile);
+
+// prev: this step reduces the previous step's residual partials inline.
 template <class T>
-static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile) {
+static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile, bool prev) {
     constexpr bool f32 = std::is_same<T, float>::value;
     const TileShape& t = tile_shapes(f32 ? FDLB_FP32 : FDLB_FP64)[tile];
     StepArgs<T> a;
@@ -483,7 +490,9 @@ static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile) {
     a.mom_out = (double*)mom_buf(p, parity ^ 1);
     a.phi_in = phi_buf(p, parity);
     a.phi_out = phi_buf(p, parity ^ 1);
-    a.partials = (double*)(p.d_work + p.off_part);
+    a.partials = part_buf(p, parity);
+    a.prev_partials = part_buf(p, parity ^ 1);
+    a.prev_nb = prev ? nblocks_of(p, tile) : 0;
     a.ctrl = ctrl(p);
     a.vel = (const VelEntry<T>*)(p.d_work + (f32 ? p.off_vel : p.off_vel64));
     for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
@@ -504,21 +513,35 @@ static int nblocks_of(const fdlb_problem& p, int tile) {
     return ((p.d.nx + t.tile_w() - 1) / t.tile_w()) * ((p.d.ny + t.tile_h() - 1) / t.tile_h());
 }
 
-// Enqueue one step (fused step kernel + residual reduction) from buffer `parity`.
-static void enqueue_step(fdlb_problem& p, int parity, int tile) {
-    const int nb = nblocks_of(p, tile);
+static bool inline_reduce(const fdlb_problem& p, int tile) { return nblocks_of(p, tile) <= INLINE_REDUCE_MAX_BLOCKS; }
+
+// prev: the launch also reduces the previous step's partials, in one extra block.
+static void launch_step_of(fdlb_problem& p, int parity, int tile, bool prev) {
+    const int nb = nblocks_of(p, tile) + (prev ? 1 : 0);
     if (p.prec == FDLB_FP32)
-        launch_step<float>(tile, step_args<float>(p, parity, tile), nb, p.stream);
+        launch_step<float>(tile, step_args<float>(p, parity, tile, prev), nb, p.stream);
     else
-        launch_step<double>(tile, step_args<double>(p, parity, tile), nb, p.stream);
-    launch_reduce((const double*)(p.d_work + p.off_part), nb, ctrl(p), 1, p.stream);
+        launch_step<double>(tile, step_args<double>(p, parity, tile, prev), nb, p.stream);
+}
+
+// Enqueue k steps from buffer `parity`: fused step kernels, and either a reduction kernel per
+// step (large grids) or inline reductions closed by one single-wave reduction (small grids).
+// Every chunk ends with its last step recorded, so the host may read the control block.
+static void enqueue_chunk(fdlb_problem& p, int parity, int tile, int64_t k) {
+    const int nb = nblocks_of(p, tile);
+    const bool inl = inline_reduce(p, tile);
+    int par = parity;
+    for (int64_t i = 0; i < k; ++i) {
+        launch_step_of(p, par, tile, inl && i > 0);
+        if (!inl) launch_reduce(part_buf(p, par), nb, ctrl(p), 1, p.stream);
+        par ^= 1;
+    }
+    if (inl && k > 0) launch_reduce_wave(part_buf(p, par ^ 1), nb, ctrl(p), p.stream);
 }
 
 static void enqueue_steps(fdlb_problem& p, int64_t n) {
-    for (int64_t i = 0; i < n; ++i) {
-        enqueue_step(p, p.parity, p.tile);
-        p.parity ^= 1;
-    }
+    enqueue_chunk(p, p.parity, p.tile, n);
+    if (n & 1) p.parity ^= 1;
 }
 
 // Plain stepping never freezes: clear the flag a previous steady solve left set.
@@ -572,14 +595,13 @@ void step_timed(fdlb_problem& p, int64_t n, double* ms_step, double* ms_reduce) 
     try {
         for (auto& e : ev) FDLB_HIP(hipEventCreate(&e));
         const int nb = nblocks_of(p, p.tile);
+        const bool inl = inline_reduce(p, p.tile);
         FDLB_HIP(hipEventRecord(ev[0], p.stream));
-        for (int64_t i = 0; i < n; ++i) {
-            if (p.prec == FDLB_FP32)
-                launch_step<float>(p.tile, step_args<float>(p, p.parity, p.tile), nb, p.stream);
-            else
-                launch_step<double>(p.tile, step_args<double>(p, p.parity, p.tile), nb, p.stream);
+        for (int64_t i = 0; i < n; ++i) {  // every step closed by its own reduction kernel
+            launch_step_of(p, p.parity, p.tile, false);
             FDLB_HIP(hipEventRecord(ev[2 * i + 1], p.stream));
-            launch_reduce((const double*)(p.d_work + p.off_part), nb, ctrl(p), 1, p.stream);
+            if (inl) launch_reduce_wave(part_buf(p, p.parity), nb, ctrl(p), p.stream);
+            else launch_reduce(part_buf(p, p.parity), nb, ctrl(p), 1, p.stream);
             FDLB_HIP(hipEventRecord(ev[2 * i + 2], p.stream));
             p.parity ^= 1;
         }
@@ -608,12 +630,8 @@ static void enqueue_graph(fdlb_problem& p, int k) {
     if (it == p.graphs.end()) {
         hipGraph_t g;
         FDLB_HIP(hipStreamBeginCapture(p.stream, hipStreamCaptureModeThreadLocal));
-        int par = p.parity;
         try {
-            for (int i = 0; i < k; ++i) {
-                enqueue_step(p, par, p.tile);
-                par ^= 1;
-            }
+            enqueue_chunk(p, p.parity, p.tile, k);
         } catch (...) {
             hipGraph_t dummy;
             (void)hipStreamEndCapture(p.stream, &dummy);
