@@ -196,14 +196,19 @@ int fdlb_checkpoint_load(fdlb_problem *p, const void *host_buf);
 /*
  * Advance nsteps time steps (relaxation, wall emission, upwind transport,
  * moments and residual of every step), asynchronously on the bound stream.
+ * A launch of at most 1024 tiles (blocks) reduces each step's residual inside
+ * the next step's launch (one extra block) and once more at the end of the
+ * call; larger grids launch a reduction kernel after every step.  Either way
+ * the control block holds every step's residual when the call's work ends.
  */
 int fdlb_step(fdlb_problem *p, int64_t nsteps);
 
 /*
- * Advance nsteps steps exactly as fdlb_step does, with HIP events recorded on
- * the bound stream around every kernel launch; returns the summed device
- * time of the fused step kernels and of the residual-reduction kernels, in
- * milliseconds (either pointer may be NULL).  Synchronous.
+ * Advance nsteps steps as fdlb_step does (same states), but with a reduction
+ * kernel after every step and HIP events recorded on the bound stream around
+ * every kernel launch; returns the summed device time of the fused step
+ * kernels and of the residual-reduction kernels, in milliseconds (either
+ * pointer may be NULL).  Synchronous.
  */
 int fdlb_step_timed(fdlb_problem *p, int64_t nsteps, double *ms_step_kernels, double *ms_reduce_kernels);
 
@@ -320,7 +325,10 @@ int fdlb_batch_init_equilibrium_dev(fdlb_batch *b, int i, const float *d_rho, co
  * Instances retire individually: an instance stops being updated at the first
  * step below tol (or at divergence), on the device, and leaves the launch at
  * the next host check.  All active instances advance together: one step-kernel
- * launch and one reduction launch per time step for the whole batch; the host
+ * launch per time step for the whole batch (two while FDLB_MIXED instances run
+ * in both precisions), with each instance's residual reduced as for a single
+ * problem (inline for small instances, a shared reduction launch per step for
+ * large ones); the host
  * polls every check_every steps; use_graph replays check_every steps as one
  * captured graph.  All instances must have been initialised (and have taken
  * step counts of equal parity).  reports: caller array of n entries (may be

@@ -1,8 +1,9 @@
 // Batched steady solves: many independent problems (different Kn, grids and velocity sets,
-// one precision) advanced together, one step-kernel launch and one reduction launch per
-// time step for all of them.  In FDLB_MIXED each problem leaves float on its own; the batch
-// then launches the float members and the double members as two groups (two step launches,
-// one reduction).
+// one precision) advanced together, one step-kernel launch per time step for all of them.
+// Each problem's residual is reduced as for a single problem: by an extra block of the next
+// launch (small problems, closed by one reduction launch per chunk) or by a shared reduction
+// launch after every step (large problems).  In FDLB_MIXED each problem leaves float on its
+// own; the batch then launches the float members and the double members as two groups.
 //
 // Every problem keeps its own state, workspace and control block inside two caller-owned
 // arenas.  A block map assigns each block of the launch to (problem, tile); each problem's
@@ -51,6 +52,7 @@ struct fdlb_batch {
     size_t off_rargs = 0;           // ReduceArgs[2 parities][2: per step, end of chunk][n]
     bool step_reduce = false;       // some member reduces every step with a kernel of its own
     bool end_reduce = false;        // some member reduces inline (closed at the end of a chunk)
+    size_t off_ctrlptr = 0, off_ctrlbuf = 0;
     char* d_state = nullptr;
     char* d_work = nullptr;
     hipStream_t stream = nullptr;
@@ -139,6 +141,10 @@ void batch_create(fdlb_batch& b, const fdlb_problem_desc* descs, int n) {
     }
     b.off_rargs = wo;
     wo += align256(4 * (size_t)n * sizeof(ReduceArgs));
+    b.off_ctrlptr = wo;  // every member's control block, gathered for one host read per check
+    wo += align256((size_t)n * sizeof(double*));
+    b.off_ctrlbuf = wo;
+    wo += align256((size_t)n * 8 * sizeof(double));
     b.state_bytes = so;
     b.work_bytes = wo;
     // Default tiles: the built-in choice for the largest problem if it fits all, else any that does.
@@ -188,6 +194,13 @@ void batch_bind(fdlb_batch& b, void* d_state, void* d_work, void* stream) {
     for (size_t i = 0; i < b.probs.size(); ++i) bind(*b.probs[i], b.d_state + b.state_off[i], b.d_work + b.work_off[i], stream);
     if (!b.pinned)
         FDLB_HIP(hipHostMalloc((void**)&b.pinned, b.probs.size() * 8 * sizeof(double), hipHostMallocDefault));
+    {
+        std::vector<const double*> ptrs;
+        for (auto& p : b.probs) ptrs.push_back(ctrl_of(*p));
+        FDLB_HIP(hipMemcpyAsync(b.d_work + b.off_ctrlptr, ptrs.data(), ptrs.size() * sizeof(ptrs[0]),
+                                hipMemcpyHostToDevice, b.stream));
+        FDLB_HIP(hipStreamSynchronize(b.stream));  // ptrs is a host temporary
+    }
     b.bound = true;
 }
 
@@ -377,9 +390,11 @@ static void enqueue_batch_chunk(fdlb_batch& b, int k, int parity, bool graph) {
 }
 
 static void read_all_ctrl(fdlb_batch& b) {
-    for (size_t i = 0; i < b.probs.size(); ++i)
-        FDLB_HIP(hipMemcpyAsync(b.pinned + 8 * i, ctrl_of(*b.probs[i]), 8 * sizeof(double), hipMemcpyDeviceToHost,
-                                b.stream));
+    const int n = (int)b.probs.size();
+    launch_gather_ctrl((const double* const*)(b.d_work + b.off_ctrlptr), n, (double*)(b.d_work + b.off_ctrlbuf),
+                       b.stream);
+    FDLB_HIP(hipMemcpyAsync(b.pinned, b.d_work + b.off_ctrlbuf, (size_t)n * 8 * sizeof(double),
+                            hipMemcpyDeviceToHost, b.stream));
     FDLB_HIP(hipStreamSynchronize(b.stream));
 }
 

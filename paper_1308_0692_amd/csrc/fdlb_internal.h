@@ -157,6 +157,8 @@ void launch_from_raw(const double* f, const double* w_nat, int a0, int a1, int64
 void launch_mass_scale(const float* frho, int64_t cells, double* scale_out, hipStream_t stream);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 void launch_widen(const float* src, double* dst, int64_t n, hipStream_t stream);
+// out[8 i + j] = ptrs[i][j], j < 8: the first control doubles of n problems in one array.
+void launch_gather_ctrl(const double* const* ptrs, int n, double* out, hipStream_t stream);
 
 // Warm-start network (mlp.hip / mlp.cpp).
 constexpr int MLP_WIDTH = 128;     // hidden width (the matrix-core tiles assume it)

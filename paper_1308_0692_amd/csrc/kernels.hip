@@ -950,6 +950,12 @@ __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ sr
         dst[i] = (double)src[i];
 }
 
+__global__ void __launch_bounds__(256) gather_ctrl_kernel(const double* const* __restrict__ ptrs, int n,
+                                                          double* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < 8 * n) out[k] = ptrs[k / 8][k % 8];
+}
+
 // Streaming copy for the bandwidth ceiling: each thread keeps 8 x 16-byte loads in flight.
 constexpr int COPY_UNROLL = 8;
 typedef float copy_vec_t __attribute__((ext_vector_type(4)));
@@ -1002,7 +1008,10 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(19, float, 4, 2, 64, 2, 1, 2, 1) \
     X(20, float, 4, 4, 64, 1, 1, 4, 1) \
     X(21, float, 1, 1, 32, 1, 8, 1, 0) \
-    X(22, float, 2, 1, 64, 1, 8, 1, 0)
+    X(22, float, 2, 1, 64, 1, 8, 1, 0) \
+    X(23, float, 4, 2, 16, 1, 4, 1, 0) \
+    X(24, float, 2, 1, 32, 1, 4, 1, 0) \
+    X(25, float, 4, 2, 16, 1, 8, 1, 0)
 
 #define FDLB_TILES_FP64(X)          \
     X(0, double, 2, 2, 64, 4, 1, 1, 1)    \
@@ -1019,7 +1028,9 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(11, double, 2, 1, 32, 1, 8, 1, 0) \
     X(12, double, 2, 2, 64, 1, 1, 4, 1) \
     X(13, double, 2, 1, 64, 1, 1, 4, 1) \
-    X(14, double, 1, 1, 32, 1, 8, 1, 0)
+    X(14, double, 1, 1, 32, 1, 8, 1, 0) \
+    X(15, double, 2, 2, 16, 1, 4, 1, 0) \
+    X(16, double, 2, 1, 32, 1, 4, 1, 0)
 
 const std::vector<TileShape>& tile_shapes(int precision) {
 #define FDLB_SHAPE(id, T, VX, K, LX, WPB, WA, WX, NT) TileShape{VX, LX, K, WPB, WA, WX, NT},
@@ -1167,6 +1178,12 @@ void launch_widen(const float* src, double* dst, int64_t n, hipStream_t stream) 
     if (n <= 0) return;
     const int64_t blocks = std::min<int64_t>(16384, (n + 255) / 256);
     hipLaunchKernelGGL(widen_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, src, dst, n);
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_gather_ctrl(const double* const* ptrs, int n, double* out, hipStream_t stream) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(gather_ctrl_kernel, dim3((8 * n + 255) / 256), dim3(256), 0, stream, ptrs, n, out);
     FDLB_HIP(hipGetLastError());
 }
 
