@@ -157,3 +157,17 @@ def test_field_samples_of_a_solved_cavity(F):
     assert np.allclose(a[:, 0], (math.log10(0.3) + 0.5) / 1.5, rtol=1e-6)
     assert np.allclose(a[:, 1], np.tile(2 * (np.arange(24) + 0.5) / 24 - 1, 20), atol=1e-7)
     assert np.allclose(a[:, 2], np.repeat(2 * (np.arange(20) + 0.5) / 20 - 1, 24), atol=1e-7)
+
+
+def test_gradient_full_training_batch(F):
+    """A full training batch (8,192 samples, the size the warm-start training uses)."""
+    import torch
+    theta = f32(W.mlp_params(81))
+    a, t = W.mlp_samples(8192, 82)
+    a, t = f32(a), f32(t)
+    net = F.Mlp(params=theta, max_batch=8192)
+    net.backward(dev(torch, a), dev(torch, t))
+    g = net.grad.cpu().numpy().astype(np.float64)
+    Eb, gb = mlp.gradient(theta, a, t, bf16=True)
+    assert np.linalg.norm(g - gb) <= 2e-4 * np.linalg.norm(gb)
+    assert abs(net.last_loss() - Eb) <= 1e-4 * Eb
