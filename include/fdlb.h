@@ -106,6 +106,7 @@ int fdlb_quad_full_range(int n, double *nodes, double *weights);
 
 typedef struct fdlb_problem_desc {
     int32_t nx, ny;                 /* cells; >= 1 */
+    double lx, ly;                  /* domain lengths in units of the length l of Kn (0 means 1) */
     int32_t periodic_x, periodic_y; /* 1: periodic axis (then that N must be 1) */
     double wall_u[4];               /* tangential wall speeds (see conventions) */
     double kn;                      /* Knudsen number of Eq. (1); INFINITY allowed */
@@ -120,8 +121,8 @@ typedef struct fdlb_problem fdlb_problem; /* opaque host handle */
 
 /*
  * Validate a description and build the velocity set, the time step
- * dt = cfl / max_alpha(|xi_x| N_x [x bounded] + |xi_y| N_y [y bounded]) and
- * omega = dt / Kn (0 for Kn = INFINITY).  Host only (no GPU call); the
+ * dt = cfl / max_alpha(|xi_x| N_x / l_x [x bounded] + |xi_y| N_y / l_y [y bounded])
+ * and omega = dt / Kn (0 for Kn = INFINITY).  Cells are l_x / N_x by l_y / N_y.  Host only (no GPU call); the
  * handle owns only host memory.  FDLB_EINVAL for bad sizes or rules,
  * FDLB_EUNSTABLE if cfl > 1 or omega > 1 and allow_unstable is 0.
  */

@@ -71,7 +71,8 @@ def _dp(a: np.ndarray):
 
 @dataclass
 class Problem:
-    """A discretised boundary-value problem on the unit square."""
+    """A discretised boundary-value problem on an l_x x l_y rectangle (the unit square by
+    default; lengths in units of the length l that defines Kn)."""
 
     nx: int
     ny: int
@@ -84,15 +85,17 @@ class Problem:
     cfl: float = 0.9
     order: int = 0           # 0: relax then transport, 1: transport then relax
     dt_override: Optional[float] = None
+    lx: float = 1.0          # domain lengths in units of the length of Kn
+    ly: float = 1.0
 
     def __post_init__(self):
         self.xi_x, self.xi_y, self.w = quadrature.velocity_set(self.qx, self.qy)
         self.q = len(self.w)
-        self.dx = 1.0 / self.nx
-        self.dy = 1.0 / self.ny
+        self.dx = self.lx / self.nx
+        self.dy = self.ly / self.ny
         ax = 0.0 if (self.periodic_x and self.nx == 1) else 1.0
         ay = 0.0 if (self.periodic_y and self.ny == 1) else 1.0
-        speed = np.max(np.abs(self.xi_x) * self.nx * ax + np.abs(self.xi_y) * self.ny * ay)
+        speed = np.max(np.abs(self.xi_x) * (self.nx / self.lx) * ax + np.abs(self.xi_y) * (self.ny / self.ly) * ay)
         self.dt = float(self.dt_override) if self.dt_override is not None else self.cfl / float(speed)
         self.omega = 0.0 if math.isinf(self.kn) else self.dt / self.kn
         self._keep = [np.ascontiguousarray(a, dtype=np.float64) for a in (self.xi_x, self.xi_y, self.w)]
@@ -102,6 +105,8 @@ class Problem:
 
     @classmethod
     def from_case(cls, case, **kw) -> "Problem":
+        kw.setdefault("lx", getattr(case, "lx", 1.0))
+        kw.setdefault("ly", getattr(case, "ly", 1.0))
         return cls(case.nx, case.ny, case.periodic_x, case.periodic_y, tuple(case.wall_u), case.kn,
                    tuple(case.qx), tuple(case.qy), case.cfl, **kw)
 

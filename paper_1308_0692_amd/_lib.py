@@ -31,6 +31,7 @@ class FdlbError(RuntimeError):
 class ProblemDesc(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32),
+        ("lx", C.c_double), ("ly", C.c_double),
         ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
         ("wall_u", C.c_double * 4),
         ("kn", C.c_double), ("cfl", C.c_double),
@@ -159,10 +160,11 @@ def quad_full_range(n: int):
 
 
 def make_desc(nx, ny, periodic_x, periodic_y, wall_u, kn, qx, qy, cfl=0.9, precision="fp32",
-              allow_unstable=False) -> ProblemDesc:
+              allow_unstable=False, lx=1.0, ly=1.0) -> ProblemDesc:
     kinds = {"half": HALF, "full": FULL}
     d = ProblemDesc()
     d.nx, d.ny = int(nx), int(ny)
+    d.lx, d.ly = float(lx), float(ly)
     d.periodic_x, d.periodic_y = int(bool(periodic_x)), int(bool(periodic_y))
     d.wall_u = (C.c_double * 4)(*[float(v) for v in wall_u])
     d.kn = float(kn)
@@ -176,7 +178,8 @@ def make_desc(nx, ny, periodic_x, periodic_y, wall_u, kn, qx, qy, cfl=0.9, preci
 
 def desc_from_case(case, precision: Optional[str] = None, allow_unstable=False) -> ProblemDesc:
     return make_desc(case.nx, case.ny, case.periodic_x, case.periodic_y, case.wall_u, case.kn,
-                     case.qx, case.qy, case.cfl, precision or case.precision, allow_unstable)
+                     case.qx, case.qy, case.cfl, precision or case.precision, allow_unstable,
+                     getattr(case, "lx", 1.0), getattr(case, "ly", 1.0))
 
 
 def tile_count(precision: str) -> int:

@@ -104,7 +104,11 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     if (!(d.kn > 0)) throw Error(FDLB_EINVAL, "kn must be positive (INFINITY allowed)");
     for (int i = 0; i < 4; ++i)
         if (!std::isfinite(d.wall_u[i])) throw Error(FDLB_EINVAL, "wall speeds must be finite");
+    if (!(d.lx >= 0) || !(d.ly >= 0) || !std::isfinite(d.lx) || !std::isfinite(d.ly))
+        throw Error(FDLB_EINVAL, "domain lengths must be positive and finite (0 means 1)");
     p.d = d;
+    if (p.d.lx == 0) p.d.lx = 1.0;
+    if (p.d.ly == 0) p.d.ly = 1.0;
     std::vector<double> x, wx, y, wy;
     rule(d.qx_kind, d.qx_n, x, wx);
     rule(d.qy_kind, d.qy_n, y, wy);
@@ -123,10 +127,11 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
         }
     p.plane = (int64_t)d.nx * d.ny;
     p.L = std::max(d.nx, d.ny);
-    // Time step of the unsplit donor cell: dt max_alpha(|xi_x| N_x + |xi_y| N_y) = CFL,
-    // counting only bounded axes (transport along a periodic single cell vanishes).
-    p.nux_scale = d.periodic_x ? 0.0 : (double)d.nx;
-    p.nuy_scale = d.periodic_y ? 0.0 : (double)d.ny;
+    // Time step of the unsplit donor cell: dt max_alpha(|xi_x| / dx + |xi_y| / dy) = CFL with
+    // 1 / dx = N_x / l_x, counting only bounded axes (transport along a periodic single cell
+    // vanishes).
+    p.nux_scale = d.periodic_x ? 0.0 : (double)d.nx / p.d.lx;
+    p.nuy_scale = d.periodic_y ? 0.0 : (double)d.ny / p.d.ly;
     double speed = 0;
     for (int a = 0; a < p.q; ++a)
         speed = std::max(speed, std::fabs(p.xi_x[a]) * p.nux_scale + std::fabs(p.xi_y[a]) * p.nuy_scale);

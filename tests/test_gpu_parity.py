@@ -366,3 +366,19 @@ def test_autotune_keeps_results(F):
     op = OP.from_case(case)
     fo = op.step(op.equilibrium(), 20)
     assert eps_f(p.download(), fo, op.w) <= 2e-6
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_rectangular_domain_matches_oracle(F, prec, bar):
+    """A 2 x 1 cavity (square cells) and a channel of width 0.3: the domain lengths enter the
+    time step and the Courant numbers on both sides."""
+    for case in (W.with_(W.cavity(40, ny=20, kn=0.2, order=2), lx=2.0, ly=1.0),
+                 W.with_(W.couette(50, kn=0.1), ly=0.3)):
+        gp = F.Problem(case, precision=prec)
+        op = OP.from_case(case)
+        assert gp.dt == op.dt
+        fg, fo = both_perturbed(gp, op, seed=31)
+        gp.upload(fg)
+        gp.step(25)
+        ref = op.step(fo, 25)
+        assert eps_f(gp.download(), ref, op.w) <= bar

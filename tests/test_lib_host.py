@@ -74,7 +74,9 @@ def test_quadrature_rejects_bad_orders(F):
 
 
 @pytest.mark.parametrize("case", [W.C1, W.C2, W.C4, W.couette_x(50), W.cavity(37, ny=29, order=3),
-                                  W.cavity(64, kn=float("inf"), order=2)])
+                                  W.cavity(64, kn=float("inf"), order=2),
+                                  W.with_(W.cavity(40, ny=20, order=2), lx=2.0, ly=1.0),
+                                  W.with_(W.couette(50), ly=0.3)])
 def test_time_step_and_velocities_match_oracle(F, case):
     from oracle.scheme import Problem as OP
     p = F.Problem(case, bind=False)
@@ -188,3 +190,20 @@ def test_network_argument_errors(F):
     assert lib.fdlb_mlp_adam_step(h, 1e-3, 0.9, 0.999, 1e-8, 1) == F._lib.ESTATE
     assert lib.fdlb_mlp_param_count(None) == F._lib.EINVAL
     lib.fdlb_mlp_destroy(h)
+
+
+def test_domain_lengths_default_and_validation(F):
+    """lx = ly = 0 in a description mean the unit length; negative or non-finite lengths are
+    rejected (host only)."""
+    case = W.cavity(32, order=2)
+    d0 = F._lib.desc_from_case(case)
+    d0.lx = d0.ly = 0.0
+    p0 = F.Problem(desc=d0, bind=False)
+    p1 = F.Problem(case, bind=False)
+    assert p0.dt == p1.dt
+    for bad in (-1.0, float("inf"), float("nan")):
+        d = F._lib.desc_from_case(case)
+        d.lx = bad
+        with pytest.raises(F.FdlbError) as e:
+            F.Problem(desc=d, bind=False)
+        assert e.value.code == F._lib.EINVAL

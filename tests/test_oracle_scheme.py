@@ -355,3 +355,23 @@ def test_equilibrium_renormalisation():
     rho, ux, uy = W.random_fields(5, 5, seed=7, amp=0.1)
     f = P.equilibrium(rho * 1.3, ux, uy, renormalize=True)
     assert abs(f.sum() - 25.0) < 1e-13
+
+
+def test_domain_scaling_is_a_change_of_units():
+    """An L x L domain with Knudsen number Kn is the unit domain with Kn / L in other units:
+    dt scales with L, while the Courant numbers and omega = dt / Kn do not, so the discrete
+    steps coincide (up to the rounding of dt and omega)."""
+    L = 2.5
+    a = Problem(24, 20, False, False, (0, 0.01, 0, 0), kn=0.3, qx=("half", 2), qy=("half", 2), lx=L, ly=L)
+    b = Problem(24, 20, False, False, (0, 0.01, 0, 0), kn=0.3 / L, qx=("half", 2), qy=("half", 2))
+    assert a.dt == pytest.approx(L * b.dt, rel=1e-15)
+    assert a.omega == pytest.approx(b.omega, rel=1e-15)
+    rho, ux, uy = W.random_fields(24, 20, seed=9, amp=0.01)
+    fa = a.step(a.equilibrium(rho, ux, uy), 40)
+    fb = b.step(b.equilibrium(rho, ux, uy), 40)
+    dev = np.abs(fb - b.w[:, None, None]).max()
+    assert np.abs(fa - fb).max() <= 1e-13 * dev
+    # a stretched axis changes the steps: the Courant numbers along x halve
+    c = Problem(24, 20, False, False, (0, 0.01, 0, 0), kn=0.3, qx=("half", 2), qy=("half", 2), lx=2.0)
+    fc = c.step(c.equilibrium(rho, ux, uy), 40)
+    assert np.abs(fc - fb).max() > 1e-6 * dev

@@ -43,6 +43,8 @@ class Case:
     cfl: float = 0.9
     tol: float = 1e-8
     precision: str = "fp32"                     # "fp32" (deviation storage) or "fp64"
+    lx: float = 1.0                             # domain lengths in units of the length of Kn
+    ly: float = 1.0
 
     @property
     def q(self) -> int:
