@@ -326,9 +326,20 @@ __global__ void __launch_bounds__(256) mlp_reduce_kernel(const float* __restrict
                                                          double inv_3n, double* __restrict__ loss) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < P) {
-        float acc = 0.f;
-        for (int b = 0; b < nblocks; ++b) acc += partial[(int64_t)b * P + k];
-        grad[k] = acc;
+        // four independent running sums (blocks b = 4i + j go to sum j), combined pairwise: a
+        // fixed order, with four loads in flight instead of one dependent chain
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        int b = 0;
+        for (; b + 4 <= nblocks; b += 4) {
+            a0 += partial[(int64_t)b * P + k];
+            a1 += partial[(int64_t)(b + 1) * P + k];
+            a2 += partial[(int64_t)(b + 2) * P + k];
+            a3 += partial[(int64_t)(b + 3) * P + k];
+        }
+        if (b < nblocks) a0 += partial[(int64_t)b * P + k];
+        if (b + 1 < nblocks) a1 += partial[(int64_t)(b + 1) * P + k];
+        if (b + 2 < nblocks) a2 += partial[(int64_t)(b + 2) * P + k];
+        grad[k] = (a0 + a1) + (a2 + a3);
     }
     if (k == 0) {
         double e = 0.0;
