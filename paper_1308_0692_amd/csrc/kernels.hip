@@ -1030,7 +1030,11 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(13, double, 2, 1, 64, 1, 1, 4, 1) \
     X(14, double, 1, 1, 32, 1, 8, 1, 0) \
     X(15, double, 2, 2, 16, 1, 4, 1, 0) \
-    X(16, double, 2, 1, 32, 1, 4, 1, 0)
+    X(16, double, 2, 1, 32, 1, 4, 1, 0) \
+    X(17, double, 1, 1, 1, 1, 4, 1, 0) \
+    X(18, double, 1, 2, 1, 1, 4, 1, 0) \
+    X(19, double, 1, 4, 1, 1, 8, 1, 0) \
+    X(20, double, 1, 1, 1, 1, 8, 1, 0)
 
 const std::vector<TileShape>& tile_shapes(int precision) {
 #define FDLB_SHAPE(id, T, VX, K, LX, WPB, WA, WX, NT) TileShape{VX, LX, K, WPB, WA, WX, NT},
