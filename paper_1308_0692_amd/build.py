@@ -51,7 +51,25 @@ def build(jobs: int = 8) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_examples()
     return LIB
+
+
+EXAMPLE = os.path.join(HERE, "examples", "cavity_c")
+
+
+def build_examples() -> str:
+    """The C consumer of the library (plain C against include/fdlb.h, linked to libfdlb.so and
+    the HIP runtime of /opt/rocm; it finds libfdlb.so one directory up through its rpath)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    src = os.path.join(HERE, "examples", "cavity_c.c")
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(HERE, "..", "include"),
+           "-I", os.path.join(rocm, "include"), "-o", EXAMPLE, src, "-L", HERE, "-lfdlb",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", f"-Wl,-rpath,$ORIGIN/..", f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"example build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return EXAMPLE
 
 
 if __name__ == "__main__":
