@@ -382,3 +382,23 @@ def test_rectangular_domain_matches_oracle(F, prec, bar):
         gp.step(25)
         ref = op.step(fo, 25)
         assert eps_f(gp.download(), ref, op.w) <= bar
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_seeded_random_problems_match_oracle(F, prec, bar):
+    """24 seeded assorted problems (grid shapes, periodic axes, half- and full-range rules, Kn
+    including infinity, speeds on all four walls, domain lengths): seven steps from a perturbed
+    state on the built-in tile and on one other fitting tile (drawn from the same seed)."""
+    rng = np.random.default_rng(2024)
+    for case in W.random_cases(24, 1308):
+        op = OP.from_case(case)
+        gp = F.Problem(case, precision=prec)
+        fg, fo = both_perturbed(gp, op, seed=7)
+        ref = op.step(fo, 7)
+        tiles = _fitting_tiles(F, case, prec)
+        for t in sorted({gp.tile, int(rng.choice(tiles))}):
+            gp.set_tile(t)
+            gp.upload(fg)
+            gp.step(7)
+            e = eps_f(gp.download(), ref, op.w)
+            assert e <= bar, (case.name, F.tile_describe(prec, t), e)

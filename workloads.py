@@ -177,3 +177,28 @@ def mlp_samples(n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
     a = rng.uniform(-1.0, 1.0, size=(n, 3))
     t = np.stack([np.sin(2 * a[:, 1]) * a[:, 0], a[:, 2] ** 2 - 0.3, np.cos(a[:, 0] + a[:, 1])], axis=1)
     return a, t
+
+
+def random_cases(count: int, seed: int) -> List[Case]:
+    """Seeded assorted problems for broad parity checks: grids 2..70 (or a periodic single cell on
+    one axis), half- or full-range rules of 1..5 nodes per half (full: 2..6), Kn log-uniform in
+    [0.02, 50] or infinite, every wall speed in [-0.02, 0.02], domain lengths in [0.5, 2]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        kind = int(rng.integers(0, 3))  # 0 box, 1 periodic x, 2 periodic y
+        nx = 1 if kind == 1 else int(rng.integers(2, 71))
+        ny = 1 if kind == 2 else int(rng.integers(2, 71))
+
+        def rule(axis_periodic: bool):
+            if not axis_periodic and rng.random() < 0.7:
+                return ("half", int(rng.integers(1, 6)))
+            return ("full", int(rng.integers(2, 7)))
+
+        qx, qy = rule(kind == 1), rule(kind == 2)
+        kn = float("inf") if rng.random() < 0.1 else float(10.0 ** rng.uniform(np.log10(0.02), np.log10(50.0)))
+        wall = tuple(float(v) for v in rng.uniform(-0.02, 0.02, size=4))
+        out.append(Case(name=f"random{i:02d}", nx=nx, ny=ny, periodic_x=kind == 1, periodic_y=kind == 2,
+                        wall_u=wall, kn=kn, qx=qx, qy=qy, lx=float(rng.uniform(0.5, 2.0)),
+                        ly=float(rng.uniform(0.5, 2.0))))
+    return out
