@@ -263,6 +263,18 @@ def main():
     log(f"[bench] {value:.4e} updates/s; step kernel {achieved:.0f} GB/s = {achieved/HBM_PEAK_GBPS:.3f} of peak")
 
     extra = {}
+    # the same cavity with populations stored in double (twice the bytes per update)
+    p64 = F.Problem(case, precision="fp64")
+    ms64 = p64.autotune(steps=3)
+    p64.init_equilibrium()
+    p64.step(5)
+    k64, _ = p64.step_timed(50)
+    b64 = updates_per_step * 16 + cells * 6 * 8 + 2 * 4 * max(case.nx, case.ny) * 8
+    extra["large_cavity_fp64"] = {"updates_per_s": updates_per_step * 50 / (k64 * 1e-3),
+                                  "step_kernel_ms": round(k64 / 50, 5), "alg_GBps": round(b64 / (k64 / 50 * 1e-3) / 1e9, 1),
+                                  "tile": F.tile_describe("fp64", p64.tile)}
+    log(f"[bench] same cavity in FP64: step kernel {k64 / 50:.3f} ms ({extra['large_cavity_fp64']['alg_GBps']} GB/s)")
+    p64.close()
     if not args.no_copy:
         extra["copy_GBps"] = round(copy_ceiling(F, torch), 1)
         log(f"[bench] streaming copy: {extra['copy_GBps']} GB/s")
