@@ -1,0 +1,84 @@
+"""Edge cases of the HIP path against the oracle: the largest velocity set (16 nodes per half on
+both axes, Q = 1024), a relaxation rate at its limit (omega = 1), empty calls, and a problem
+with no moving wall, which must stay at rest to round-off (the wall constant sqrt(2 pi) A - 1 of
+Eq. (9) is zero only in exact arithmetic)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.scheme import Problem as OP
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1308_0692_amd as F
+    return F
+
+
+def perturbed(xi_x, xi_y, w, nx, ny, seed):
+    rho, ux, uy = W.random_fields(nx, ny, seed, amp=0.01)
+    noise = W.random_noise(len(w), nx, ny, seed + 1)
+    feq = w[:, None, None] * rho[None] * (1 + xi_x[:, None, None] * ux[None] + xi_y[:, None, None] * uy[None])
+    return feq * (1 + 0.02 * noise)
+
+
+def compare(F, case, prec, steps, bar):
+    op = OP.from_case(case)
+    gp = F.Problem(case, precision=prec)
+    x, y, w = gp.velocities()
+    gp.upload(perturbed(x, y, w, case.nx, case.ny, 5))
+    gp.step(steps)
+    ref = op.step(perturbed(op.xi_x, op.xi_y, op.w, case.nx, case.ny, 5), steps)
+    dev = np.abs(ref - op.w[:, None, None]).max()
+    assert np.abs(gp.download() - ref).max() <= bar * dev
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_largest_velocity_set(F, prec, bar):
+    case = W.cavity(6, ny=5, kn=0.5, order=16)
+    assert F.Problem(case, bind=False).q == 1024
+    compare(F, case, prec, 5, bar)
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_relaxation_rate_at_its_limit(F, prec, bar):
+    base = W.cavity(24, ny=20, order=2)
+    dt = F.Problem(base, bind=False).dt
+    case = W.with_(base, kn=dt)          # omega = dt / Kn = 1: full relaxation every step
+    p = F.Problem(case, bind=False)
+    assert p.omega == 1.0
+    compare(F, case, prec, 10, bar)
+
+
+def test_empty_calls(F):
+    case = W.cavity(16, order=2)
+    p = F.Problem(case, precision="fp64")
+    p.init_equilibrium(*W.random_fields(16, 16, 3, amp=0.01))
+    f0 = p.download()
+    p.step(0)
+    assert np.array_equal(p.download(), f0)
+    rep = p.solve(1e-8, 0, check_every=10)
+    assert rep["steps"] == 0 and rep["status"] == 1
+    assert np.array_equal(p.download(), f0)
+    import torch
+    net = F.Mlp(max_batch=64)
+    y = net.forward(torch.empty((0, 3), dtype=torch.float32, device="cuda"))
+    assert y.shape == (0, 3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_no_moving_wall_stays_at_rest(F, prec):
+    case = W.cavity(20, ny=12, kn=0.3, u_w=0.0, order=3)
+    p = F.Problem(case, precision=prec)
+    p.init_equilibrium()
+    p.step(50)
+    x, y, w = p.velocities()
+    assert np.abs(p.download() - w[:, None, None]).max() <= 1e-13 * w.max()
+    rho, ux, uy, pxy = p.moments()
+    assert np.abs(rho - 1.0).max() <= 1e-13
+    assert np.abs(ux).max() <= 1e-13 and np.abs(uy).max() <= 1e-13
