@@ -357,6 +357,15 @@ int fdlb_batch_autotune(fdlb_batch *b, int steps, double *best_ms_per_step);
  * built-in choice.  fdlb_batch_active_precision gives instance i's current precision.
  */
 int fdlb_batch_active_precision(const fdlb_batch *b, int i);
+/*
+ * Tail of a batch solve: once at most max_members instances remain active (and the solve began
+ * with more), each precision group switches to the built-in tile choice for its largest remaining
+ * instance, if that shape fits every instance; the batch's own tiles are restored when the solve
+ * returns.  A shape chosen for many concurrent instances trades latency for throughput, which
+ * the last instances no longer need.  Default 8; 0 disables (every step then uses the batch's
+ * tile, so an instance's results are bit-identical to a single solve with that tile).
+ */
+int fdlb_batch_set_retile(fdlb_batch *b, int max_members);
 
 /* ---- learned warm start ----------------------------------------------------------------- */
 

@@ -304,6 +304,10 @@ class Batch:
     def active_precision(self, i: int) -> str:
         return _lib.PRECISION_NAMES[check(_lib.lib.fdlb_batch_active_precision(self._h, int(i)), allow=(0, 1))]
 
+    def set_retile(self, max_members: int):
+        """Tail re-tiling threshold of the solves (fdlb_batch_set_retile); 0 disables."""
+        check(_lib.lib.fdlb_batch_set_retile(self._h, int(max_members)))
+
     @property
     def tile(self) -> int:
         return _lib.lib.fdlb_batch_get_tile(self._h)

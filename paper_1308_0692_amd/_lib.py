@@ -109,6 +109,7 @@ def _load():
         "fdlb_batch_get_tile": (C.c_int, [vp]),
         "fdlb_batch_autotune": (C.c_int, [vp, C.c_int, dp]),
         "fdlb_batch_active_precision": (C.c_int, [vp, C.c_int]),
+        "fdlb_batch_set_retile": (C.c_int, [vp, C.c_int]),
         "fdlb_mlp_create": (C.c_int, [C.c_int, i64, C.POINTER(vp)]),
         "fdlb_mlp_destroy": (None, [vp]),
         "fdlb_mlp_param_count": (i64, [vp]),

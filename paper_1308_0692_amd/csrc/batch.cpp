@@ -53,6 +53,7 @@ struct fdlb_batch {
     bool step_reduce = false;       // some member reduces every step with a kernel of its own
     bool end_reduce = false;        // some member reduces inline (closed at the end of a chunk)
     size_t off_ctrlptr = 0, off_ctrlbuf = 0;
+    int retile_members = 8;         // re-choose tiles once at most this many instances remain (0: never)
     char* d_state = nullptr;
     char* d_work = nullptr;
     hipStream_t stream = nullptr;
@@ -428,6 +429,10 @@ int batch_solve(fdlb_batch& b, double tol, int64_t max_steps, int32_t check_ever
     for (int i = 0; i < n; ++i) b.active.push_back(i);
     upload_map(b);
     const bool graph = use_graph && b.stream != nullptr && check_every >= 2;
+    // The tail: once few instances remain, the launch is latency-bound and the shape chosen for
+    // the full batch (many waves per tile, throughput) loses to the single-problem choice.
+    const int saved_tile[2] = {b.grp[0].tile, b.grp[1].tile};
+    bool may_retile = b.retile_members > 0 && n > b.retile_members;
     std::vector<int32_t> hlen(n, 0);
     std::vector<MixedSwitch> sw;
     std::vector<double> fp32_until(n);  // step count where a member's float phase ended, -1: not yet
@@ -463,9 +468,31 @@ int batch_solve(fdlb_batch& b, double tol, int64_t max_steps, int32_t check_ever
         if (switched) upload_rargs(b);
         if (switched || still.size() != b.active.size()) {
             b.active = still;
+            if (may_retile && !still.empty() && (int)still.size() <= b.retile_members) {
+                may_retile = false;
+                bool changed = false;
+                for (int g = 0; g < 2; ++g) {
+                    if (!b.grp[g].used) continue;
+                    int big = -1;
+                    for (int i : still)
+                        if (group_of(*b.probs[i]) == g &&
+                            (big < 0 || b.probs[i]->plane * b.probs[i]->q > b.probs[big]->plane * b.probs[big]->q))
+                            big = i;
+                    if (big < 0) continue;
+                    const fdlb_problem& pb = *b.probs[big];
+                    const int t = heuristic_tile_for(prec_of_group(g), pb.d.nx, pb.d.ny, pb.d.periodic_x, pb.d.periodic_y);
+                    if (t != b.grp[g].tile && tile_fits_all(b, g, t)) {
+                        group_set_tile(b, g, t);
+                        changed = true;
+                    }
+                }
+                if (changed) upload_args(b);
+            }
             upload_map(b);
         }
     }
+    for (int g = 0; g < 2; ++g)
+        if (b.grp[g].used && b.grp[g].tile != saved_tile[g]) group_set_tile(b, g, saved_tile[g]);
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int status = FDLB_OK;
     for (int i = 0; i < n; ++i) {
@@ -623,6 +650,14 @@ int fdlb_batch_field_samples(fdlb_batch* b, int i, float* d_in, float* d_target)
 int fdlb_batch_set_tile(fdlb_batch* b, int tile) {
     return guard_call([&] {
         batch_set_tile(bh(b), tile);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_set_retile(fdlb_batch* b, int max_members) {
+    return guard_call([&] {
+        if (max_members < 0) throw Error(FDLB_EINVAL, "max_members must be >= 0");
+        bh(b).retile_members = max_members;
         return FDLB_OK;
     });
 }

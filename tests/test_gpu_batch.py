@@ -27,6 +27,7 @@ MIXED = [W.cavity(64, kn=0.3, order=2), W.cavity(48, ny=40, kn=1.0, order=3),
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_batch_members_equal_solo_runs(F, prec):
     b = F.Batch(MIXED, precision=prec)
+    b.set_retile(0)  # one tile throughout: bit-identical to single solves with that tile
     for i in range(len(MIXED)):
         b.init_equilibrium(i)
     status, reps = b.solve(1e-7, 60000, check_every=50)
@@ -128,3 +129,25 @@ def test_sweep_full_size_sampled_members_match_oracle(F):
         r0, ux0, uy0 = op.moments(fo)
         assert float(np.hypot(ux - ux0, uy - uy0).max() / np.hypot(ux0, uy0).max()) <= 2e-5
         assert float(np.abs(rho - r0).max()) <= 2e-5
+
+
+def test_tail_retiling_keeps_results_and_restores_tiles(F):
+    """With the default tail re-tiling the last instances switch to their single-problem tile:
+    every instance still converges to its single-solve answer (the steps differ at most by the
+    rounding of the residual), and the batch's tile is restored afterwards."""
+    b = F.Batch(MIXED, precision="fp64")
+    b.set_tile(b.tile)
+    tile0 = b.tile
+    for i in range(len(MIXED)):
+        b.init_equilibrium(i)
+    status, reps = b.solve(1e-9, 200000, check_every=50)
+    assert status == 0 and b.tile == tile0
+    for i, case in enumerate(MIXED):
+        p = F.Problem(case, precision="fp64")
+        p.set_tile(tile0)
+        p.init_equilibrium()
+        rep = p.solve(1e-9, 200000, check_every=50)
+        assert abs(rep["steps"] - reps[i]["steps"]) <= 1, i
+        _, ux, uy, _ = p.moments()
+        _, bx, by, _ = b.moments(i)
+        assert np.hypot(bx - ux, by - uy).max() <= 1e-7 * np.hypot(ux, uy).max(), i

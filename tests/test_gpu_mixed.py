@@ -124,6 +124,7 @@ def test_batch_members_switch_individually_and_equal_solo(F):
     cases = [W.cavity(48, kn=0.3, order=2), W.cavity(48, kn=2.0, order=3), W.cavity(48, kn=0.05, order=2),
              W.cavity(48, kn=8.0, order=2)]
     b = F.Batch(cases, precision="mixed")
+    b.set_retile(0)  # one tile throughout: bit-identical to single solves with that tile
     for i in range(len(cases)):
         b.init_equilibrium(i)
     status, reps = b.solve(1e-9, 200000, check_every=100)
