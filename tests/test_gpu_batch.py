@@ -132,11 +132,11 @@ def test_sweep_full_size_sampled_members_match_oracle(F):
 
 
 def test_tail_retiling_keeps_results_and_restores_tiles(F):
-    """With the default tail re-tiling the last instances switch to their single-problem tile:
+    """With tail re-tiling the last instances switch to their single-problem tile:
     every instance still converges to its single-solve answer (the steps differ at most by the
     rounding of the residual), and the batch's tile is restored afterwards."""
     b = F.Batch(MIXED, precision="fp64")
-    b.set_tile(b.tile)
+    b.set_retile(4)  # six instances: the last four switch
     tile0 = b.tile
     for i in range(len(MIXED)):
         b.init_equilibrium(i)
