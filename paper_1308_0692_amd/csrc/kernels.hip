@@ -19,13 +19,20 @@
 //
 // Work decomposition: a wave owns a tile of (LX*VX) x (LY*K) cells (LX lanes
 // along x, LY = 64/LX along y, each lane VX consecutive cells of K rows) and
-// loops over all velocities, quadrant by quadrant (signs of xi_x, xi_y are
-// then compile-time constants).  The upwind neighbour of a cell is in the
-// same lane's registers, in a neighbouring lane (cross-lane shuffle of the
-// relaxed value), in a halo cell outside the wave (loaded and relaxed by the
-// edge lane), or the wall emission of Eq. (8).  Blocks are mapped to tiles
-// so that each of the 8 XCDs owns a contiguous band of tile rows (its own
-// L2 then serves the halo rows shared between vertically adjacent tiles).
+// loops over the velocities quadrant by quadrant (signs of xi_x, xi_y are
+// then compile-time constants); small grids split the velocities of a tile
+// over 2, 4 or 8 waves whose partial moments meet in LDS.  The upwind
+// neighbour of a cell is in the same lane's registers, in a neighbouring lane
+// (cross-lane shuffle of the relaxed value), in a halo cell outside the wave
+// (loaded and relaxed by the edge lane), or the wall emission of Eq. (8).
+// Blocks are mapped to tiles so that each of the 8 XCDs owns a contiguous band
+// of tile rows (its own L2 then serves the halo rows shared between vertically
+// adjacent tiles).
+//
+// Residual: every block writes three partial sums; they are reduced by a
+// one-block kernel after the step (large grids) or by one extra block of the
+// next step's launch (grids of at most INLINE_REDUCE_MAX_BLOCKS tiles), in a
+// fixed order either way, so runs are bit-reproducible.
 #include <algorithm>
 #include <type_traits>
 
