@@ -343,6 +343,13 @@ int fdlb_batch_solve(fdlb_batch *b, double tol, int64_t max_steps, int32_t check
 int fdlb_batch_moments(fdlb_batch *b, int i, double *rho, double *ux, double *uy, double *pxy);
 int fdlb_batch_state_download(fdlb_batch *b, int i, double *f_host);
 /*
+ * Instance i's raw populations from a host array in the layout of fdlb_state_upload
+ * ([Q][ny][nx] float64, Eq. (2) velocities); like fdlb_batch_init_equilibrium it restarts
+ * that instance (step parity 0, a mixed-precision instance back in its float phase).
+ * FDLB_EINVAL for an index out of range or a NULL array.  Synchronous.
+ */
+int fdlb_batch_state_upload(fdlb_batch *b, int i, const double *f_host);
+/*
  * One tile shape serves the whole batch (it must fit every problem).  fdlb_batch_autotune
  * times every fitting shape on the whole batch for `steps` steps (every problem is re-seeded
  * at rest afterwards) and keeps the fastest.  Synchronous.

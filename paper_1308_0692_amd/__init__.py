@@ -28,9 +28,14 @@ def _torch():
     return torch
 
 
-def _alloc(nbytes: int, device):
+def _alloc(nbytes: int, device, poison: bool = False):
+    """A 256-byte aligned device buffer; poison fills it with 0xFF bytes (NaN as float or double),
+    so that a read of memory the library never wrote shows up in the results."""
     torch = _torch()
     t = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    if poison:
+        t.fill_(255)
+        torch.cuda.current_stream(device).synchronize()
     off = (-t.data_ptr()) % 256
     return t, t.data_ptr() + off
 
@@ -39,7 +44,8 @@ class Problem:
     """One boundary-value problem bound to device memory on `device` (default cuda:0)."""
 
     def __init__(self, case=None, *, precision: Optional[str] = None, allow_unstable: bool = False,
-                 device="cuda:0", stream=None, bind: bool = True, desc: Optional[_lib.ProblemDesc] = None):
+                 device="cuda:0", stream=None, bind: bool = True, desc: Optional[_lib.ProblemDesc] = None,
+                 poison: bool = False):
         self.desc = desc if desc is not None else desc_from_case(case, precision, allow_unstable)
         self.precision = _lib.PRECISION_NAMES[self.desc.precision]
         h = C.c_void_p()
@@ -54,16 +60,16 @@ class Problem:
         self.device = device
         self._stream = stream
         if bind:
-            self.bind()
+            self.bind(poison=poison)
 
     # -- memory ----------------------------------------------------------------
-    def bind(self):
+    def bind(self, poison: bool = False):
         torch = _torch()
         # A stream of its own (default priority) so that step chunks can be graph-captured.
         s = self._stream if self._stream is not None else torch.cuda.Stream(device=self.device)
         self._stream = s
-        self._state_t, self._state = _alloc(self.state_bytes, self.device)
-        self._work_t, self._work = _alloc(self.workspace_bytes, self.device)
+        self._state_t, self._state = _alloc(self.state_bytes, self.device, poison)
+        self._work_t, self._work = _alloc(self.workspace_bytes, self.device, poison)
         check(_lib.lib.fdlb_bind(self._h, C.c_void_p(self._state), C.c_void_p(self._work),
                                  C.c_void_p(s.cuda_stream)))
 
@@ -218,11 +224,21 @@ def stream_copy(dst, src, nbytes: int, stream=None):
                                     int(nbytes), C.c_void_p(s.cuda_stream)))
 
 
+def _velocity_count(desc) -> int:
+    """Q of a problem description (a host-side handle, created and destroyed at once)."""
+    h = C.c_void_p()
+    check(_lib.lib.fdlb_problem_create(C.byref(desc), C.byref(h)))
+    try:
+        return _lib.lib.fdlb_problem_q(h)
+    finally:
+        _lib.lib.fdlb_problem_destroy(h)
+
+
 class Batch:
     """Many independent problems solved together (one launch per step for all of them)."""
 
     def __init__(self, cases, *, precision: Optional[str] = None, allow_unstable=False, device="cuda:0",
-                 stream=None, descs=None):
+                 stream=None, descs=None, poison: bool = False):
         torch = _torch()
         if descs is None:
             descs = [desc_from_case(c, precision, allow_unstable) for c in cases]
@@ -232,11 +248,12 @@ class Batch:
         check(_lib.lib.fdlb_batch_create(arr, self.n, C.byref(h)))
         self._h = h
         self.shapes = [(d.nx, d.ny) for d in descs]
+        self.qs = [_velocity_count(d) for d in descs]
         self.precision = _lib.PRECISION_NAMES[descs[0].precision]
         self.device = device
         self._stream = stream if stream is not None else torch.cuda.Stream(device=device)
-        self._state_t, self._state = _alloc(_lib.lib.fdlb_batch_state_bytes(h), device)
-        self._work_t, self._work = _alloc(_lib.lib.fdlb_batch_workspace_bytes(h), device)
+        self._state_t, self._state = _alloc(_lib.lib.fdlb_batch_state_bytes(h), device, poison)
+        self._work_t, self._work = _alloc(_lib.lib.fdlb_batch_workspace_bytes(h), device, poison)
         check(_lib.lib.fdlb_batch_bind(h, C.c_void_p(self._state), C.c_void_p(self._work),
                                        C.c_void_p(self._stream.cuda_stream)))
 
@@ -282,9 +299,17 @@ class Batch:
         check(_lib.lib.fdlb_batch_moments(self._h, int(i), *[_lib._dp(a) for a in out]))
         return tuple(out)
 
-    def download(self, i: int, q: int) -> np.ndarray:
+    def upload(self, i: int, f: np.ndarray):
         nx, ny = self.shapes[i]
-        f = np.empty((q, ny, nx))
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (self.qs[i], ny, nx)
+        check(_lib.lib.fdlb_batch_state_upload(self._h, int(i), _lib._dp(f)))
+
+    def download(self, i: int, q: Optional[int] = None) -> np.ndarray:
+        nx, ny = self.shapes[i]
+        if q is not None and q != self.qs[i]:
+            raise ValueError(f"instance {i} has {self.qs[i]} velocities, not {q}")
+        f = np.empty((self.qs[i], ny, nx))
         check(_lib.lib.fdlb_batch_state_download(self._h, int(i), _lib._dp(f)))
         return f
 
@@ -338,7 +363,7 @@ class Mlp:
     float32 tensors owned here, all arithmetic in the library's kernels."""
 
     def __init__(self, hidden: int = 4, max_batch: int = 8192, seed: int = 0, device="cuda:0", stream=None,
-                 params=None):
+                 params=None, poison: bool = False):
         torch = _torch()
         h = C.c_void_p()
         check(_lib.lib.fdlb_mlp_create(int(hidden), int(max_batch), C.byref(h)))
@@ -355,7 +380,7 @@ class Mlp:
         self.grad = torch.zeros_like(self.params)
         self.adam_m = torch.zeros_like(self.params)
         self.adam_v = torch.zeros_like(self.params)
-        self._work_t, self._work = _alloc(_lib.lib.fdlb_mlp_workspace_bytes(h), device)
+        self._work_t, self._work = _alloc(_lib.lib.fdlb_mlp_workspace_bytes(h), device, poison)
         self._stream = stream if stream is not None else torch.cuda.Stream(device=device)
         torch.cuda.current_stream(device).synchronize()   # parameter upload and zeroed moments
         check(_lib.lib.fdlb_mlp_bind(h, *[C.c_void_p(t.data_ptr()) for t in

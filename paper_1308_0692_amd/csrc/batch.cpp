@@ -31,6 +31,7 @@ void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, cons
 void init_equilibrium_dev(fdlb_problem& p, const float* rho, const float* ux, const float* uy, int renorm);
 void moments(fdlb_problem& p, double* rho, double* ux, double* uy, double* pxy);
 void state_download(fdlb_problem& p, double* f);
+void state_upload(fdlb_problem& p, const double* f);
 }  // namespace fdlb
 
 // The members that run in one precision: their block map and step arguments.
@@ -220,6 +221,7 @@ void batch_moments(fdlb_batch& b, int i, double* rho, double* ux, double* uy, do
     moments(inst(b, i), rho, ux, uy, pxy);
 }
 void batch_state_download(fdlb_batch& b, int i, double* f) { state_download(inst(b, i), f); }
+void batch_state_upload(fdlb_batch& b, int i, const double* f) { state_upload(inst(b, i), f); }
 
 template <class T>
 static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile, bool prev) {
@@ -636,6 +638,13 @@ int fdlb_batch_moments(fdlb_batch* b, int i, double* rho, double* ux, double* uy
 int fdlb_batch_state_download(fdlb_batch* b, int i, double* f_host) {
     return guard_call([&] {
         batch_state_download(bh(b), i, f_host);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_state_upload(fdlb_batch* b, int i, const double* f_host) {
+    return guard_call([&] {
+        batch_state_upload(bh(b), i, f_host);
         return FDLB_OK;
     });
 }

@@ -171,10 +171,14 @@ __device__ __forceinline__ bool frozen(const double* __restrict__ ctrl) {
     return ctrl[CTRL_FREEZE] != 0.0 && (ctrl[CTRL_FIRST_BELOW] >= 0.0 || ctrl[CTRL_DIVERGED] >= 0.0);
 }
 
-// Residual of a step from its sums: R = sqrt(sum |du|^2 / sum |u|^2).
+// Residual of a step from its sums: R = sqrt(sum |du|^2 / sum |u|^2).  A state at rest that
+// stays at rest has R = 0, one that leaves rest R = inf; a non-finite state makes the sums NaN
+// and so R, which counts as a runaway (never as convergence).
 __device__ __forceinline__ double residual_of(double num, double den) {
     if (den > 0.0) return sqrt(num / den);
-    return num > 0.0 ? __builtin_huge_val() : 0.0;
+    if (den == 0.0 && num == 0.0) return 0.0;
+    if (den == 0.0 && num > 0.0) return __builtin_huge_val();
+    return __builtin_nan("");
 }
 __device__ __forceinline__ bool runaway(double R, double umax2) { return !(R <= 1e300) || !(umax2 <= 0.25); }
 

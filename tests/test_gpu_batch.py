@@ -151,3 +151,28 @@ def test_tail_retiling_keeps_results_and_restores_tiles(F):
         _, ux, uy, _ = p.moments()
         _, bx, by, _ = b.moments(i)
         assert np.hypot(bx - ux, by - uy).max() <= 1e-7 * np.hypot(ux, uy).max(), i
+
+
+def test_batch_member_upload_equals_single_problem_upload(F):
+    """A member restarted from uploaded populations marches bit for bit as a single problem
+    started from the same populations (same tile shape, no tail re-tiling)."""
+    cases = [W.cavity(40, kn=0.3, order=2), W.cavity(28, ny=36, kn=0.8, order=3)]
+    b = F.Batch(cases, precision="fp32")
+    b.set_retile(0)
+    rng = np.random.default_rng(5)
+    fs = []
+    for i, case in enumerate(cases):
+        b.init_equilibrium(i)
+        f = b.download(i)
+        f *= 1 + 0.01 * rng.standard_normal(f.shape)
+        b.upload(i, f)
+        fs.append(f)
+    status, reps = b.solve(1e-7, 50000, check_every=30)
+    assert status == 0
+    for i, case in enumerate(cases):
+        p = F.Problem(case, precision="fp32")
+        p.set_tile(b.tile)
+        p.upload(fs[i])
+        rep = p.solve(1e-7, 50000, check_every=30)
+        assert rep["steps"] == reps[i]["steps"]
+        assert np.array_equal(p.download(), b.download(i))

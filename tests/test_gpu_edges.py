@@ -2,6 +2,8 @@
 both axes, Q = 1024), a relaxation rate at its limit (omega = 1), empty calls, and a problem
 with no moving wall, which must stay at rest to round-off (the wall constant sqrt(2 pi) A - 1 of
 Eq. (9) is zero only in exact arithmetic)."""
+import re
+
 import numpy as np
 import pytest
 
@@ -82,3 +84,43 @@ def test_no_moving_wall_stays_at_rest(F, prec):
     rho, ux, uy, pxy = p.moments()
     assert np.abs(rho - 1.0).max() <= 1e-13
     assert np.abs(ux).max() <= 1e-13 and np.abs(uy).max() <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_nan_in_the_state_is_reported_as_divergence(F, prec):
+    """A NaN in one population of one cell: the residual of the first step is NaN, which
+    the device-side check counts as a runaway, so the solve stops with EDIVERGED at step 1
+    instead of returning NaN fields as converged (NaN arithmetic does not fault)."""
+    case = W.cavity(33, ny=21, kn=0.2, order=2)
+    p = F.Problem(case, precision=prec)
+    p.init_equilibrium()
+    f = p.download()
+    f[3, 10, 17] = np.nan
+    p.upload(f)
+    rep = p.solve(1e-8, 1000, check_every=25, raise_on_diverge=False)
+    assert rep["status"] == F._lib.EDIVERGED
+    with pytest.raises(F.FdlbError) as e:
+        p.upload(f)
+        p.solve(1e-8, 1000, check_every=25)
+    assert e.value.code == F._lib.EDIVERGED
+    assert re.search(r"diverged at step 1\b", str(e.value)), str(e.value)
+    # the problem stays usable: a fresh start converges
+    p.init_equilibrium()
+    assert p.solve(1e-6, 100000, check_every=50)["status"] == 0
+
+
+def test_nan_in_one_batch_member_leaves_the_others(F):
+    cases = [W.cavity(32, kn=0.3, order=2), W.cavity(40, kn=0.3, order=2), W.cavity(24, kn=1.0, order=2)]
+    b = F.Batch(cases, precision="fp32")
+    for i in range(3):
+        b.init_equilibrium(i)
+    f = b.download(1)
+    f[0, 0, 0] = np.nan
+    b.upload(1, f)
+    status, reps = b.solve(1e-6, 50000, check_every=40)
+    assert status == F._lib.EDIVERGED
+    assert reps[1]["status"] == F._lib.EDIVERGED
+    assert reps[0]["status"] == 0 and reps[2]["status"] == 0
+    for i in (0, 2):
+        rho, ux, uy, _ = b.moments(i)
+        assert np.all(np.isfinite(rho)) and np.all(np.isfinite(ux))
