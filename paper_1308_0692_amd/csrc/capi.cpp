@@ -227,7 +227,7 @@ int fdlb_tile_describe(int precision, int tile, char* buf, size_t len) {
         const TileShape& t = s[tile];
         std::string d = "vx" + std::to_string(t.vx) + " lx" + std::to_string(t.lx) + " k" + std::to_string(t.k) +
                         " w" + std::to_string(t.wpb) + (t.wa > 1 ? " a" + std::to_string(t.wa) : std::string()) +
-                        (t.wx > 1 ? " x" + std::to_string(t.wx) : std::string()) + (t.nt ? " nt" : "") + " (" +
+                        (t.wx > 1 ? " x" + std::to_string(t.wx) : std::string()) + (t.nt ? " nt" : "") + (t.pd > 1 ? " p" + std::to_string(t.pd) : std::string()) + " (" +
                         std::to_string(t.tile_w()) + "x" + std::to_string(t.tile_h()) + ")";
         std::strncpy(buf, d.c_str(), len - 1);
         buf[len - 1] = 0;

@@ -84,6 +84,7 @@ struct TileShape {
     int wa;    // waves per block sharing one tile, splitting the velocities
     int wx;    // waves per block side by side along x
     int nt;    // non-temporal population stores
+    int pd;    // velocity planes whose loads are in flight beyond the current one
     int tile_w() const { return vx * lx * wx; }
     int tile_h() const { return (64 / lx) * k * wpb; }
 };

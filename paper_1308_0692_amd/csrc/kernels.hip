@@ -45,9 +45,6 @@ namespace {
 constexpr double SQRT_2PI = 2.50662827463100050241576528481104525;
 constexpr int NUM_XCD = 8;
 
-#ifndef FDLB_PREFETCH
-#define FDLB_PREFETCH 1  // velocity planes in flight beyond the current one (2 costs occupancy)
-#endif
 #ifdef FDLB_MIN_WAVES  // ask the register allocator for this many waves per SIMD
 #define FDLB_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(FDLB_MIN_WAVES)))
 #else
@@ -132,6 +129,29 @@ __device__ __forceinline__ int load_alpha(const VelEntry<T>* p, const int e) {
     return ((cptr)p)[e].alpha;
 }
 
+// The value v holds in lane (lane - D); lanes whose source lies outside the wave get a value
+// that callers never use.  A shift by one lane is a DPP wave shift (a register move: no LDS
+// round trip, no wait on the counter that LDS shares with scalar loads); other distances go
+// through ds_bpermute.
+template <int D, class T>
+__device__ __forceinline__ T lane_from(const T v, const int lane) {
+    if constexpr (D == 1 || D == -1) {
+        constexpr int CTRL = D == 1 ? 0x138 : 0x130;  // wave_shr:1 (from lane - 1), wave_shl:1 (lane + 1)
+        if constexpr (sizeof(T) == 4) {
+            return __builtin_bit_cast(
+                T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+        } else {
+            const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+            const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+            const unsigned hi =
+                (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+            return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+        }
+    } else {
+        return __shfl(v, lane - D, 64);
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -204,7 +224,7 @@ __device__ __forceinline__ void record_step(double* __restrict__ ctrl, double nu
 // latency instead of four; otherwise it takes every WA-th velocity of each quadrant.
 // bid/nb: this block's index among the blocks of its problem; part: where its residual
 // partials go.
-template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT>
+template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD>
 __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, const int nb,
                                           double* __restrict__ part) {
     constexpr int LY = 64 / LX;
@@ -407,8 +427,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
         // plane's round trip to HBM lasts longer than the compute on it).  The loop is unrolled
         // PD + 1 times so that the plane buffers change roles without register copies (a copy
         // out of a buffer whose load is in flight would have to wait for it).
-        constexpr int PD = FDLB_PREFETCH;
-        static_assert(PD == 1 || PD == 2, "prefetch distance must be 1 or 2");
+        static_assert(PD >= 1 && PD <= 8, "prefetch distance must be 1..8");
         const int e0 = qb + (QSPLIT ? (wa >> 2) : wa);
         const int elast = qe - 1 - ((qe - 1 - e0) % SW);  // last plane of this wave (if e0 < qe)
         auto clampe = [&](const int en) { return en <= elast ? en : elast; };
@@ -442,14 +461,14 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
             T xb[K];
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const T sh = __shfl(gr[r][SX > 0 ? VX - 1 : 0], lane - SX, 64);
+                const T sh = lane_from<SX>(gr[r][SX > 0 ? VX - 1 : 0], lane);
                 const T em = c.w * Px[r] + c.wy * Qx[r];
                 xb[r] = xmode == MODE_SHUF ? sh : (xmode == MODE_LOAD ? gxh[r] : em);
             }
             T yb[VX];
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                const T sh = __shfl(gr[SY > 0 ? K - 1 : 0][v], lane - SY * LX, 64);
+                const T sh = lane_from<SY * LX>(gr[SY > 0 ? K - 1 : 0][v], lane);
                 const T em = c.w * Py[v] + c.wx * Qy[v];
                 yb[v] = ymode == MODE_SHUF ? sh : (ymode == MODE_LOAD ? gyh[v] : em);
             }
@@ -517,33 +536,21 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
             }
         };
 
-        T b0[K][VX], b0x[K], b0y[VX], b1[K][VX], b1x[K], b1y[VX];
+        // Planes past this wave's last one are clamped to it: loaded again, never used.
+        T bv[PD + 1][K][VX], bx[PD + 1][K], by[PD + 1][VX];
         if (e0 < qe) {
-            load_plane(e0, b0, b0x, b0y);
-            if constexpr (PD == 1) {
-                for (int e = e0;;) {
-                    load_plane(clampe(e + SW), b1, b1x, b1y);
-                    step_one(e, b0, b0x, b0y);
-                    if ((e += SW) >= qe) break;
-                    load_plane(clampe(e + SW), b0, b0x, b0y);
-                    step_one(e, b1, b1x, b1y);
-                    if ((e += SW) >= qe) break;
-                }
-            } else {
-                T b2[K][VX], b2x[K], b2y[VX];
-                load_plane(clampe(e0 + SW), b1, b1x, b1y);
-                for (int e = e0;;) {
-                    load_plane(clampe(e + 2 * SW), b2, b2x, b2y);
-                    step_one(e, b0, b0x, b0y);
-                    if ((e += SW) >= qe) break;
-                    load_plane(clampe(e + 2 * SW), b0, b0x, b0y);
-                    step_one(e, b1, b1x, b1y);
-                    if ((e += SW) >= qe) break;
-                    load_plane(clampe(e + 2 * SW), b1, b1x, b1y);
-                    step_one(e, b2, b2x, b2y);
-                    if ((e += SW) >= qe) break;
+#pragma unroll
+            for (int j = 0; j < PD; ++j) load_plane(clampe(e0 + j * SW), bv[j], bx[j], by[j]);
+            for (int e = e0;;) {
+#pragma unroll
+                for (int j = 0; j <= PD; ++j) {
+                    const int jl = (j + PD) % (PD + 1);  // the buffer that plane e + PD*SW goes to
+                    load_plane(clampe(e + PD * SW), bv[jl], bx[jl], by[jl]);
+                    step_one(e, bv[j], bx[j], by[j]);
+                    if ((e += SW) >= qe) goto planes_done;
                 }
             }
+        planes_done:;
         }
     };
 
@@ -684,19 +691,19 @@ __device__ __forceinline__ void reduce_previous(const StepArgs<T>& A) {
     if (threadIdx.x == 0) record_step(A.ctrl, num, den, um, 1);
 }
 
-template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT>
+template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD>
 __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR step_kernel(const StepArgs<T> A) {
     const int nb = (int)gridDim.x - (A.prev_nb > 0 ? 1 : 0);  // the last block reduces, if any
     if ((int)blockIdx.x == nb) {
         reduce_previous(A);
         return;
     }
-    step_body<T, VX, K, LX, WPB, WA, WX, NT>(A, blockIdx.x, nb, A.partials + 3 * blockIdx.x);
+    step_body<T, VX, K, LX, WPB, WA, WX, NT, PD>(A, blockIdx.x, nb, A.partials + 3 * blockIdx.x);
 }
 
 // Many problems in one launch: block g works on tile map[g].local of problem map[g].inst.
 // Each problem's blocks start at a multiple of 8, so the XCD-aware tile order holds per problem.
-template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT>
+template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD>
 __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR batch_step_kernel(const BlockMap* __restrict__ map,
                                                                         const StepArgs<T>* __restrict__ args) {
     const BlockMap m = map[blockIdx.x];
@@ -706,7 +713,7 @@ __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR batch_step
         if (A.prev_nb > 0) reduce_previous(A);
         return;
     }
-    step_body<T, VX, K, LX, WPB, WA, WX, NT>(A, m.local, m.nb, A.partials + 3 * m.local);
+    step_body<T, VX, K, LX, WPB, WA, WX, NT, PD>(A, m.local, m.nb, A.partials + 3 * m.local);
 }
 
 // ---------------------------------------------------------------------------
@@ -995,60 +1002,64 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
 // ---------------------------------------------------------------------------
 // Tile shapes and launchers.
 // ---------------------------------------------------------------------------
-// Compiled tile shapes: (id, type, VX, K, LX, WPB, WA, WX, NT).
-#define FDLB_TILES_FP32(X)          \
-    X(0, float, 4, 2, 64, 4, 1, 1, 1)     \
-    X(1, float, 4, 2, 16, 4, 1, 1, 1)     \
-    X(2, float, 4, 2, 32, 4, 1, 1, 1)     \
-    X(3, float, 4, 1, 64, 4, 1, 1, 1)     \
-    X(4, float, 4, 4, 16, 2, 1, 1, 1)     \
-    X(5, float, 2, 4, 64, 4, 1, 1, 1)     \
-    X(6, float, 1, 4, 64, 4, 1, 1, 0)     \
-    X(7, float, 1, 4, 1, 1, 1, 1, 0)      \
-    X(8, float, 1, 2, 16, 1, 1, 1, 0)     \
-    X(9, float, 4, 1, 16, 4, 1, 1, 1)     \
-    X(10, float, 1, 1, 16, 1, 1, 1, 0)    \
-    X(11, float, 4, 1, 16, 1, 4, 1, 0)    \
-    X(12, float, 1, 1, 64, 1, 8, 1, 0)    \
-    X(13, float, 4, 1, 64, 1, 4, 1, 0)    \
-    X(14, float, 1, 4, 1, 1, 4, 1, 0)     \
-    X(15, float, 2, 1, 32, 1, 8, 1, 0)    \
-    X(16, float, 4, 1, 16, 2, 2, 1, 0) \
-    X(17, float, 4, 2, 64, 1, 1, 4, 1) \
-    X(18, float, 4, 1, 64, 1, 1, 4, 1) \
-    X(19, float, 4, 2, 64, 2, 1, 2, 1) \
-    X(20, float, 4, 4, 64, 1, 1, 4, 1) \
-    X(21, float, 1, 1, 32, 1, 8, 1, 0) \
-    X(22, float, 2, 1, 64, 1, 8, 1, 0) \
-    X(23, float, 4, 2, 16, 1, 4, 1, 0) \
-    X(24, float, 2, 1, 32, 1, 4, 1, 0) \
-    X(25, float, 4, 2, 16, 1, 8, 1, 0)
+// Compiled tile shapes: id, type, VX, K, LX, WPB, WA, WX, NT, PD (velocity planes prefetched).
+#ifndef FDLB_TILES_FP32
+#define FDLB_TILES_FP32(X)                \
+    X(0, float, 4, 2, 64, 4, 1, 1, 1, 1)  \
+    X(1, float, 4, 2, 16, 4, 1, 1, 1, 1)  \
+    X(2, float, 4, 2, 32, 4, 1, 1, 1, 1)  \
+    X(3, float, 4, 1, 64, 4, 1, 1, 1, 1)  \
+    X(4, float, 4, 4, 16, 2, 1, 1, 1, 1)  \
+    X(5, float, 2, 4, 64, 4, 1, 1, 1, 1)  \
+    X(6, float, 1, 4, 64, 4, 1, 1, 0, 1)  \
+    X(7, float, 1, 4, 1, 1, 1, 1, 0, 1)   \
+    X(8, float, 1, 2, 16, 1, 1, 1, 0, 1)  \
+    X(9, float, 4, 1, 16, 4, 1, 1, 1, 1)  \
+    X(10, float, 1, 1, 16, 1, 1, 1, 0, 1) \
+    X(11, float, 4, 1, 16, 1, 4, 1, 0, 1) \
+    X(12, float, 1, 1, 64, 1, 8, 1, 0, 1) \
+    X(13, float, 4, 1, 64, 1, 4, 1, 0, 1) \
+    X(14, float, 1, 4, 1, 1, 4, 1, 0, 1)  \
+    X(15, float, 2, 1, 32, 1, 8, 1, 0, 1) \
+    X(16, float, 4, 1, 16, 2, 2, 1, 0, 1) \
+    X(17, float, 4, 2, 64, 1, 1, 4, 1, 1) \
+    X(18, float, 4, 1, 64, 1, 1, 4, 1, 1) \
+    X(19, float, 4, 2, 64, 2, 1, 2, 1, 1) \
+    X(20, float, 4, 4, 64, 1, 1, 4, 1, 1) \
+    X(21, float, 1, 1, 32, 1, 8, 1, 0, 1) \
+    X(22, float, 2, 1, 64, 1, 8, 1, 0, 1) \
+    X(23, float, 4, 2, 16, 1, 4, 1, 0, 1) \
+    X(24, float, 2, 1, 32, 1, 4, 1, 0, 1) \
+    X(25, float, 4, 2, 16, 1, 8, 1, 0, 1)
+#endif
 
-#define FDLB_TILES_FP64(X)          \
-    X(0, double, 2, 2, 64, 4, 1, 1, 1)    \
-    X(1, double, 2, 2, 16, 4, 1, 1, 1)    \
-    X(2, double, 2, 2, 32, 4, 1, 1, 1)    \
-    X(3, double, 1, 2, 64, 4, 1, 1, 0)    \
-    X(4, double, 1, 4, 1, 1, 1, 1, 0)     \
-    X(5, double, 1, 2, 16, 1, 1, 1, 0)    \
-    X(6, double, 2, 1, 64, 4, 1, 1, 1)    \
-    X(7, double, 1, 1, 16, 1, 1, 1, 0)    \
-    X(8, double, 2, 1, 16, 1, 4, 1, 0)    \
-    X(9, double, 1, 1, 64, 1, 8, 1, 0)    \
-    X(10, double, 1, 4, 1, 1, 4, 1, 0)    \
-    X(11, double, 2, 1, 32, 1, 8, 1, 0) \
-    X(12, double, 2, 2, 64, 1, 1, 4, 1) \
-    X(13, double, 2, 1, 64, 1, 1, 4, 1) \
-    X(14, double, 1, 1, 32, 1, 8, 1, 0) \
-    X(15, double, 2, 2, 16, 1, 4, 1, 0) \
-    X(16, double, 2, 1, 32, 1, 4, 1, 0) \
-    X(17, double, 1, 1, 1, 1, 4, 1, 0) \
-    X(18, double, 1, 2, 1, 1, 4, 1, 0) \
-    X(19, double, 1, 4, 1, 1, 8, 1, 0) \
-    X(20, double, 1, 1, 1, 1, 8, 1, 0)
+#ifndef FDLB_TILES_FP64
+#define FDLB_TILES_FP64(X)                 \
+    X(0, double, 2, 2, 64, 4, 1, 1, 1, 1)  \
+    X(1, double, 2, 2, 16, 4, 1, 1, 1, 1)  \
+    X(2, double, 2, 2, 32, 4, 1, 1, 1, 1)  \
+    X(3, double, 1, 2, 64, 4, 1, 1, 0, 1)  \
+    X(4, double, 1, 4, 1, 1, 1, 1, 0, 1)   \
+    X(5, double, 1, 2, 16, 1, 1, 1, 0, 1)  \
+    X(6, double, 2, 1, 64, 4, 1, 1, 1, 1)  \
+    X(7, double, 1, 1, 16, 1, 1, 1, 0, 1)  \
+    X(8, double, 2, 1, 16, 1, 4, 1, 0, 1)  \
+    X(9, double, 1, 1, 64, 1, 8, 1, 0, 1)  \
+    X(10, double, 1, 4, 1, 1, 4, 1, 0, 1)  \
+    X(11, double, 2, 1, 32, 1, 8, 1, 0, 1) \
+    X(12, double, 2, 2, 64, 1, 1, 4, 1, 1) \
+    X(13, double, 2, 1, 64, 1, 1, 4, 1, 1) \
+    X(14, double, 1, 1, 32, 1, 8, 1, 0, 1) \
+    X(15, double, 2, 2, 16, 1, 4, 1, 0, 1) \
+    X(16, double, 2, 1, 32, 1, 4, 1, 0, 1) \
+    X(17, double, 1, 1, 1, 1, 4, 1, 0, 1)  \
+    X(18, double, 1, 2, 1, 1, 4, 1, 0, 1)  \
+    X(19, double, 1, 4, 1, 1, 8, 1, 0, 1)  \
+    X(20, double, 1, 1, 1, 1, 8, 1, 0, 1)
+#endif
 
 const std::vector<TileShape>& tile_shapes(int precision) {
-#define FDLB_SHAPE(id, T, VX, K, LX, WPB, WA, WX, NT) TileShape{VX, LX, K, WPB, WA, WX, NT},
+#define FDLB_SHAPE(id, T, VX, K, LX, WPB, WA, WX, NT, PD) TileShape{VX, LX, K, WPB, WA, WX, NT, PD},
     static const std::vector<TileShape> s32 = {FDLB_TILES_FP32(FDLB_SHAPE)};
     static const std::vector<TileShape> s64 = {FDLB_TILES_FP64(FDLB_SHAPE)};
 #undef FDLB_SHAPE
@@ -1058,9 +1069,9 @@ const std::vector<TileShape>& tile_shapes(int precision) {
 template <>
 void launch_step<float>(int tile, const StepArgs<float>& a, int nblocks, hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT)                                                              \
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                              \
     case id:                                                                                             \
-        hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
+        hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
                            stream, a);                                                                   \
         break;
         FDLB_TILES_FP32(FDLB_CASE)
@@ -1073,9 +1084,9 @@ void launch_step<float>(int tile, const StepArgs<float>& a, int nblocks, hipStre
 template <>
 void launch_step<double>(int tile, const StepArgs<double>& a, int nblocks, hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT)                                                              \
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                              \
     case id:                                                                                             \
-        hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
+        hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
                            stream, a);                                                                   \
         break;
         FDLB_TILES_FP64(FDLB_CASE)
@@ -1089,9 +1100,9 @@ template <>
 void launch_batch_step<float>(int tile, const BlockMap* map, const StepArgs<float>* args, int nblocks,
                               hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT)                                                                    \
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                                    \
     case id:                                                                                                   \
-        hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
+        hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
                            stream, map, args);                                                                 \
         break;
         FDLB_TILES_FP32(FDLB_CASE)
@@ -1105,9 +1116,9 @@ template <>
 void launch_batch_step<double>(int tile, const BlockMap* map, const StepArgs<double>* args, int nblocks,
                                hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT)                                                                    \
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                                    \
     case id:                                                                                                   \
-        hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
+        hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
                            stream, map, args);                                                                 \
         break;
         FDLB_TILES_FP64(FDLB_CASE)
