@@ -38,7 +38,11 @@ struct VelEntry {
     T xx, xy;         // xi_x, xi_y
     T nux, nuy;       // dt |xi_x| N_x, dt |xi_y| N_y (0 along a periodic single-cell axis)
     int32_t alpha;    // plane index of this velocity in the state
-    int32_t pad[3];
+    int32_t pad;
+    // byte offset of that plane in a population buffer of type T (alpha * plane * sizeof(T)); held
+    // at 4-byte alignment so that the float table keeps the alignment, and the compiler the load
+    // grouping, that the bandwidth-bound tiles were tuned with
+    int64_t off __attribute__((packed, aligned(4)));
 };
 
 // Per-wall constants of Eq. (9) in deviation form (double).  For the wall's

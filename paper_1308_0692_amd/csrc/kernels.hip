@@ -128,6 +128,11 @@ __device__ __forceinline__ int load_alpha(const VelEntry<T>* p, const int e) {
     typedef const __attribute__((address_space(4))) VelEntry<T>* cptr;
     return ((cptr)p)[e].alpha;
 }
+template <class T>
+__device__ __forceinline__ int64_t load_off(const VelEntry<T>* p, const int e) {
+    typedef const __attribute__((address_space(4))) VelEntry<T>* cptr;
+    return ((cptr)p)[e].off;
+}
 
 // The value v holds in lane (lane - D); lanes whose source lies outside the wave get a value
 // that callers never use.  A shift by one lane is a DPP wave shift (a register move: no LDS
@@ -398,6 +403,16 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
             }
         }
 
+        // Plane e of the source.  Tiles with one or two cells per lane take the plane's byte offset
+        // precomputed in the table: one 64-bit add instead of a 64-bit multiply on the scalar
+        // unit, which the many small waves of such tiles keep busy (measured: 5-9 % per step on
+        // 64^2-192^2 grids); wider tiles are bound by HBM and keep the multiply, with which
+        // their loads issue best.
+        constexpr bool OFF = K * VX <= 2;
+        auto plane_of = [&](const T* base, const int e) -> const T* {
+            if constexpr (OFF) return (const T*)((const char*)base + load_off(A.vel, e));
+            else return base + (int64_t)load_alpha(A.vel, e) * plane;
+        };
         // Loads of one velocity plane: this lane's cells and the halo cells it relaxes itself.
         // Every load is unconditional, from an address that is always inside the plane (rows
         // past the grid read its last row, a halo that is not needed reads the lane's own cell;
@@ -414,7 +429,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
         }
         const int64_t ohy = (int64_t)((ymode == MODE_LOAD) ? yh : (y0 < ny ? y0 : ny - 1)) * nx + xc;
         auto load_plane = [&](const int e, T (&hv)[K][VX], T (&hx)[K], T (&hy)[VX]) {
-            const T* __restrict__ s = A.src + (int64_t)load_alpha(A.vel, e) * plane;
+            const T* __restrict__ s = plane_of(A.src, e);
 #pragma unroll
             for (int r = 0; r < K; ++r) vload<VX>(hv[r], s + orow[r]);
 #pragma unroll
@@ -434,7 +449,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
 
         auto step_one = [&](const int e, const T (&g)[K][VX], const T (&gxh_in)[K], const T (&gyh_in)[VX]) {
             const VelEntry<T> c = load_vel(A.vel, e);
-            T* __restrict__ d = A.dst + (int64_t)c.alpha * plane;
+            T* __restrict__ d = OFF ? (T*)((char*)A.dst + load_off(A.vel, e)) : A.dst + (int64_t)c.alpha * plane;
             T gxh[K], gyh[VX];
 #pragma unroll
             for (int r = 0; r < K; ++r) gxh[r] = gxh_in[r];

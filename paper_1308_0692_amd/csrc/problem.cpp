@@ -248,6 +248,7 @@ static std::vector<VelEntry<T>> vel_table(const fdlb_problem& p) {
         c.nux = (T)(p.dt * std::fabs(x) * p.nux_scale);
         c.nuy = (T)(p.dt * std::fabs(y) * p.nuy_scale);
         c.alpha = a;
+        c.off = (int64_t)a * p.plane * (int64_t)sizeof(T);
     }
     return v;
 }
