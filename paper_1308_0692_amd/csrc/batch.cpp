@@ -310,7 +310,17 @@ static void upload_map(fdlb_batch& b) {
         if (!G.used) continue;
         std::vector<BlockMap> m;
         const TileShape& t = tile_shapes(prec_of_group(g))[G.tile];
-        for (int i : b.active) {
+        // Longest blocks first (more velocities per cell, then more blocks): the hardware hands
+        // out blocks in index order, so the last ones to start are the short ones and the launch
+        // ends with less of the chip idle.  A block's work depends only on (inst, local), so the
+        // order changes no result.
+        std::vector<int> order(b.active.begin(), b.active.end());
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            const fdlb_problem &px = *b.probs[x], &py = *b.probs[y];
+            if (px.q != py.q) return px.q > py.q;
+            return nblocks_tile(px, t) > nblocks_tile(py, t);
+        });
+        for (int i : order) {
             if (group_of(*b.probs[i]) != g) continue;
             const int nb = nblocks_tile(*b.probs[i], t);
             for (int l = 0; l < nb; ++l) m.push_back(BlockMap{i, l, nb, 0});
