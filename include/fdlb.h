@@ -360,8 +360,10 @@ int fdlb_batch_autotune(fdlb_batch *b, int steps, double *best_ms_per_step);
 /*
  * FDLB_MIXED batches: each instance leaves float on its own (see FDLB_MIXED_SWITCH_R); while
  * some instances run in float and others in double, every step launches the two groups one
- * after the other.  The tile calls above act on the float group; the double group uses the
- * built-in choice.  fdlb_batch_active_precision gives instance i's current precision.
+ * after the other.  The tile calls above act on the float group; the double group starts with
+ * the built-in choice, and fdlb_batch_autotune also times its shapes with every instance
+ * promoted to double (best_ms_per_step reports the float group's figure).
+ * fdlb_batch_active_precision gives instance i's current precision.
  */
 int fdlb_batch_active_precision(const fdlb_batch *b, int i);
 /*

@@ -578,6 +578,50 @@ double batch_autotune(fdlb_batch& b, int steps) {
     return best;
 }
 
+// Tile of a mixed batch's double group: every member promoted, each fitting shape timed over
+// `steps` steps of the whole batch (members re-seeded afterwards, back in float).
+static void batch_autotune_promoted(fdlb_batch& b, int steps) {
+    if (b.precision != FDLB_MIXED || !b.grp[1].used) return;
+    hipEvent_t e0, e1;
+    FDLB_HIP(hipEventCreate(&e0));
+    FDLB_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_tile = b.grp[1].tile;
+    try {
+        for (int t = 0; t < (int)tile_shapes(FDLB_FP64).size(); ++t) {
+            if (!tile_fits_all(b, 1, t)) continue;
+            group_set_tile(b, 1, t);
+            for (size_t i = 0; i < b.probs.size(); ++i) {
+                init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+                promote(*b.probs[i]);
+            }
+            upload_args(b);
+            b.active.clear();
+            for (size_t i = 0; i < b.probs.size(); ++i) b.active.push_back((int)i);
+            upload_map(b);
+            enqueue_batch_chunk(b, 2, 0, false);
+            FDLB_HIP(hipEventRecord(e0, b.stream));
+            enqueue_batch_chunk(b, steps, 0, false);
+            FDLB_HIP(hipEventRecord(e1, b.stream));
+            FDLB_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            FDLB_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / steps < best) {
+                best = ms / steps;
+                best_tile = t;
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    group_set_tile(b, 1, best_tile);
+    for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+}
+
 }  // namespace fdlb
 
 // ---- C ABI -------------------------------------------------------------------------------
@@ -691,6 +735,7 @@ int fdlb_batch_active_precision(const fdlb_batch* b, int i) {
 int fdlb_batch_autotune(fdlb_batch* b, int steps, double* best_ms_per_step) {
     return guard_call([&] {
         const double ms = batch_autotune(bh(b), steps);
+        batch_autotune_promoted(bh(b), steps);
         if (best_ms_per_step) *best_ms_per_step = ms;
         return FDLB_OK;
     });

@@ -1045,7 +1045,9 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(22, float, 2, 1, 64, 1, 8, 1, 0, 1) \
     X(23, float, 4, 2, 16, 1, 4, 1, 0, 1) \
     X(24, float, 2, 1, 32, 1, 4, 1, 0, 1) \
-    X(25, float, 4, 2, 16, 1, 8, 1, 0, 1)
+    X(25, float, 4, 2, 16, 1, 8, 1, 0, 1) \
+    X(26, float, 1, 1, 1, 1, 8, 1, 0, 1) \
+    X(27, float, 1, 2, 1, 1, 4, 1, 0, 1)
 #endif
 
 #ifndef FDLB_TILES_FP64

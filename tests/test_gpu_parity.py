@@ -130,6 +130,26 @@ def test_fp32_every_tile_matches_oracle(F, case):
         assert np.abs(rho - r0).max() <= 2e-5
 
 
+@pytest.mark.parametrize("case", [W.couette(200, kn=0.1), W.couette(37, kn=0.4, qy=("half", 3))],
+                         ids=["couette200", "couette37"])
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_every_column_tile_matches_oracle(F, case, prec, bar):
+    """Single-cell-wide (periodic x) grids run on column tiles: every such shape, a full column
+    of several tiles and a ragged one, from a non-equilibrium state."""
+    op = OP.from_case(case)
+    gp = F.Problem(case, precision=prec)
+    fg, fo = both_perturbed(gp, op, seed=14)
+    ref = op.step(fo, 9)
+    tiles = _fitting_tiles(F, case, prec)
+    assert len(tiles) >= 3
+    for t in tiles:
+        gp.set_tile(t)
+        gp.upload(fg)
+        gp.step(9)
+        e = eps_f(gp.download(), ref, op.w)
+        assert e <= bar, (t, F.tile_describe(prec, t), e)
+
+
 @pytest.mark.parametrize("case", [W.couette_x(64, kn=0.2), W.couette(33, kn=0.7, qy=("half", 3)),
                                   W.cavity(2, kn=1.0, order=2), W.cavity(3, ny=5, kn=1.0, order=2)],
                          ids=["couettex64", "couette33", "cavity2", "cavity3x5"])
