@@ -193,7 +193,9 @@ __device__ __forceinline__ void wave_partials(const double* __restrict__ pp, int
 // A problem whose solve has converged or diverged stops being updated (its state stays at
 // the step that met the criterion), when the control block asks for it.
 __device__ __forceinline__ bool frozen(const double* __restrict__ ctrl) {
-    return ctrl[CTRL_FREEZE] != 0.0 && (ctrl[CTRL_FIRST_BELOW] >= 0.0 || ctrl[CTRL_DIVERGED] >= 0.0);
+    // (bitwise, not short-circuit: the three loads are issued together, one round trip)
+    const double f = ctrl[CTRL_FREEZE], a = ctrl[CTRL_FIRST_BELOW], d = ctrl[CTRL_DIVERGED];
+    return (f != 0.0) & ((a >= 0.0) | (d >= 0.0));
 }
 
 // Residual of a step from its sums: R = sqrt(sum |du|^2 / sum |u|^2).  A state at rest that
@@ -282,11 +284,12 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
 
     // Wall emission parameters of this step (Eqs. 8-9): rho_w - 1 and u_w rho_w per wall face.
     const double omega = A.omega_d;
-    const bool on_left = xv && x0 == 0 && A.wall[LEFT].active;
-    const bool on_right = xv && (x0 + VX == nx) && A.wall[RIGHT].active;
-    const bool on_bot = xv && y0 == 0 && A.wall[BOTTOM].active;
+    // (bitwise, not short-circuit: no branch, and no round trip, per wall flag)
+    const bool on_left = xv & (x0 == 0) & (A.wall[LEFT].active != 0);
+    const bool on_right = xv & (x0 + VX == nx) & (A.wall[RIGHT].active != 0);
+    const bool on_bot = xv & (y0 == 0) & (A.wall[BOTTOM].active != 0);
     const int r_top = ny - 1 - y0;
-    const bool on_top = xv && r_top >= 0 && r_top < K && A.wall[TOP].active;
+    const bool on_top = xv & (r_top >= 0) & (r_top < K) & (A.wall[TOP].active != 0);
     const int xw = on_left ? LEFT : RIGHT;
     const int yw = on_bot ? BOTTOM : TOP;
 
