@@ -207,3 +207,35 @@ def test_domain_lengths_default_and_validation(F):
         with pytest.raises(F.FdlbError) as e:
             F.Problem(desc=d, bind=False)
         assert e.value.code == F._lib.EINVAL
+
+
+def test_kernel_resource_report_parser():
+    from paper_1308_0692_amd import build as B
+    text = """k.hip:9:1: remark: Function Name: _Z3fooPf [-Rpass-analysis=kernel-resource-usage]
+    9 | __global__ void foo(float* p) {}
+      | ^
+k.hip:9:1: remark:     SGPRs: 18 [-Rpass-analysis=kernel-resource-usage]
+k.hip:9:1: remark:     VGPRs: 59 [-Rpass-analysis=kernel-resource-usage]
+k.hip:9:1: remark:     AGPRs: 0 [-Rpass-analysis=kernel-resource-usage]
+k.hip:9:1: remark:     ScratchSize [bytes/lane]: 12 [-Rpass-analysis=kernel-resource-usage]
+k.hip:9:1: remark:     Occupancy [waves/SIMD]: 8 [-Rpass-analysis=kernel-resource-usage]
+k.hip:9:1: remark:     LDS Size [bytes/block]: 0 [-Rpass-analysis=kernel-resource-usage]
+"""
+    r = B.parse_resources(text)
+    assert r == {"_Z3fooPf": {"sgpr": 18, "vgpr": 59, "agpr": 0, "scratch": 12, "waves_per_simd": 8, "lds": 0}}
+
+
+def test_built_step_kernels_use_no_scratch():
+    """The build's resource report (written next to the objects): no step kernel spills or keeps
+    a stack copy, and every one fits at least one wave per SIMD."""
+    import json
+    import os
+    from paper_1308_0692_amd import build as B
+    path = os.path.join(B.BUILD, "kernel_resources.json")
+    if not os.path.exists(path):
+        pytest.skip("no build report (library built elsewhere)")
+    rep = json.load(open(path))
+    steps = {k: v for k, v in rep.items() if "step_kernel" in k}
+    assert steps
+    assert all(v.get("scratch", 0) == 0 for v in steps.values())
+    assert all(v.get("waves_per_simd", 0) >= 1 for v in steps.values())
