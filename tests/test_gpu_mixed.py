@@ -154,3 +154,26 @@ def test_batch_mixed_matches_oracle(F):
         r0, ux0, uy0 = op.moments(fo)
         assert eps_u(ux, uy, ux0, uy0) <= 2e-5, i
         assert float(np.abs(rho - r0).max()) <= 2e-5, i
+
+
+def test_batch_mixed_autotune_keeps_results(F):
+    """Autotuning a mixed batch times both groups' shapes (the double group with every member
+    promoted) and re-seeds the members; the solve afterwards still reaches the oracle's
+    converged solution within the FP32 bar."""
+    cases = [W.cavity(40, ny=32, kn=0.4, order=2), W.cavity(24, ny=56, kn=3.0, order=3),
+             W.cavity(32, kn=0.05, order=2)]
+    b = F.Batch(cases, precision="mixed")
+    assert b.autotune(steps=3) > 0
+    for i in range(len(cases)):
+        assert b.active_precision(i) == "fp32", i   # re-seeded in float
+        b.init_equilibrium(i)
+    status, reps = b.solve(1e-9, 300000, check_every=100)
+    assert status == 0
+    for i, case in enumerate(cases):
+        assert b.active_precision(i) == "fp64", i
+        op = OP.from_case(case)
+        fo, steps, hist = op.solve(op.equilibrium(), 1e-11, 600000)
+        rho, ux, uy, _ = b.moments(i)
+        r0, ux0, uy0 = op.moments(fo)
+        assert eps_u(ux, uy, ux0, uy0) <= 2e-5, i
+        assert float(np.abs(rho - r0).max()) <= 2e-5, i
