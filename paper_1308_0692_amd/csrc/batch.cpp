@@ -544,19 +544,23 @@ double batch_autotune(fdlb_batch& b, int steps) {
     const int g = primary_group(b);
     double best = 1e300;
     int best_tile = b.grp[g].tile;
+    // Seeded once (every member in the primary group's precision): a step's cost does not depend
+    // on the values it marches, so the shapes are timed one after another on the evolving state,
+    // with the step parity carried over, and the members are re-seeded once at the end.
+    for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+    int parity = 0;
     try {
         for (int t = 0; t < (int)tile_shapes(prec_of_group(g)).size(); ++t) {
             if (!tile_fits_all(b, g, t)) continue;
             group_set_tile(b, g, t);
-            // Re-seeding starts every member in the primary group's precision.
-            for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
             upload_args(b);
             b.active.clear();
             for (size_t i = 0; i < b.probs.size(); ++i) b.active.push_back((int)i);
             upload_map(b);
-            enqueue_batch_chunk(b, 2, 0, false);
+            enqueue_batch_chunk(b, 2, parity, false);
             FDLB_HIP(hipEventRecord(e0, b.stream));
-            enqueue_batch_chunk(b, steps, 0, false);
+            enqueue_batch_chunk(b, steps, parity, false);
+            if (steps & 1) parity ^= 1;
             FDLB_HIP(hipEventRecord(e1, b.stream));
             FDLB_HIP(hipEventSynchronize(e1));
             float ms = 0;
@@ -578,8 +582,9 @@ double batch_autotune(fdlb_batch& b, int steps) {
     return best;
 }
 
-// Tile of a mixed batch's double group: every member promoted, each fitting shape timed over
-// `steps` steps of the whole batch (members re-seeded afterwards, back in float).
+// Tile of a mixed batch's double group: every member promoted (once), each fitting shape timed
+// over `steps` steps of the whole batch on the evolving state (members re-seeded afterwards,
+// back in float).
 static void batch_autotune_promoted(fdlb_batch& b, int steps) {
     if (b.precision != FDLB_MIXED || !b.grp[1].used) return;
     hipEvent_t e0, e1;
@@ -587,21 +592,23 @@ static void batch_autotune_promoted(fdlb_batch& b, int steps) {
     FDLB_HIP(hipEventCreate(&e1));
     double best = 1e300;
     int best_tile = b.grp[1].tile;
+    for (size_t i = 0; i < b.probs.size(); ++i) {
+        init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+        promote(*b.probs[i]);
+    }
+    int parity = 0;
     try {
         for (int t = 0; t < (int)tile_shapes(FDLB_FP64).size(); ++t) {
             if (!tile_fits_all(b, 1, t)) continue;
             group_set_tile(b, 1, t);
-            for (size_t i = 0; i < b.probs.size(); ++i) {
-                init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
-                promote(*b.probs[i]);
-            }
             upload_args(b);
             b.active.clear();
             for (size_t i = 0; i < b.probs.size(); ++i) b.active.push_back((int)i);
             upload_map(b);
-            enqueue_batch_chunk(b, 2, 0, false);
+            enqueue_batch_chunk(b, 2, parity, false);
             FDLB_HIP(hipEventRecord(e0, b.stream));
-            enqueue_batch_chunk(b, steps, 0, false);
+            enqueue_batch_chunk(b, steps, parity, false);
+            if (steps & 1) parity ^= 1;
             FDLB_HIP(hipEventRecord(e1, b.stream));
             FDLB_HIP(hipEventSynchronize(e1));
             float ms = 0;

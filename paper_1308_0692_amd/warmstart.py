@@ -29,13 +29,20 @@ def cavity_desc(n: int, kn: float, u_w: float = 0.01, order: int = 4, precision:
 
 
 def generate(kns: Iterable[float], n: int = 64, order: int = 4, u_w: float = 0.01, tol: float = 1e-8,
-             precision: str = "mixed", check_every: int = 200, max_steps: int = 400000, device="cuda:0"):
+             precision: str = "mixed", check_every: int = 200, max_steps: int = 400000, device="cuda:0",
+             autotune: bool = True):
     """Solve one cavity per Kn (as one batch) and return (inputs, targets, reports): device
-    float32 tensors of shape (len(kns) n^2, 3) and the per-instance solve reports."""
+    float32 tensors of shape (len(kns) n^2, 3) and the per-instance solve reports.  autotune:
+    time the compiled tile shapes on the batch first (a few steps each; the built-in choice is
+    made for single problems)."""
     import torch
     kns = [float(k) for k in kns]
     descs = [cavity_desc(n, kn, u_w, order, precision) for kn in kns]
     b = Batch(None, descs=descs, device=device)
+    t0 = time.perf_counter()
+    if autotune:
+        b.autotune(steps=3)
+    tune_s = time.perf_counter() - t0
     for i in range(len(kns)):
         b.init_equilibrium(i)
     t0 = time.perf_counter()
@@ -48,7 +55,7 @@ def generate(kns: Iterable[float], n: int = 64, order: int = 4, u_w: float = 0.0
         b.field_samples(i, X[i * cells:(i + 1) * cells], T[i * cells:(i + 1) * cells])
     torch.cuda.synchronize(device)
     b.close()
-    return X, T, {"status": status, "wall_s": wall, "reports": reps}
+    return X, T, {"status": status, "wall_s": wall, "autotune_s": tune_s, "reports": reps}
 
 
 def train(net: Mlp, X, T, epochs: int, batch: int, lr: float = 3e-3, lr_final: float = 1e-5, seed: int = 0,
@@ -120,8 +127,10 @@ def experiment(train_kn, heldout_kn, train_n: int = 64, order: int = 4, u_w: flo
     X, T, info = generate(train_kn, n=train_n, order=order, u_w=u_w, tol=tol, precision=precision)
     out["generate_s"] = round(time.perf_counter() - t0, 3)
     out["generate_solve_s"] = round(info["wall_s"], 3)
+    out["generate_autotune_s"] = round(info["autotune_s"], 3)
     out["samples"] = int(X.shape[0])
-    log(f"  generated {X.shape[0]} samples from {len(train_kn)} solves in {out['generate_s']:.1f} s")
+    log(f"  generated {X.shape[0]} samples from {len(train_kn)} solves in {out['generate_s']:.1f} s "
+        f"(tile autotune {info['autotune_s']:.1f} s, solve {info['wall_s']:.1f} s)")
     net = Mlp(hidden=4, max_batch=batch, seed=seed_value)
     t0 = time.perf_counter()
     losses = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed_value, log=log)
