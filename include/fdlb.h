@@ -342,6 +342,9 @@ int fdlb_batch_solve(fdlb_batch *b, double tol, int64_t max_steps, int32_t check
                      int32_t use_graph, fdlb_report *reports);
 int fdlb_batch_moments(fdlb_batch *b, int i, double *rho, double *ux, double *uy, double *pxy);
 int fdlb_batch_state_download(fdlb_batch *b, int i, double *f_host);
+/* Number of velocities of instance i (the Q of its state layout), or FDLB_EINVAL for an index
+ * out of range. */
+int fdlb_batch_problem_q(const fdlb_batch *b, int i);
 /*
  * Instance i's raw populations from a host array in the layout of fdlb_state_upload
  * ([Q][ny][nx] float64, Eq. (2) velocities); like fdlb_batch_init_equilibrium it restarts

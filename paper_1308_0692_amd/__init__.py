@@ -224,16 +224,6 @@ def stream_copy(dst, src, nbytes: int, stream=None):
                                     int(nbytes), C.c_void_p(s.cuda_stream)))
 
 
-def _velocity_count(desc) -> int:
-    """Q of a problem description (a host-side handle, created and destroyed at once)."""
-    h = C.c_void_p()
-    check(_lib.lib.fdlb_problem_create(C.byref(desc), C.byref(h)))
-    try:
-        return _lib.lib.fdlb_problem_q(h)
-    finally:
-        _lib.lib.fdlb_problem_destroy(h)
-
-
 class Batch:
     """Many independent problems solved together (one launch per step for all of them)."""
 
@@ -248,7 +238,7 @@ class Batch:
         check(_lib.lib.fdlb_batch_create(arr, self.n, C.byref(h)))
         self._h = h
         self.shapes = [(d.nx, d.ny) for d in descs]
-        self.qs = [_velocity_count(d) for d in descs]
+        self.qs = [_lib.lib.fdlb_batch_problem_q(h, i) for i in range(self.n)]
         self.precision = _lib.PRECISION_NAMES[descs[0].precision]
         self.device = device
         self._stream = stream if stream is not None else torch.cuda.Stream(device=device)

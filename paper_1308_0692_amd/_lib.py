@@ -106,6 +106,7 @@ def _load():
         "fdlb_batch_moments": (C.c_int, [vp, C.c_int, dp, dp, dp, dp]),
         "fdlb_batch_state_download": (C.c_int, [vp, C.c_int, dp]),
         "fdlb_batch_state_upload": (C.c_int, [vp, C.c_int, dp]),
+        "fdlb_batch_problem_q": (C.c_int, [vp, C.c_int]),
         "fdlb_batch_set_tile": (C.c_int, [vp, C.c_int]),
         "fdlb_batch_get_tile": (C.c_int, [vp]),
         "fdlb_batch_autotune": (C.c_int, [vp, C.c_int, dp]),

@@ -60,6 +60,7 @@ struct fdlb_batch {
     hipStream_t stream = nullptr;
     bool bound = false;
     double* pinned = nullptr;       // n x 8 control doubles
+    double* member_pinned = nullptr;  // n x 64 doubles: the members' staging buffers, one allocation
     std::vector<int> active;        // problems in the current block maps
     int map_version = 0;
     // (k, parity, map version, float tile, double tile)
@@ -67,6 +68,8 @@ struct fdlb_batch {
     ~fdlb_batch() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         if (pinned) (void)hipHostFree(pinned);
+        probs.clear();  // the members first: their staging buffers are slices of member_pinned
+        if (member_pinned) (void)hipHostFree(member_pinned);
     }
 };
 
@@ -193,6 +196,15 @@ void batch_bind(fdlb_batch& b, void* d_state, void* d_work, void* stream) {
     b.d_state = (char*)d_state;
     b.d_work = (char*)d_work;
     b.stream = (hipStream_t)stream;
+    // One pinned allocation for all members' staging buffers (thousands of small pinned
+    // allocations, and their frees, cost about a millisecond each).
+    if (!b.member_pinned) {
+        FDLB_HIP(hipHostMalloc((void**)&b.member_pinned, b.probs.size() * 64 * sizeof(double), hipHostMallocDefault));
+        for (size_t i = 0; i < b.probs.size(); ++i) {
+            b.probs[i]->pinned = b.member_pinned + 64 * i;
+            b.probs[i]->own_pinned = false;
+        }
+    }
     for (size_t i = 0; i < b.probs.size(); ++i) bind(*b.probs[i], b.d_state + b.state_off[i], b.d_work + b.work_off[i], stream);
     if (!b.pinned)
         FDLB_HIP(hipHostMalloc((void**)&b.pinned, b.probs.size() * 8 * sizeof(double), hipHostMallocDefault));
@@ -733,6 +745,11 @@ int fdlb_batch_set_retile(fdlb_batch* b, int max_members) {
 }
 
 int fdlb_batch_get_tile(const fdlb_batch* b) { return b ? b->grp[primary_group(*b)].tile : FDLB_EINVAL; }
+
+int fdlb_batch_problem_q(const fdlb_batch* b, int i) {
+    if (!b || i < 0 || i >= (int)b->probs.size()) return FDLB_EINVAL;
+    return b->probs[i]->q;
+}
 
 int fdlb_batch_active_precision(const fdlb_batch* b, int i) {
     if (!b || i < 0 || i >= (int)b->probs.size()) return FDLB_EINVAL;

@@ -249,7 +249,8 @@ struct fdlb_problem {
     bool bound = false;
     bool seeded = false;
     int parity = 0;                        // population buffer holding the current state
-    double* pinned = nullptr;              // small pinned host buffer for control reads
+    double* pinned = nullptr;              // small pinned host buffer for control reads (64 doubles)
+    bool own_pinned = true;                // false: a slice of its batch's block, freed by the batch
     bool freeze_on = false;                // the device control block has the freeze flag set
     // captured graphs keyed by (steps per replay, precision, tile, starting parity)
     std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;

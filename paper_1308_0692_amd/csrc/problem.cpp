@@ -5,13 +5,16 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "fdlb_internal.h"
 
 fdlb_problem::~fdlb_problem() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
-    if (pinned) (void)hipHostFree(pinned);
+    if (pinned && own_pinned) (void)hipHostFree(pinned);
 }
 
 namespace fdlb {
@@ -22,7 +25,28 @@ constexpr double SQRT_2PI = 2.50662827463100050241576528481104525;
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+void rule_uncached(int kind, int n, std::vector<double>& x, std::vector<double>& w);
+
+// Nodes and weights of a rule, computed once per (kind, n) for the process (the extended-
+// precision construction costs ~1 ms; a batch of thousands of problems shares a few rules).
 void rule(int kind, int n, std::vector<double>& x, std::vector<double>& w) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, std::pair<std::vector<double>, std::vector<double>>> cache;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find({kind, n});
+        if (it != cache.end()) {
+            x = it->second.first;
+            w = it->second.second;
+            return;
+        }
+    }
+    rule_uncached(kind, n, x, w);
+    std::lock_guard<std::mutex> lock(mu);
+    cache.emplace(std::make_pair(kind, n), std::make_pair(x, w));
+}
+
+void rule_uncached(int kind, int n, std::vector<double>& x, std::vector<double>& w) {
     if (kind == FDLB_HALF) {
         if (n < 1 || n > 16) throw Error(FDLB_EINVAL, "half-range rule needs 1..16 nodes per half");
         x.resize(2 * n);

@@ -239,3 +239,23 @@ def test_built_step_kernels_use_no_scratch():
     assert steps
     assert all(v.get("scratch", 0) == 0 for v in steps.values())
     assert all(v.get("waves_per_simd", 0) >= 1 for v in steps.values())
+
+
+def test_batch_reports_each_members_velocity_count():
+    """A batch is created on the host alone; each member's Q comes from its own velocity sets,
+    and an index out of range is an error."""
+    from paper_1308_0692_amd import _lib
+    descs = [_lib.make_desc(32, 32, False, False, (0.0, 0.01, 0.0, 0.0), 0.1, ("half", 2), ("half", 2)),
+             _lib.make_desc(40, 40, False, False, (0.0, 0.01, 0.0, 0.0), 1.0, ("half", 4), ("half", 3)),
+             _lib.make_desc(24, 16, False, False, (0.0, 0.01, 0.0, 0.0), 0.3, ("half", 3), ("half", 4))]
+    for d in descs:
+        d.precision = _lib.PRECISIONS["fp32"]
+    arr = (_lib.ProblemDesc * len(descs))(*descs)
+    h = C.c_void_p()
+    assert _lib.lib.fdlb_batch_create(arr, len(descs), C.byref(h)) == 0
+    try:
+        assert [_lib.lib.fdlb_batch_problem_q(h, i) for i in range(3)] == [16, 48, 48]
+        assert _lib.lib.fdlb_batch_problem_q(h, 3) == _lib.EINVAL
+        assert _lib.lib.fdlb_batch_problem_q(h, -1) == _lib.EINVAL
+    finally:
+        _lib.lib.fdlb_batch_destroy(h)
