@@ -432,6 +432,18 @@ int fdlb_mlp_last_loss(fdlb_mlp *m, double *loss);
 int fdlb_mlp_adam_step(fdlb_mlp *m, double lr, double beta1, double beta2, double eps, int64_t step);
 
 /*
+ * `steps` minibatch steps, each fdlb_mlp_backward then fdlb_mlp_adam_step, enqueued back to back
+ * (the same kernels in the same order as the two calls, hence the same parameters to the bit).
+ * Step s uses the samples d_rows[s batch .. min((s + 1) batch, n_rows)) (device int32 row indices,
+ * e.g. a permutation of 0..n_rows-1), learning rate lr[s] (host array of `steps` values) and Adam
+ * step count first_step + s.  FDLB_EINVAL if batch is not in 1..max_batch, if a step would start
+ * past n_rows, or for NULL arrays.  Asynchronous on the bound stream.
+ */
+int fdlb_mlp_train(fdlb_mlp *m, const float *d_in, const float *d_target, const int32_t *d_rows, int64_t n_rows,
+                   int64_t batch, int64_t steps, const double *lr, double beta1, double beta2, double eps,
+                   int64_t first_step);
+
+/*
  * Predicted fields of an nx x ny problem with Knudsen number kn and fastest wall speed
  * u_w, into device arrays of nx ny floats ([y][x]): rho = 1 + u_w y_0, u = u_w (y_1, y_2).
  */

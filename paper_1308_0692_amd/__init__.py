@@ -422,6 +422,19 @@ class Mlp:
                                           int(self.step_count)))
         self._leave()
 
+    def train_steps(self, x, t, rows, batch: int, lrs, beta1: float = 0.9, beta2: float = 0.999,
+                    eps: float = 1e-8):
+        """len(lrs) minibatch steps (backward, then Adam) enqueued in one call: step s takes the
+        samples rows[s batch : (s + 1) batch] (int32 device tensor) and learning rate lrs[s];
+        the same parameters, to the bit, as that many backward / adam_step calls."""
+        lr = np.ascontiguousarray(lrs, dtype=np.float64)
+        self._enter(x, t, rows)
+        check(_lib.lib.fdlb_mlp_train(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                      C.c_void_p(rows.data_ptr()), int(rows.numel()), int(batch), int(lr.size),
+                                      _lib._dp(lr), float(beta1), float(beta2), float(eps), int(self.step_count + 1)))
+        self.step_count += int(lr.size)
+        self._leave()
+
     def predict_fields(self, kn: float, nx: int, ny: int, u_w: float):
         """Device float32 (rho, ux, uy), each of shape (ny, nx)."""
         torch = _torch()

@@ -122,6 +122,8 @@ def _load():
         "fdlb_mlp_backward": (C.c_int, [vp, vp, vp, vp, i64]),
         "fdlb_mlp_last_loss": (C.c_int, [vp, dp]),
         "fdlb_mlp_adam_step": (C.c_int, [vp, C.c_double, C.c_double, C.c_double, C.c_double, i64]),
+        "fdlb_mlp_train": (C.c_int, [vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_int64, dp, C.c_double, C.c_double,
+                                    C.c_double, C.c_int64]),
         "fdlb_mlp_predict_fields": (C.c_int, [vp, C.c_double, C.c_int, C.c_int, C.c_double, vp, vp, vp]),
         "fdlb_field_samples": (C.c_int, [vp, vp, vp]),
         "fdlb_batch_field_samples": (C.c_int, [vp, C.c_int, vp, vp]),

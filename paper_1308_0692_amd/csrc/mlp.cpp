@@ -1,5 +1,6 @@
 // Host runtime of the warm-start network: layout of the parameter vector and the workspace,
 // parameter initialisation, and the training / inference entry points of include/fdlb.h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -108,6 +109,44 @@ void mlp_create(fdlb_mlp& m, int hidden, int64_t max_batch) {
 
 using namespace fdlb;
 
+// One training evaluation (forward, loss, gradient) of n samples; rows may be NULL.
+static void backward_of(fdlb_mlp& M, const float* d_in, const float* d_target, const int32_t* d_rows, int64_t n) {
+    require_bound(M);
+    if (n < 1 || n > M.max_batch) throw Error(FDLB_EINVAL, "n must be 1..max_batch");
+    if (!d_in || !d_target) throw Error(FDLB_EINVAL, "NULL input or target");
+    MlpArgs a = base_args(M);
+    a.in = d_in;
+    a.target = d_target;
+    a.rows = d_rows;
+    a.n = n;
+    a.n_cap = M.max_batch;
+    a.out = (float*)(M.work + M.off_out);
+    a.act = (float*)(M.work + M.off_act);
+    a.partial = (float*)(M.work + M.off_part);
+    a.loss_part = (double*)(M.work + M.off_lossp);
+    a.inv_3n = (float)(1.0 / (3.0 * (double)n));
+    refresh_bf16(M, a);
+    launch_mlp_forward(a, true, M.stream);
+    launch_mlp_backward(a, M.stream);
+    const int nb = (int)((n + MLP_TILE - 1) / MLP_TILE);
+    launch_mlp_reduce(a.partial, nb, M.P, M.grad, a.loss_part, 1.0 / (3.0 * (double)n),
+                      (double*)(M.work + M.off_loss), M.stream);
+    M.have_loss = true;
+}
+
+static void check_adam(double lr, double beta1, double beta2, double eps, int64_t step) {
+    if (step < 1) throw Error(FDLB_EINVAL, "step counts from 1");
+    if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        throw Error(FDLB_EINVAL, "bad Adam hyper-parameters");
+}
+
+static void adam_of(fdlb_mlp& M, double lr, double beta1, double beta2, double eps, int64_t step) {
+    const double c1 = 1.0 / (1.0 - std::pow(beta1, (double)step));
+    const double c2 = 1.0 / (1.0 - std::pow(beta2, (double)step));
+    launch_mlp_adam(M.params, M.grad, M.adam_m, M.adam_v, M.P, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                    (float)c1, (float)c2, M.stream);
+}
+
 extern "C" {
 
 int fdlb_mlp_create(int hidden_layers, int64_t max_batch, fdlb_mlp** out) {
@@ -184,28 +223,7 @@ int fdlb_mlp_forward(fdlb_mlp* m, const float* d_in, int64_t n, float* d_out) {
 
 int fdlb_mlp_backward(fdlb_mlp* m, const float* d_in, const float* d_target, const int32_t* d_rows, int64_t n) {
     return guard_call([&] {
-        fdlb_mlp& M = mh(m);
-        require_bound(M);
-        if (n < 1 || n > M.max_batch) throw Error(FDLB_EINVAL, "n must be 1..max_batch");
-        if (!d_in || !d_target) throw Error(FDLB_EINVAL, "NULL input or target");
-        MlpArgs a = base_args(M);
-        a.in = d_in;
-        a.target = d_target;
-        a.rows = d_rows;
-        a.n = n;
-        a.n_cap = M.max_batch;
-        a.out = (float*)(M.work + M.off_out);
-        a.act = (float*)(M.work + M.off_act);
-        a.partial = (float*)(M.work + M.off_part);
-        a.loss_part = (double*)(M.work + M.off_lossp);
-        a.inv_3n = (float)(1.0 / (3.0 * (double)n));
-        refresh_bf16(M, a);
-        launch_mlp_forward(a, true, M.stream);
-        launch_mlp_backward(a, M.stream);
-        const int nb = (int)((n + MLP_TILE - 1) / MLP_TILE);
-        launch_mlp_reduce(a.partial, nb, M.P, M.grad, a.loss_part, 1.0 / (3.0 * (double)n),
-                          (double*)(M.work + M.off_loss), M.stream);
-        M.have_loss = true;
+        backward_of(mh(m), d_in, d_target, d_rows, n);
         return FDLB_OK;
     });
 }
@@ -227,13 +245,28 @@ int fdlb_mlp_adam_step(fdlb_mlp* m, double lr, double beta1, double beta2, doubl
     return guard_call([&] {
         fdlb_mlp& M = mh(m);
         require_bound(M);
-        if (step < 1) throw Error(FDLB_EINVAL, "step counts from 1");
-        if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
-            throw Error(FDLB_EINVAL, "bad Adam hyper-parameters");
-        const double c1 = 1.0 / (1.0 - std::pow(beta1, (double)step));
-        const double c2 = 1.0 / (1.0 - std::pow(beta2, (double)step));
-        launch_mlp_adam(M.params, M.grad, M.adam_m, M.adam_v, M.P, (float)lr, (float)beta1, (float)beta2, (float)eps,
-                        (float)c1, (float)c2, M.stream);
+        check_adam(lr, beta1, beta2, eps, step);
+        adam_of(M, lr, beta1, beta2, eps, step);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_mlp_train(fdlb_mlp* m, const float* d_in, const float* d_target, const int32_t* d_rows, int64_t n_rows,
+                   int64_t batch, int64_t steps, const double* lr, double beta1, double beta2, double eps,
+                   int64_t first_step) {
+    return guard_call([&] {
+        fdlb_mlp& M = mh(m);
+        require_bound(M);
+        if (!d_in || !d_target || !d_rows || (steps > 0 && !lr)) throw Error(FDLB_EINVAL, "NULL array");
+        if (batch < 1 || batch > M.max_batch) throw Error(FDLB_EINVAL, "batch must be 1..max_batch");
+        if (steps < 0 || n_rows < 0 || (steps > 0 && (steps - 1) * batch >= n_rows))
+            throw Error(FDLB_EINVAL, "every step needs at least one row");
+        for (int64_t s = 0; s < steps; ++s) check_adam(lr[s], beta1, beta2, eps, first_step + s);
+        for (int64_t s = 0; s < steps; ++s) {
+            const int64_t r0 = s * batch, n = std::min(batch, n_rows - r0);
+            backward_of(M, d_in, d_target, d_rows + r0, n);
+            adam_of(M, lr[s], beta1, beta2, eps, first_step + s);
+        }
         return FDLB_OK;
     });
 }

@@ -66,18 +66,20 @@ def train(net: Mlp, X, T, epochs: int, batch: int, lr: float = 3e-3, lr_final: f
     N = X.shape[0]
     if batch > net.max_batch:
         raise ValueError("batch exceeds the network's max_batch")
-    rng = np.random.default_rng(seed)
+    # minibatch order: a permutation per epoch drawn on the device (a host permutation of millions
+    # of samples, and its copy, would cost more than the epoch's training steps)
+    gen = torch.Generator(device=X.device)
+    gen.manual_seed(int(seed))
     steps = epochs * math.ceil(N / batch)
     s = 0
     losses = []
+    per_epoch = math.ceil(N / batch)
     for e in range(epochs):
-        perm = torch.as_tensor(rng.permutation(N).astype(np.int32)).to(X.device)
-        for k in range(0, N, batch):
-            rows = perm[k:k + batch]
-            net.backward(X, T, rows=rows)
-            frac = s / max(1, steps - 1)
-            net.adam_step(lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * frac)))
-            s += 1
+        perm = torch.randperm(N, generator=gen, device=X.device).to(torch.int32)
+        # one call per epoch: the minibatch loop (backward, Adam) runs behind the C ABI
+        fracs = (s + np.arange(per_epoch)) / max(1, steps - 1)
+        net.train_steps(X, T, perm, batch, lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * fracs)))
+        s += per_epoch
         losses.append(net.last_loss())
         if log and (e % max(1, epochs // 10) == 0 or e == epochs - 1):
             log(f"epoch {e}: minibatch loss {losses[-1]:.3e}")

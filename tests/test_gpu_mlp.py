@@ -171,3 +171,26 @@ def test_gradient_full_training_batch(F):
     Eb, gb = mlp.gradient(theta, a, t, bf16=True)
     assert np.linalg.norm(g - gb) <= 2e-4 * np.linalg.norm(gb)
     assert abs(net.last_loss() - Eb) <= 1e-4 * Eb
+
+
+def test_train_steps_equals_the_step_by_step_loop(F):
+    """fdlb_mlp_train enqueues the same kernels in the same order as backward + adam_step per
+    minibatch: parameters, Adam moments and loss agree to the bit (ragged last minibatch)."""
+    import torch
+    theta = f32(W.mlp_params(90))
+    a, t = W.mlp_samples(1000, 91)
+    A, T = dev(torch, a), dev(torch, t)
+    rows = dev(torch, np.random.default_rng(92).permutation(1000).astype(np.int32), np.int32)
+    lrs = [3e-3, 2e-3, 1e-3, 5e-4]           # 4 steps of 300: 300, 300, 300, 100 rows
+    n1 = F.Mlp(params=theta, max_batch=512)
+    n2 = F.Mlp(params=theta, max_batch=512)
+    n1.train_steps(A, T, rows, 300, lrs)
+    for s, lr in enumerate(lrs):
+        n2.backward(A, T, rows=rows[s * 300:(s + 1) * 300])
+        n2.adam_step(lr)
+    assert n1.step_count == n2.step_count == 4
+    assert torch.equal(n1.params, n2.params)
+    assert torch.equal(n1.adam_m, n2.adam_m) and torch.equal(n1.adam_v, n2.adam_v)
+    assert n1.last_loss() == n2.last_loss()
+    with pytest.raises(F.FdlbError):
+        n1.train_steps(A, T, rows, 300, lrs + [1e-4])   # a fifth step would start past the rows
