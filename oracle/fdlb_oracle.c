@@ -22,7 +22,7 @@
  *     with rho_w from the impermeability sum of Eq. (9) over the populations
  *     that arrive at the wall (xi . n < 0).
  *
- * Readings where the paper is silent (each is listed in the design doc):
+ * Readings where the paper is silent:
  *   grid: cell-centred cells, walls on the outer cell faces, the wall value
  *     acting as the upwind neighbour of the wall cell; rho_w taken from the
  *     wall cell's post-relaxation populations; relax then transport (the

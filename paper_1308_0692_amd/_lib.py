@@ -54,8 +54,7 @@ class Report(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                          "(python -c 'import __graft_entry__ as g; g.build()')")
+        raise ImportError(f"{LIB_PATH} is missing: build it with python paper_1308_0692_amd/build.py")
     # torch first: the library then binds to the HIP runtime torch has loaded, so that one
     # runtime (one view of the devices, streams and allocations) serves the process.
     import torch  # noqa: F401

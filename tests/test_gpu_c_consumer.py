@@ -26,7 +26,7 @@ def F():
 
 
 def test_c_consumer_equals_python_binding(F, tmp_path):
-    assert os.path.exists(EXE), "examples/cavity_c is missing: run __graft_entry__.build()"
+    assert os.path.exists(EXE), "examples/cavity_c is missing: run python paper_1308_0692_amd/build.py"
     n, kn, tol = 48, 0.2, 1e-9
     out = tmp_path / "f.bin"
     r = subprocess.run([EXE, str(n), str(kn), str(tol), "2", str(out)], capture_output=True, text=True, timeout=120)
