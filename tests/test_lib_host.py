@@ -259,3 +259,18 @@ def test_batch_reports_each_members_velocity_count():
         assert _lib.lib.fdlb_batch_problem_q(h, -1) == _lib.EINVAL
     finally:
         _lib.lib.fdlb_batch_destroy(h)
+
+
+def test_builtin_tile_choices_of_the_workloads(F):
+    """The built-in shape choices that the measured results rest on: single-cell-wide channels
+    take the 64-cell column split eight ways, small cavities the 64 x 1 tile split eight ways
+    (latency-bound), the large cavity a wide non-temporal tile without a split (bandwidth-bound);
+    and no shape is compiled twice."""
+    for prec in ("fp32", "fp64"):
+        descs = [F.tile_describe(prec, t) for t in range(F.tile_count(prec))]
+        assert len(set(descs)) == len(descs), prec
+        for case in (W.C1, W.couette(37)):
+            assert F.tile_describe(prec, F.Problem(case, precision=prec, bind=False).tile) == "vx1 lx1 k1 w1 a8 (1x64)"
+        assert F.tile_describe(prec, F.Problem(W.C2, precision=prec, bind=False).tile) == "vx1 lx64 k1 w1 a8 (64x1)"
+        big = F.tile_describe(prec, F.Problem(W.C4, precision=prec, bind=False).tile)
+        assert " nt " in big and " a" not in big and big.startswith("vx4" if prec == "fp32" else "vx2"), big
