@@ -249,21 +249,35 @@ def test_fp64_cavity_converged_steps_match(F):
 # Full size: the large cavity in the launch configuration the benchmark times.
 # ---------------------------------------------------------------------------
 
-def test_large_cavity_full_size_fp32(F):
-    """1024 x 1024 x 256 velocities: two steps from a seeded non-uniform equilibrium,
-    every cell's moments against the oracle run at full size."""
+@pytest.fixture(scope="module")
+def large_cavity_reference():
+    """The oracle's moments of the large cavity (1024 x 1024 x 256 velocities) two steps
+    from a seeded non-uniform equilibrium, with the fields it started from."""
     case = W.C4
-    gp = F.Problem(case, precision="fp32")
     op = OP.from_case(case)
-    rho, ux, uy = W.random_fields(case.nx, case.ny, seed=4, amp=0.01)
-    gp.init_equilibrium(rho, ux, uy)
-    gp.step(2)
-    fo = op.step(op.equilibrium(rho, ux, uy), 2)
-    r1, ux1, uy1, _ = gp.moments()
-    r0, ux0, uy0 = op.moments(fo)
+    fields = W.random_fields(case.nx, case.ny, seed=4, amp=0.01)
+    fo = op.step(op.equilibrium(*fields), 2)
+    moments = op.moments(fo)
     del fo
-    assert eps_u(ux1, uy1, ux0, uy0) <= 2e-5
-    assert np.abs(r1 - r0).max() <= 2e-6
+    return fields, moments
+
+
+@pytest.mark.parametrize("prec,bar_u,bar_rho", [("fp32", 2e-5, 2e-6), ("fp64", 1e-12, 1e-13)])
+def test_large_cavity_full_size_every_tile(F, large_cavity_reference, prec, bar_u, bar_rho):
+    """Full size, every compiled shape that fits (so whichever one the autotuner picks for the
+    benchmark's timing): every cell's moments against the oracle's."""
+    (rho, ux, uy), (r0, ux0, uy0) = large_cavity_reference
+    gp = F.Problem(W.C4, precision=prec)
+    tiles = _fitting_tiles(F, W.C4, prec)
+    assert len(tiles) >= 5
+    for t in tiles:
+        gp.set_tile(t)
+        gp.init_equilibrium(rho, ux, uy)
+        gp.step(2)
+        r1, ux1, uy1, _ = gp.moments()
+        assert eps_u(ux1, uy1, ux0, uy0) <= bar_u, (t, F.tile_describe(prec, t))
+        assert np.abs(r1 - r0).max() <= bar_rho, (t, F.tile_describe(prec, t))
+    gp.close()
 
 
 # ---------------------------------------------------------------------------
