@@ -207,8 +207,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU, "
-              "see the sharding design notes", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the step is measured on one GPU's "
+              "share of the work, and no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
 
     import torch
