@@ -195,8 +195,12 @@ int fdlb_checkpoint_load(fdlb_problem *p, const void *host_buf);
 /* ---- time marching ------------------------------------------------------------ */
 
 /*
- * Advance nsteps time steps (relaxation, wall emission, upwind transport,
- * moments and residual of every step), asynchronously on the bound stream.
+ * Advance nsteps time steps, asynchronously on the bound stream.  Each step
+ * relaxes every population by an explicit Euler step of Eq. (1) toward the
+ * equilibrium of Eq. (5), re-emits the populations leaving each wall with
+ * Eq. (8) and the wall density of Eq. (9), transports with the first-order
+ * upwind difference of the fully discrete scheme, and forms the moments of
+ * Eqs. (6)-(7) and the step's residual (fdlb_last_residual).
  * A launch of at most 1024 tiles (blocks) reduces each step's residual inside
  * the next step's launch (one extra block) and once more at the end of the
  * call; larger grids launch a reduction kernel after every step.  Either way
@@ -216,7 +220,9 @@ int fdlb_step_timed(fdlb_problem *p, int64_t nsteps, double *ms_step_kernels, do
 /*
  * Residual of the most recent step, R = ||u^{n+1} - u^n||_2 / ||u^{n+1}||_2
  * over all cells (both velocity components), and the number of steps since
- * the last init.  Synchronous.
+ * the last init.  The paper states no stopping rule; this relative change of
+ * the velocity field (Eq. 7) per step is the one every solve here uses.
+ * Synchronous.
  */
 int fdlb_last_residual(fdlb_problem *p, double *residual, int64_t *steps);
 
@@ -271,7 +277,13 @@ int fdlb_wall_profile(fdlb_problem *p, int wall, double *rho, double *u_t, doubl
 
 /*
  * Tile shapes of the step kernel.  fdlb_tile_count() gives the number of
- * compiled shapes; fdlb_tile_describe writes "VXxLX/KxW" style text.
+ * compiled shapes; fdlb_tile_describe writes text such as
+ * "vx4 lx32 k2 w4 nt (128x16)": cells per lane along x, lanes along x, rows
+ * per lane, waves stacked along y, then "aN" (velocities split over N waves),
+ * "xN" (N waves side by side), "nt" (non-temporal population stores) and
+ * "pN" (N velocity planes prefetched) when present, and the tile's size in
+ * cells; a buffer too short gets a truncated,
+ * NUL-terminated text.
  * fdlb_problem_set_tile selects one (-1: the built-in heuristic); shapes that
  * do not fit the problem give FDLB_EINVAL.  fdlb_autotune times every
  * fitting shape for `steps` steps on the bound buffers (the state is
