@@ -341,9 +341,8 @@ int fdlb_batch_init_equilibrium_dev(fdlb_batch *b, int i, const float *d_rho, co
  * launch per time step for the whole batch (two while FDLB_MIXED instances run
  * in both precisions), with each instance's residual reduced as for a single
  * problem (inline for small instances, a shared reduction launch per step for
- * large ones); the host
- * polls every check_every steps; use_graph replays check_every steps as one
- * captured graph.  All instances must have been initialised (and have taken
+ * large ones); the host polls every check_every steps; use_graph replays
+ * check_every steps as one captured graph.  All instances must have been initialised (and have taken
  * step counts of equal parity).  reports: caller array of n entries (may be
  * NULL; each entry's history/history_cap are honoured).
  * Returns FDLB_OK when every instance converged, FDLB_ENOTCONVERGED if some
