@@ -1,5 +1,6 @@
 """Edge cases of the HIP path against the oracle: the largest velocity set (16 nodes per half on
-both axes, Q = 1024), a relaxation rate at its limit (omega = 1), empty calls, and a problem
+both axes, Q = 1024) and the smallest ones (Q = 4 and 2, on every tile shape), a relaxation
+rate at its limit (omega = 1), empty calls, and a problem
 with no moving wall, which must stay at rest to round-off (the wall constant sqrt(2 pi) A - 1 of
 Eq. (9) is zero only in exact arithmetic)."""
 import re
@@ -45,6 +46,34 @@ def test_largest_velocity_set(F, prec, bar):
     case = W.cavity(6, ny=5, kn=0.5, order=16)
     assert F.Problem(case, bind=False).q == 1024
     compare(F, case, prec, 5, bar)
+
+
+@pytest.mark.parametrize("case", [W.cavity(12, ny=10, kn=0.3, order=1),
+                                  W.couette(21, kn=0.5, qx=("full", 1), qy=("half", 1))],
+                         ids=["cavity_q4", "couette_q2"])
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_smallest_velocity_sets_every_tile(F, case, prec, bar):
+    """One node per half-line: Q = 4 in the cavity, Q = 2 in the channel (two velocity
+    quadrants empty).  Shapes that split the velocities over several waves leave most waves
+    without a velocity; every shape that fits must still match the oracle."""
+    op = OP.from_case(case)
+    ref = op.step(perturbed(op.xi_x, op.xi_y, op.w, case.nx, case.ny, 7), 25)
+    dev = np.abs(ref - op.w[:, None, None]).max()
+    gp = F.Problem(case, precision=prec)
+    assert gp.q == op.q
+    x, y, w = gp.velocities()
+    f0 = perturbed(x, y, w, case.nx, case.ny, 7)
+    tiles = []
+    for t in range(F.tile_count(prec)):
+        try:
+            gp.set_tile(t)
+        except F.FdlbError:
+            continue
+        tiles.append(t)
+        gp.upload(f0)
+        gp.step(25)
+        assert np.abs(gp.download() - ref).max() <= bar * dev, (t, F.tile_describe(prec, t))
+    assert len(tiles) >= 4
 
 
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
