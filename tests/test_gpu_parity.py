@@ -282,6 +282,35 @@ def test_large_cavity_full_size_every_tile(F, large_cavity_reference, prec, bar_
     gp.close()
 
 
+@pytest.mark.parametrize("prec,wide,bar_u,bar_rho,bar_mass",
+                         [("fp32", "vx4 lx32 k2 w4 nt (128x16)", 2e-5, 2e-6, 1e-8),
+                          ("fp64", "vx2 lx64 k2 w4 nt (128x8)", 1e-12, 1e-13, 1e-12)])
+def test_beyond_two_to_the_31_populations(F, prec, wide, bar_u, bar_rho, bar_mass):
+    """2900 x 2900 cells x 256 velocities = 2.15e9 populations per buffer (beyond 2^31 values,
+    byte offsets beyond 2^33), too large for the oracle, so checked by properties that hold at
+    any size: two tile shapes -- one that adds each plane's precomputed byte offset, one that
+    multiplies the plane index -- march three steps from the same seeded non-uniform equilibrium
+    and agree to rounding in every cell's moments (each a sum over all 256 planes, the last
+    ones the farthest from the buffer's start), and the total mass is conserved."""
+    case = W.cavity(2900, kn=1.0, order=8)
+    gp = F.Problem(case, precision=prec)
+    assert gp.q * case.nx * case.ny > 2 ** 31
+    descs = {F.tile_describe(prec, t): t for t in range(F.tile_count(prec))}
+    rho0, ux0, uy0 = W.random_fields(case.nx, case.ny, seed=29, amp=0.01)
+    out = []
+    for d in ("vx1 lx64 k1 w1 a8 (64x1)", wide):
+        gp.set_tile(descs[d])
+        gp.init_equilibrium(rho0, ux0, uy0)
+        gp.step(3)
+        rho, ux, uy, _ = gp.moments()
+        assert abs(float(rho.sum()) - float(rho0.sum())) <= bar_mass * rho0.size, d
+        out.append((rho, ux, uy))
+    (ra, uxa, uya), (rb, uxb, uyb) = out
+    assert np.abs(ra - rb).max() <= bar_rho
+    assert eps_u(uxa, uya, uxb, uyb) <= bar_u
+    gp.close()
+
+
 # ---------------------------------------------------------------------------
 # Runtime features.
 # ---------------------------------------------------------------------------
