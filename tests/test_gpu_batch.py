@@ -42,6 +42,23 @@ def test_batch_members_equal_solo_runs(F, prec):
         assert np.array_equal(p.moments()[1], b.moments(i)[1]), i
 
 
+@pytest.mark.parametrize("case", [W.cavity(40, ny=28, kn=0.2, order=3), W.couette(90, kn=0.3)],
+                         ids=["cavity", "couette"])
+def test_one_member_batch_equals_single_problem(F, case):
+    """A batch of one problem (on its built-in shape, column tiles for the channel) marches bit
+    for bit like the problem alone on the same shape."""
+    b = F.Batch([case], precision="fp32")
+    b.init_equilibrium(0)
+    status, reps = b.solve(1e-6, 40000, check_every=40)
+    assert status == 0
+    p = F.Problem(case, precision="fp32")
+    p.set_tile(b.tile)
+    p.init_equilibrium()
+    rep = p.solve(1e-6, 40000, check_every=40)
+    assert rep["steps"] == reps[0]["steps"]
+    assert np.array_equal(p.download(), b.download(0, p.q))
+
+
 def test_batch_fp64_matches_oracle_at_fixed_steps(F):
     cases = MIXED[:4]
     b = F.Batch(cases, precision="fp64")

@@ -261,6 +261,25 @@ def test_batch_reports_each_members_velocity_count():
         _lib.lib.fdlb_batch_destroy(h)
 
 
+def test_batch_create_rejects_bad_arguments(F):
+    """No problems, a NULL description array or output, mixed precisions, and an invalid member
+    (named in the message) are errors, and no handle is returned."""
+    from paper_1308_0692_amd import _lib
+    good = _lib.make_desc(32, 32, False, False, (0.0, 0.01, 0.0, 0.0), 0.1, ("half", 2), ("half", 2))
+    bad = _lib.make_desc(0, 32, False, False, (0.0, 0.01, 0.0, 0.0), 0.1, ("half", 2), ("half", 2))
+    other = _lib.make_desc(32, 32, False, False, (0.0, 0.01, 0.0, 0.0), 0.1, ("half", 2), ("half", 2),
+                           precision="fp64")
+    h = C.c_void_p()
+    one = (_lib.ProblemDesc * 1)(good)
+    assert _lib.lib.fdlb_batch_create(one, 0, C.byref(h)) == _lib.EINVAL and not h.value
+    assert _lib.lib.fdlb_batch_create(None, 1, C.byref(h)) == _lib.EINVAL and not h.value
+    assert _lib.lib.fdlb_batch_create(one, 1, None) == _lib.EINVAL
+    assert _lib.lib.fdlb_batch_create((_lib.ProblemDesc * 2)(good, other), 2, C.byref(h)) == _lib.EINVAL
+    assert not h.value and b"precision" in _lib.lib.fdlb_last_error()
+    assert _lib.lib.fdlb_batch_create((_lib.ProblemDesc * 2)(good, bad), 2, C.byref(h)) == _lib.EINVAL
+    assert not h.value and _lib.lib.fdlb_last_error().startswith(b"problem 1:")
+
+
 def test_builtin_tile_choices_of_the_workloads(F):
     """The built-in shape choices that the measured results rest on: single-cell-wide channels
     take the 64-cell column split eight ways, small cavities the 64 x 1 tile split eight ways
