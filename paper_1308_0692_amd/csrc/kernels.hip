@@ -26,8 +26,8 @@
 // (cross-lane shuffle of the relaxed value), in a halo cell outside the wave
 // (loaded and relaxed by the edge lane), or the wall emission of Eq. (8).
 // Blocks are mapped to tiles so that each of the 8 XCDs owns a contiguous band
-// of tile rows (its own L2 then serves the halo rows shared between vertically
-// adjacent tiles).
+// of tile rows, keeping vertically adjacent tiles, which read each other's edge
+// rows as halos, on one XCD and its L2.
 //
 // Residual: every block writes three partial sums; they are reduced by a
 // one-block kernel after the step (large grids) or by one extra block of the
