@@ -293,3 +293,51 @@ def test_builtin_tile_choices_of_the_workloads(F):
         assert F.tile_describe(prec, F.Problem(W.C2, precision=prec, bind=False).tile) == "vx1 lx64 k1 w1 a8 (64x1)"
         big = F.tile_describe(prec, F.Problem(W.C4, precision=prec, bind=False).tile)
         assert " nt " in big and " a" not in big and big.startswith("vx4" if prec == "fp32" else "vx2"), big
+
+
+def test_problems_created_from_many_threads_at_once(F):
+    """Distinct handles are independent: problems created concurrently from eight threads (their
+    quadrature rules overlapping, so the rule cache is shared) give the same velocity sets and
+    time steps as problems created alone, and each thread's error message stays its own."""
+    import threading
+    from paper_1308_0692_amd import _lib
+    orders = [2, 3, 4, 5, 6, 7, 8, 3]
+    bad = _lib.make_desc(0, 8, False, False, (0.0, 0.01, 0.0, 0.0), 0.1, ("half", 2), ("half", 2))
+
+    def make(order):
+        d = _lib.make_desc(16, 12, False, False, (0.0, 0.01, 0.0, 0.0), 0.3, ("half", order), ("half", order + 1))
+        h = C.c_void_p()
+        assert _lib.lib.fdlb_problem_create(C.byref(d), C.byref(h)) == 0
+        q = _lib.lib.fdlb_problem_q(h)
+        x, y, w = (np.empty(q) for _ in range(3))
+        assert _lib.lib.fdlb_problem_velocities(h, *[_lib._dp(a) for a in (x, y, w)]) == 0
+        dt = _lib.lib.fdlb_problem_dt(h)
+        _lib.lib.fdlb_problem_destroy(h)
+        return q, dt, x, y, w
+
+    alone = {o: make(o) for o in set(orders)}
+    errors, results = [], []
+
+    def work(order):
+        try:
+            for _ in range(20):
+                got = make(order)
+                ref = alone[order]
+                assert got[0] == ref[0] and got[1] == ref[1]
+                assert all(np.array_equal(a, b) for a, b in zip(got[2:], ref[2:]))
+                h = C.c_void_p()
+                assert _lib.lib.fdlb_problem_create(C.byref(bad), C.byref(h)) == _lib.EINVAL
+                assert _lib.lib.fdlb_last_error() == b"nx and ny must be >= 1"
+                make(order)  # a success clears this thread's message
+                assert _lib.lib.fdlb_last_error() == b""
+            results.append(order)
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(o,)) for o in orders]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    assert sorted(results) == sorted(orders)
