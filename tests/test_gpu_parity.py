@@ -332,6 +332,41 @@ def test_graph_replays_match_eager(F):
         assert a.last_residual() == b.last_residual()
 
 
+def test_two_problems_on_their_own_streams_interleaved(F):
+    """Distinct handles are independent on the device too: two problems (each on its own
+    stream, different precisions and sizes) with their steps and graph-captured solves enqueued
+    alternately end bit-identical to the same work done one problem at a time."""
+    ca, cb = W.cavity(40, ny=32, kn=0.2, order=3), W.cavity(64, kn=0.5, order=2)
+
+    def work(p, part):
+        if part == 0:
+            p.init_equilibrium()
+            p.step(37)
+        elif part == 1:
+            return p.solve(1e-6, 20000, check_every=40, use_graph=True)["steps"]
+        else:
+            p.step(11)
+
+    solo = []
+    for case, prec in ((ca, "fp64"), (cb, "fp32")):
+        p = F.Problem(case, precision=prec)
+        steps = [work(p, k) for k in range(3)][1]
+        solo.append((steps, p.download(), p.last_residual()))
+        p.close()
+    a, b = F.Problem(ca, precision="fp64"), F.Problem(cb, precision="fp32")
+    assert a.stream != b.stream
+    got_steps = [None, None]
+    for k in range(3):
+        for i, p in enumerate((a, b)):
+            r = work(p, k)
+            if k == 1:
+                got_steps[i] = r
+    for i, p in enumerate((a, b)):
+        assert got_steps[i] == solo[i][0], i
+        assert np.array_equal(p.download(), solo[i][1]), i
+        assert p.last_residual() == solo[i][2], i
+
+
 def test_checkpoint_resume(F):
     """Exact checkpoints resume bit-identically; a raw-population upload resumes to
     round-off (its moments are recomputed from the stored populations)."""
