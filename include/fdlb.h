@@ -123,8 +123,11 @@ typedef struct fdlb_problem fdlb_problem; /* opaque host handle */
  * Validate a description and build the velocity set, the time step
  * dt = cfl / max_alpha(|xi_x| N_x / l_x [x bounded] + |xi_y| N_y / l_y [y bounded])
  * and omega = dt / Kn (0 for Kn = INFINITY).  Cells are l_x / N_x by l_y / N_y.  Host only (no GPU call); the
- * handle owns only host memory.  FDLB_EINVAL for bad sizes or rules,
- * FDLB_EUNSTABLE if cfl > 1 or omega > 1 and allow_unstable is 0.
+ * handle owns only host memory.  FDLB_EINVAL for bad sizes or rules, and for
+ * a full-range rule on a bounded axis (Eq. (9) makes a wall impermeable only
+ * for half-range nodes: sqrt(2 pi) sum_{xi > 0} w xi = 1); full-range rules
+ * serve periodic axes.  FDLB_EUNSTABLE if cfl > 1 or omega > 1 and
+ * allow_unstable is 0.
  */
 int fdlb_problem_create(const fdlb_problem_desc *desc, fdlb_problem **out);
 void fdlb_problem_destroy(fdlb_problem *p); /* NULL is a no-op; no GPU call */

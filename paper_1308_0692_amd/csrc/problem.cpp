@@ -122,6 +122,13 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
         throw Error(FDLB_EINVAL, "a periodic axis must have exactly one cell");
     if (!d.periodic_x && d.nx < 2) throw Error(FDLB_EINVAL, "a bounded axis needs at least 2 cells");
     if (!d.periodic_y && d.ny < 2) throw Error(FDLB_EINVAL, "a bounded axis needs at least 2 cells");
+    // Eq. (9) takes the wall density as sqrt(2 pi) times the arriving flux; the wall is then
+    // impermeable because a half-range rule integrates xi over each half-line exactly (sum of
+    // w xi over xi > 0 is (2 pi)^(-1/2)).  A full-range rule does not, and such a wall creates or
+    // destroys mass (from rest: +87 % in 200 steps for 4 nodes, -75 % for 3).
+    if ((!d.periodic_x && d.qx_kind == FDLB_FULL) || (!d.periodic_y && d.qy_kind == FDLB_FULL))
+        throw Error(FDLB_EINVAL, "a bounded axis needs a half-range rule (the wall of Eq. (9) is impermeable only "
+                                 "for half-range nodes)");
     if (d.precision != FDLB_FP32 && d.precision != FDLB_FP64 && d.precision != FDLB_MIXED)
         throw Error(FDLB_EINVAL, "precision must be FDLB_FP32, FDLB_FP64 or FDLB_MIXED");
     if (!(d.cfl > 0) || !std::isfinite(d.cfl)) throw Error(FDLB_EINVAL, "cfl must be positive and finite");

@@ -341,3 +341,16 @@ def test_problems_created_from_many_threads_at_once(F):
         t.join()
     assert not errors, errors
     assert sorted(results) == sorted(orders)
+
+
+def test_full_range_rule_on_a_bounded_axis_is_rejected(F):
+    """Walls need half-range nodes on their normal axis (Eq. 9 is impermeable only then); a
+    full-range rule is accepted on a periodic axis (the channel's GH3 in x)."""
+    from paper_1308_0692_amd import _lib
+    for qx, qy in ((("full", 4), ("half", 4)), (("half", 4), ("full", 3)), (("full", 4), ("full", 4))):
+        d = _lib.make_desc(16, 16, False, False, (0.0, 0.01, 0.0, 0.0), 0.1, qx, qy)
+        h = C.c_void_p()
+        assert _lib.lib.fdlb_problem_create(C.byref(d), C.byref(h)) == _lib.EINVAL, (qx, qy)
+        assert not h.value and b"half-range rule" in _lib.lib.fdlb_last_error()
+    for case in (W.C1, W.couette_x(40, qy=("full", 3)), W.couette(30, qx=("full", 1))):
+        assert F.Problem(case, bind=False).q > 0

@@ -375,3 +375,21 @@ def test_domain_scaling_is_a_change_of_units():
     c = Problem(24, 20, False, False, (0, 0.01, 0, 0), kn=0.3, qx=("half", 2), qy=("half", 2), lx=2.0)
     fc = c.step(c.equilibrium(rho, ux, uy), 40)
     assert np.abs(fc - fb).max() > 1e-6 * dev
+
+
+def test_wall_is_impermeable_only_with_half_range_nodes():
+    """Eq. (9) sets the wall density to sqrt(2 pi) times the arriving flux; the leaving flux then
+    equals it because a half-range rule gives sum_{xi>0} w xi = (2 pi)^(-1/2) exactly.  From rest
+    with no moving wall, half-range sets stay at rest to round-off; full-range sets on the wall
+    axes (sum_{xi>0} w xi = 0.444 for 4 nodes, sqrt(3)/6 = 0.289 for 3, against 0.399) create or
+    destroy mass."""
+    for order, rule, at_rest in ((2, "half", True), (3, "half", True), (4, "full", False), (3, "full", False)):
+        c = W.with_(W.cavity(10, kn=0.5, u_w=0.0, order=2), qx=(rule, order), qy=(rule, order))
+        op = Problem.from_case(c)
+        f0 = op.equilibrium()
+        f = op.step(f0, 100)
+        m0, m = op.moments(f0)[0].sum(), op.moments(f)[0].sum()
+        if at_rest:
+            assert np.abs(f - op.w[:, None, None]).max() <= 1e-14 and abs(m - m0) <= 1e-12 * m0, (rule, order)
+        else:
+            assert abs(m - m0) > 0.1 * m0, (rule, order, m, m0)
