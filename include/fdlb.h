@@ -23,7 +23,9 @@
  *    cell (the paper's planar Couette flow), so transport along it vanishes.
  *  - Walls: index 0 bottom (y = 0), 1 top (y = 1), 2 left (x = 0), 3 right
  *    (x = 1).  wall_u[i] is the wall's tangential speed: along +x for the
- *    bottom/top walls, along +y for the left/right walls.
+ *    bottom/top walls, along +y for the left/right walls.  A periodic axis has
+ *    no walls: the speeds given for them are ignored.  The velocity rule on a
+ *    bounded axis must be half-range (see fdlb_problem_create).
  *  - Velocity order: alpha = j * Q_x + i, i indexing the x rule and j the y
  *    rule, both rules with nodes ascending.
  *  - Host arrays of cell fields are row-major [y][x] (N_x fastest), doubles.
