@@ -128,8 +128,10 @@ typedef struct fdlb_problem fdlb_problem; /* opaque host handle */
  * handle owns only host memory.  FDLB_EINVAL for bad sizes or rules, and for
  * a full-range rule on a bounded axis (Eq. (9) makes a wall impermeable only
  * for half-range nodes: sqrt(2 pi) sum_{xi > 0} w xi = 1); full-range rules
- * serve periodic axes.  FDLB_EUNSTABLE if cfl > 1 or omega > 1 and
- * allow_unstable is 0.
+ * serve periodic axes.  Every rule needs at least 2 nodes (per half-line
+ * for half-range) so that it integrates xi^2 exactly and the relaxation of
+ * Eqs. (1), (5) conserves momentum; FDLB_EINVAL otherwise.  FDLB_EUNSTABLE if
+ * cfl > 1 or omega > 1 and allow_unstable is 0.
  */
 int fdlb_problem_create(const fdlb_problem_desc *desc, fdlb_problem **out);
 void fdlb_problem_destroy(fdlb_problem *p); /* NULL is a no-op; no GPU call */

@@ -129,6 +129,12 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     if ((!d.periodic_x && d.qx_kind == FDLB_FULL) || (!d.periodic_y && d.qy_kind == FDLB_FULL))
         throw Error(FDLB_EINVAL, "a bounded axis needs a half-range rule (the wall of Eq. (9) is impermeable only "
                                  "for half-range nodes)");
+    // The relaxation conserves momentum only if each rule integrates xi^2 exactly (sum w xi^2 = 1):
+    // a Gauss rule of n nodes (per half-line) integrates degree 2n - 1, so n >= 2.  One node per
+    // half-line gives sum w xi^2 = 2 / pi, and a one-node full-range rule has xi = 0 only.
+    if (d.qx_n < 2 || d.qy_n < 2)
+        throw Error(FDLB_EINVAL, "each velocity rule needs at least 2 nodes (per half-line for half-range) so that it "
+                                 "integrates xi^2 exactly");
     if (d.precision != FDLB_FP32 && d.precision != FDLB_FP64 && d.precision != FDLB_MIXED)
         throw Error(FDLB_EINVAL, "precision must be FDLB_FP32, FDLB_FP64 or FDLB_MIXED");
     if (!(d.cfl > 0) || !std::isfinite(d.cfl)) throw Error(FDLB_EINVAL, "cfl must be positive and finite");

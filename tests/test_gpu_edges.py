@@ -1,5 +1,5 @@
 """Edge cases of the HIP path against the oracle: the largest velocity set (16 nodes per half on
-both axes, Q = 1024) and the smallest ones (Q = 4 and 2, on every tile shape), a relaxation
+both axes, Q = 1024) and the smallest ones (Q = 16 and 8, on every tile shape), a relaxation
 rate at its limit (omega = 1), empty calls, and a problem
 with no moving wall, which must stay at rest to round-off (the wall constant sqrt(2 pi) A - 1 of
 Eq. (9) is zero only in exact arithmetic)."""
@@ -48,14 +48,14 @@ def test_largest_velocity_set(F, prec, bar):
     compare(F, case, prec, 5, bar)
 
 
-@pytest.mark.parametrize("case", [W.cavity(12, ny=10, kn=0.3, order=1),
-                                  W.couette(21, kn=0.5, qx=("full", 1), qy=("half", 1))],
-                         ids=["cavity_q4", "couette_q2"])
+@pytest.mark.parametrize("case", [W.cavity(12, ny=10, kn=0.3, order=2),
+                                  W.couette(21, kn=0.5, qx=("full", 2), qy=("half", 2))],
+                         ids=["cavity_q16", "couette_q8"])
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
 def test_smallest_velocity_sets_every_tile(F, case, prec, bar):
-    """One node per half-line: Q = 4 in the cavity, Q = 2 in the channel (two velocity
-    quadrants empty).  Shapes that split the velocities over several waves leave most waves
-    without a velocity; every shape that fits must still match the oracle."""
+    """The smallest valid velocity sets (two nodes per rule): Q = 16 in the cavity and Q = 8 in
+    the channel, two velocities per quadrant, so shapes that split the velocities eight ways
+    leave each wave one velocity; every shape that fits must match the oracle."""
     op = OP.from_case(case)
     ref = op.step(perturbed(op.xi_x, op.xi_y, op.w, case.nx, case.ny, 7), 25)
     dev = np.abs(ref - op.w[:, None, None]).max()

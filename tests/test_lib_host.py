@@ -352,5 +352,21 @@ def test_full_range_rule_on_a_bounded_axis_is_rejected(F):
         h = C.c_void_p()
         assert _lib.lib.fdlb_problem_create(C.byref(d), C.byref(h)) == _lib.EINVAL, (qx, qy)
         assert not h.value and b"half-range rule" in _lib.lib.fdlb_last_error()
-    for case in (W.C1, W.couette_x(40, qy=("full", 3)), W.couette(30, qx=("full", 1))):
+    for case in (W.C1, W.couette_x(40, qy=("full", 3)), W.couette(30, qx=("full", 2))):
         assert F.Problem(case, bind=False).q > 0
+
+
+def test_one_node_rules_are_rejected(F):
+    """A rule must integrate xi^2 exactly for the relaxation to conserve momentum: one node per
+    half-line (sum w xi^2 = 2/pi) and the one-node full-range rule (xi = 0) are rejected, two
+    nodes are accepted; the quadrature routines themselves still give the one-node rules."""
+    from paper_1308_0692_amd import _lib
+    for case in (W.cavity(12, order=1), W.couette(20, qx=("full", 1)), W.couette(20, qy=("half", 1))):
+        with pytest.raises(F.FdlbError) as e:
+            F.Problem(case, bind=False)
+        assert e.value.code == _lib.EINVAL and "at least 2 nodes" in str(e.value)
+    assert F.Problem(W.cavity(12, order=2), bind=False).q == 16
+    assert F.Problem(W.couette(20, qx=("full", 2), qy=("half", 2)), bind=False).q == 8
+    x, w = _lib.quad_half_range(1)
+    assert np.allclose(x, [-np.sqrt(2 / np.pi), np.sqrt(2 / np.pi)]) and np.allclose(w, [0.5, 0.5])
+    assert abs(float(np.sum(w * x * x)) - 2 / np.pi) < 1e-15

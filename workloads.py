@@ -181,7 +181,7 @@ def mlp_samples(n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
 
 def random_cases(count: int, seed: int) -> List[Case]:
     """Seeded assorted problems for broad parity checks: grids 2..70 (or a periodic single cell on
-    one axis), half-range rules of 1..5 nodes per half on bounded axes (walls need them) and half-
+    one axis), half-range rules of 2..5 nodes per half on bounded axes (walls need them) and half-
     or full-range rules (full: 2..6 nodes) on a periodic axis, Kn log-uniform in [0.02, 50] or
     infinite, every wall speed in [-0.02, 0.02], domain lengths in [0.5, 2]."""
     rng = np.random.default_rng(seed)
@@ -193,7 +193,7 @@ def random_cases(count: int, seed: int) -> List[Case]:
 
         def rule(axis_periodic: bool):
             if not axis_periodic or rng.random() < 0.5:
-                return ("half", int(rng.integers(1, 6)))
+                return ("half", int(rng.integers(2, 6)))
             return ("full", int(rng.integers(2, 7)))
 
         qx, qy = rule(kind == 1), rule(kind == 2)
