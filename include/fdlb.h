@@ -174,7 +174,10 @@ int fdlb_init_equilibrium(fdlb_problem *p, const double *rho, const double *ux, 
 
 /*
  * Same from device arrays of N_x N_y floats each (e.g. a network's output),
- * laid out [y][x]; none may be NULL.  Renormalisation as above, on device.
+ * laid out [y][x]; none may be NULL.  Renormalisation as above, on device
+ * (asynchronous): a density field whose sum is not positive leaves a NaN
+ * state, which the next fdlb_solve_steady reports as FDLB_EDIVERGED (the host
+ * variant returns FDLB_EINVAL instead).
  */
 int fdlb_init_equilibrium_dev(fdlb_problem *p, const float *d_rho, const float *d_ux, const float *d_uy,
                               int renormalize_mass);

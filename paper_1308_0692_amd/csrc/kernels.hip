@@ -829,7 +829,9 @@ __global__ void __launch_bounds__(1024) mass_scale_kernel(const float* __restric
         if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = (double)cells / s[0];
+    // A total that is not positive cannot be renormalised: the scale is then NaN, so the seeded
+    // state is NaN and the next steady solve reports divergence at its first step.
+    if (threadIdx.x == 0) *out = s[0] > 0.0 ? (double)cells / s[0] : __builtin_nan("");
 }
 
 // ---------------------------------------------------------------------------

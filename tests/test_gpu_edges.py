@@ -138,6 +138,26 @@ def test_nan_in_the_state_is_reported_as_divergence(F, prec):
     assert p.solve(1e-6, 100000, check_every=50)["status"] == 0
 
 
+def test_renormalising_a_non_positive_mass(F):
+    """The host seed refuses a density field whose sum is not positive; the device seed cannot
+    refuse (it is asynchronous), so it leaves a NaN state that the next solve reports as
+    divergence at step 1; a valid seed afterwards works."""
+    import torch
+    case = W.cavity(16, ny=12, kn=0.3, order=2)
+    p = F.Problem(case, precision="fp32")
+    rho = -np.ones((12, 16))
+    with pytest.raises(F.FdlbError) as e:
+        p.init_equilibrium(rho, None, None, renormalize=True)
+    assert e.value.code == F._lib.EINVAL
+    z = torch.zeros((12, 16), dtype=torch.float32, device="cuda")
+    for r in (z, z - 1.0):
+        p.init_equilibrium_dev(r, z, z, renormalize=True)
+        rep = p.solve(1e-8, 1000, check_every=10, raise_on_diverge=False)
+        assert rep["status"] == F._lib.EDIVERGED and rep["steps"] == 1
+    p.init_equilibrium_dev(z + 1.0, z, z, renormalize=True)
+    assert p.solve(1e-6, 100000, check_every=50)["status"] == 0
+
+
 def test_nan_in_one_batch_member_leaves_the_others(F):
     cases = [W.cavity(32, kn=0.3, order=2), W.cavity(40, kn=0.3, order=2), W.cavity(24, kn=1.0, order=2)]
     b = F.Batch(cases, precision="fp32")
