@@ -259,7 +259,8 @@ int fdlb_mlp_train(fdlb_mlp* m, const float* d_in, const float* d_target, const 
         require_bound(M);
         if (!d_in || !d_target || !d_rows || (steps > 0 && !lr)) throw Error(FDLB_EINVAL, "NULL array");
         if (batch < 1 || batch > M.max_batch) throw Error(FDLB_EINVAL, "batch must be 1..max_batch");
-        if (steps < 0 || n_rows < 0 || (steps > 0 && (steps - 1) * batch >= n_rows))
+        // step s starts at row s * batch: the last one must start before n_rows (no overflow)
+        if (steps < 0 || n_rows < 0 || (steps > 0 && (n_rows < 1 || steps - 1 > (n_rows - 1) / batch)))
             throw Error(FDLB_EINVAL, "every step needs at least one row");
         for (int64_t s = 0; s < steps; ++s) check_adam(lr[s], beta1, beta2, eps, first_step + s);
         for (int64_t s = 0; s < steps; ++s) {
@@ -277,6 +278,7 @@ int fdlb_mlp_predict_fields(fdlb_mlp* m, double kn, int nx, int ny, double u_w, 
         fdlb_mlp& M = mh(m);
         require_bound(M);
         if (!(kn > 0) || !std::isfinite(kn)) throw Error(FDLB_EINVAL, "kn must be positive and finite");
+        if (!std::isfinite(u_w)) throw Error(FDLB_EINVAL, "u_w must be finite");
         if (nx < 1 || ny < 1) throw Error(FDLB_EINVAL, "nx and ny must be >= 1");
         if (!d_rho || !d_ux || !d_uy) throw Error(FDLB_EINVAL, "NULL output field");
         MlpArgs a = base_args(M);

@@ -194,3 +194,30 @@ def test_train_steps_equals_the_step_by_step_loop(F):
     assert n1.last_loss() == n2.last_loss()
     with pytest.raises(F.FdlbError):
         n1.train_steps(A, T, rows, 300, lrs + [1e-4])   # a fifth step would start past the rows
+
+
+def test_train_and_predict_reject_bad_arguments(F):
+    """The minibatch schedule must give every step a row (checked without overflow, before any
+    learning rate is read), and the predicted fields need a finite wall speed."""
+    import ctypes as C
+    import torch
+    from paper_1308_0692_amd import _lib
+    net = F.Mlp(max_batch=64)
+    a, t = W.mlp_samples(17, 3)
+    x, y = dev(torch, f32(a)), dev(torch, f32(t))
+    rows = torch.arange(17, dtype=torch.int32, device="cuda")
+    lr = np.full(4, 1e-3)
+
+    def train(n_rows, batch, steps):
+        return _lib.lib.fdlb_mlp_train(net._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                       C.c_void_p(rows.data_ptr()), n_rows, batch, steps, _lib._dp(lr),
+                                       0.9, 0.999, 1e-8, 1)
+
+    assert train(17, 8, 3) == 0          # rows 0-7, 8-15, 16
+    assert train(16, 8, 3) == _lib.EINVAL  # the third step would start at row 16
+    assert train(0, 8, 1) == _lib.EINVAL
+    assert train(17, 8, 2 ** 62) == _lib.EINVAL  # (steps - 1) * batch would overflow
+    torch.cuda.synchronize()
+    for u_w in (float("nan"), float("inf")):
+        with pytest.raises(F.FdlbError):
+            net.predict_fields(0.1, 8, 8, u_w)
