@@ -196,8 +196,10 @@ int fdlb_state_download(fdlb_problem *p, double *f_host); /* synchronous */
  * precision, their moment and wall-flux buffers, the step counter) as an
  * opaque host byte buffer of fdlb_checkpoint_bytes() bytes, owned by the
  * caller.  Loading it into a problem built from the same description and
- * marching on gives bit-identical results to never having stopped.
- * Synchronous.
+ * marching on gives bit-identical results to never having stopped.  The
+ * buffer opens with a header naming the problem (grid, number of velocities,
+ * precision), checked first: a checkpoint of another problem gives
+ * FDLB_EINVAL and leaves the state untouched.  Synchronous.
  */
 size_t fdlb_checkpoint_bytes(const fdlb_problem *p);
 int fdlb_checkpoint_save(fdlb_problem *p, void *host_buf);

@@ -213,7 +213,7 @@ enum CtrlSlot {
     CTRL_MAXU = 4,        // max |u| of the last step
     CTRL_TOL = 5,         // tolerance the reduce kernel compares against
     CTRL_FREEZE = 6,      // 1: stop updating once converged or diverged (steady solves)
-    CTRL_HOST = 7,        // not used by the kernels (checkpoints keep the precision in it)
+    CTRL_HOST = 7,        // not used by the kernels
     CTRL_RING = 8,        // ring of residuals, CTRL_RING_LEN entries
 };
 constexpr int CTRL_RING_LEN = 4096;

@@ -474,14 +474,22 @@ void state_download(fdlb_problem& p, double* f) {
 
 // Exact checkpoint: the current population buffer, its moment and wall-flux
 // buffers and the step counter, as raw device bytes.
+// A checkpoint opens with a header naming the problem it belongs to, checked before anything
+// else is read: [magic, nx, ny, q, requested precision, precision of the stored state, 0, 0].
+constexpr double CKPT_MAGIC = 1178881090.0 + 1.0;  // "FDLB" as an integer, format 1
+constexpr size_t CKPT_HEAD = 8 * sizeof(double);
+
 size_t checkpoint_bytes(const fdlb_problem& p) {
-    return p.pop_bytes + p.mom_bytes + p.phi_bytes + 8 * sizeof(double);
+    return CKPT_HEAD + p.pop_bytes + p.mom_bytes + p.phi_bytes + 8 * sizeof(double);
 }
 
 void checkpoint_save(fdlb_problem& p, void* host) {
     require_seeded(p);
     if (!host) throw Error(FDLB_EINVAL, "NULL host buffer");
-    char* h = (char*)host;
+    const double head[8] = {CKPT_MAGIC, (double)p.d.nx, (double)p.d.ny, (double)p.q, (double)p.d.precision,
+                            (double)p.prec, 0.0, 0.0};
+    std::memcpy(host, head, CKPT_HEAD);
+    char* h = (char*)host + CKPT_HEAD;
     FDLB_HIP(hipMemcpyAsync(h, pop_buf(p, p.parity), p.pop_bytes, hipMemcpyDeviceToHost, p.stream));
     FDLB_HIP(hipMemcpyAsync(h + p.pop_bytes, mom_buf(p, p.parity), p.mom_bytes, hipMemcpyDeviceToHost, p.stream));
     FDLB_HIP(hipMemcpyAsync(h + p.pop_bytes + p.mom_bytes, phi_buf(p, p.parity), p.phi_bytes, hipMemcpyDeviceToHost,
@@ -489,21 +497,22 @@ void checkpoint_save(fdlb_problem& p, void* host) {
     FDLB_HIP(hipMemcpyAsync(h + p.pop_bytes + p.mom_bytes + p.phi_bytes, ctrl(p), 8 * sizeof(double),
                             hipMemcpyDeviceToHost, p.stream));
     FDLB_HIP(hipStreamSynchronize(p.stream));
-    const double prec = (double)p.prec;
-    std::memcpy(h + p.pop_bytes + p.mom_bytes + p.phi_bytes + CTRL_HOST * sizeof(double), &prec, sizeof(prec));
 }
 
 void checkpoint_load(fdlb_problem& p, const void* host) {
     require_bound(p);
     if (!host) throw Error(FDLB_EINVAL, "NULL host buffer");
-    const char* h = (const char*)host;
-    double prec = 0;
-    std::memcpy(&prec, h + p.pop_bytes + p.mom_bytes + p.phi_bytes + CTRL_HOST * sizeof(double), sizeof(prec));
-    if (p.d.precision == FDLB_MIXED) {
-        if (prec != (double)FDLB_FP32 && prec != (double)FDLB_FP64)
-            throw Error(FDLB_EINVAL, "not a checkpoint of a mixed-precision problem");
-        set_active(p, (int)prec);
-    }
+    double head[8];
+    std::memcpy(head, host, CKPT_HEAD);
+    if (head[0] != CKPT_MAGIC) throw Error(FDLB_EINVAL, "not a checkpoint of this library");
+    if (head[1] != (double)p.d.nx || head[2] != (double)p.d.ny || head[3] != (double)p.q ||
+        head[4] != (double)p.d.precision)
+        throw Error(FDLB_EINVAL, "checkpoint of a different problem (grid, velocity set or precision)");
+    const double prec = head[5];
+    if (prec != (double)FDLB_FP32 && prec != (double)FDLB_FP64) throw Error(FDLB_EINVAL, "corrupt checkpoint header");
+    if (p.d.precision == FDLB_MIXED) set_active(p, (int)prec);
+    else if (prec != (double)p.prec) throw Error(FDLB_EINVAL, "corrupt checkpoint header");
+    const char* h = (const char*)host + CKPT_HEAD;
     p.parity = 0;
     FDLB_HIP(hipMemcpyAsync(pop_buf(p, 0), h, p.pop_bytes, hipMemcpyHostToDevice, p.stream));
     FDLB_HIP(hipMemcpyAsync(mom_buf(p, 0), h + p.pop_bytes, p.mom_bytes, hipMemcpyHostToDevice, p.stream));

@@ -393,6 +393,26 @@ def test_checkpoint_resume(F):
         assert e <= (1e-13 if prec == "fp64" else 1e-6), (prec, e)
 
 
+def test_checkpoint_of_another_problem_is_refused(F):
+    """A checkpoint names its problem: one from a grid of the same size in bytes (40 x 32 against
+    32 x 40) or with a damaged header is refused, and the state it was meant for is untouched."""
+    a = F.Problem(W.cavity(40, ny=32, kn=0.2, order=2), precision="fp64")
+    b = F.Problem(W.cavity(32, ny=40, kn=0.2, order=2), precision="fp64")
+    for p in (a, b):
+        p.init_equilibrium()
+        p.step(20)
+    ck = a.checkpoint()
+    assert len(ck) == len(b.checkpoint())
+    before = b.download()
+    for bad in (ck, b"\0" * 8 + b.checkpoint()[8:]):
+        with pytest.raises(F.FdlbError) as e:
+            b.restore(bad)
+        assert e.value.code == F._lib.EINVAL
+        assert np.array_equal(b.download(), before)
+    b.restore(b.checkpoint())
+    assert np.array_equal(b.download(), before)
+
+
 def test_init_from_device_fields_and_mass(F):
     import torch
     case = W.cavity(32, ny=24, kn=0.1, order=2)
