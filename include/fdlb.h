@@ -197,9 +197,11 @@ int fdlb_state_download(fdlb_problem *p, double *f_host); /* synchronous */
  * opaque host byte buffer of fdlb_checkpoint_bytes() bytes, owned by the
  * caller.  Loading it into a problem built from the same description and
  * marching on gives bit-identical results to never having stopped.  The
- * buffer opens with a header naming the problem (grid, number of velocities,
+ * buffer opens with a header naming the problem (grid, both velocity rules,
  * precision), checked first: a checkpoint of another problem gives
- * FDLB_EINVAL and leaves the state untouched.  Synchronous.
+ * FDLB_EINVAL and leaves the state untouched.  A checkpoint saved after a
+ * steady solve restores as a state that marches on (the solve's request to
+ * stop at its converged step is not restored).  Synchronous.
  */
 size_t fdlb_checkpoint_bytes(const fdlb_problem *p);
 int fdlb_checkpoint_save(fdlb_problem *p, void *host_buf);

@@ -475,9 +475,13 @@ void state_download(fdlb_problem& p, double* f) {
 // Exact checkpoint: the current population buffer, its moment and wall-flux
 // buffers and the step counter, as raw device bytes.
 // A checkpoint opens with a header naming the problem it belongs to, checked before anything
-// else is read: [magic, nx, ny, q, requested precision, precision of the stored state, 0, 0].
-constexpr double CKPT_MAGIC = 1178881090.0 + 1.0;  // "FDLB" as an integer, format 1
+// else is read: [magic, nx, ny, q, requested precision, precision of the stored state, x rule,
+// y rule], a rule as 1000 kind + nodes (two sets with the same Q, such as a half-range rule and
+// its transpose, order their populations differently).
+constexpr double CKPT_MAGIC = 1178881090.0 + 2.0;  // "FDLB" as an integer, format 2
 constexpr size_t CKPT_HEAD = 8 * sizeof(double);
+
+static double rule_code(int kind, int n) { return 1000.0 * kind + n; }
 
 size_t checkpoint_bytes(const fdlb_problem& p) {
     return CKPT_HEAD + p.pop_bytes + p.mom_bytes + p.phi_bytes + 8 * sizeof(double);
@@ -487,7 +491,7 @@ void checkpoint_save(fdlb_problem& p, void* host) {
     require_seeded(p);
     if (!host) throw Error(FDLB_EINVAL, "NULL host buffer");
     const double head[8] = {CKPT_MAGIC, (double)p.d.nx, (double)p.d.ny, (double)p.q, (double)p.d.precision,
-                            (double)p.prec, 0.0, 0.0};
+                            (double)p.prec, rule_code(p.d.qx_kind, p.d.qx_n), rule_code(p.d.qy_kind, p.d.qy_n)};
     std::memcpy(host, head, CKPT_HEAD);
     char* h = (char*)host + CKPT_HEAD;
     FDLB_HIP(hipMemcpyAsync(h, pop_buf(p, p.parity), p.pop_bytes, hipMemcpyDeviceToHost, p.stream));
@@ -506,21 +510,33 @@ void checkpoint_load(fdlb_problem& p, const void* host) {
     std::memcpy(head, host, CKPT_HEAD);
     if (head[0] != CKPT_MAGIC) throw Error(FDLB_EINVAL, "not a checkpoint of this library");
     if (head[1] != (double)p.d.nx || head[2] != (double)p.d.ny || head[3] != (double)p.q ||
-        head[4] != (double)p.d.precision)
+        head[4] != (double)p.d.precision || head[6] != rule_code(p.d.qx_kind, p.d.qx_n) ||
+        head[7] != rule_code(p.d.qy_kind, p.d.qy_n))
         throw Error(FDLB_EINVAL, "checkpoint of a different problem (grid, velocity set or precision)");
     const double prec = head[5];
     if (prec != (double)FDLB_FP32 && prec != (double)FDLB_FP64) throw Error(FDLB_EINVAL, "corrupt checkpoint header");
-    if (p.d.precision == FDLB_MIXED) set_active(p, (int)prec);
-    else if (prec != (double)p.prec) throw Error(FDLB_EINVAL, "corrupt checkpoint header");
+    if (p.d.precision != FDLB_MIXED && prec != (double)p.prec) throw Error(FDLB_EINVAL, "corrupt checkpoint header");
     const char* h = (const char*)host + CKPT_HEAD;
-    p.parity = 0;
-    FDLB_HIP(hipMemcpyAsync(pop_buf(p, 0), h, p.pop_bytes, hipMemcpyHostToDevice, p.stream));
-    FDLB_HIP(hipMemcpyAsync(mom_buf(p, 0), h + p.pop_bytes, p.mom_bytes, hipMemcpyHostToDevice, p.stream));
-    FDLB_HIP(hipMemcpyAsync(phi_buf(p, 0), h + p.pop_bytes + p.mom_bytes, p.phi_bytes, hipMemcpyHostToDevice,
+    // The saved control block, with the freeze request of a steady solve cleared: a restored
+    // problem marches until a solve asks again.  The state goes to the buffer its step count
+    // names (every path keeps the current buffer at step mod 2; a steady solve re-derives it).
+    double c[8];
+    std::memcpy(c, h + p.pop_bytes + p.mom_bytes + p.phi_bytes, 8 * sizeof(double));
+    const double saved_step = c[CTRL_STEP];
+    if (!(saved_step >= 0) || saved_step != std::floor(saved_step) || saved_step > 9.0e15)
+        throw Error(FDLB_EINVAL, "corrupt checkpoint (step counter)");
+    c[CTRL_FREEZE] = 0.0;
+    if (p.d.precision == FDLB_MIXED) set_active(p, (int)prec);
+    std::memcpy(p.pinned, c, sizeof(c));  // the control block is copied from pinned staging
+    const int par = (int)((int64_t)saved_step & 1);
+    FDLB_HIP(hipMemcpyAsync(pop_buf(p, par), h, p.pop_bytes, hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipMemcpyAsync(mom_buf(p, par), h + p.pop_bytes, p.mom_bytes, hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipMemcpyAsync(phi_buf(p, par), h + p.pop_bytes + p.mom_bytes, p.phi_bytes, hipMemcpyHostToDevice,
                             p.stream));
-    FDLB_HIP(hipMemcpyAsync(ctrl(p), h + p.pop_bytes + p.mom_bytes + p.phi_bytes, 8 * sizeof(double),
-                            hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipMemcpyAsync(ctrl(p), p.pinned, 8 * sizeof(double), hipMemcpyHostToDevice, p.stream));
     FDLB_HIP(hipStreamSynchronize(p.stream));
+    p.parity = par;
+    p.freeze_on = false;
     p.seeded = true;
 }
 

@@ -413,6 +413,76 @@ def test_checkpoint_of_another_problem_is_refused(F):
     assert np.array_equal(b.download(), before)
 
 
+def test_checkpoint_at_odd_step_then_solve(F):
+    """A checkpoint taken after an odd number of steps, restored into a fresh problem and solved
+    to a tolerance, ends bit-identical to the uninterrupted solve (the restored state sits in the
+    buffer its step count names)."""
+    case = W.cavity(24, ny=20, kn=0.2, order=2)
+    for prec in ("fp64", "fp32"):
+        a = F.Problem(case, precision=prec)
+        a.init_equilibrium()
+        a.step(151)
+        ck = a.checkpoint()
+        ra = a.solve(1e-7, 20000, check_every=50)
+        c = F.Problem(case, precision=prec)
+        c.restore(ck)
+        rc = c.solve(1e-7, 20000, check_every=50)
+        assert ra["status"] == 0 and rc["status"] == 0
+        assert rc["steps"] == ra["steps"] and rc["residual"] == ra["residual"], prec
+        assert c.last_residual() == a.last_residual()
+        assert np.array_equal(c.download(), a.download()), prec
+        for x, y in zip(c.moments(), a.moments()):
+            assert np.array_equal(x, y), prec
+        # stepping zero steps leaves the restored state where it is
+        d = F.Problem(case, precision=prec)
+        d.restore(ck)
+        d.step(0)
+        b = F.Problem(case, precision=prec)
+        b.init_equilibrium()
+        b.step(151)
+        assert np.array_equal(d.download(), b.download()), prec
+
+
+def test_checkpoint_after_steady_solve_steps_on(F):
+    """A checkpoint saved after a steady solve (whose kernels were asked to stop at the
+    converged step) restores into a problem that marches: an odd number of steps afterwards it
+    equals the original problem stepped the same count."""
+    case = W.cavity(24, ny=20, kn=0.2, order=2)
+    for prec in ("fp64", "fp32", "mixed"):
+        a = F.Problem(case, precision=prec)
+        a.init_equilibrium()
+        r = a.solve(1e-6, 20000, check_every=50)
+        assert r["status"] == 0
+        ck = a.checkpoint()
+        c = F.Problem(case, precision=prec)
+        c.restore(ck)
+        assert c.last_residual()[1] == a.last_residual()[1]
+        for k in (7, 3):
+            a.step(k)
+            c.step(k)
+            assert c.last_residual() == a.last_residual(), (prec, k)
+            assert np.array_equal(c.download(), a.download()), (prec, k)
+
+
+def test_checkpoint_of_transposed_velocity_set_is_refused(F):
+    """Two velocity sets with the same number of velocities, a half-range 2 x 4 set and its
+    transpose, order their populations differently: a checkpoint of one is refused by the other."""
+    base = W.cavity(24, kn=0.2, order=2)
+    a = F.Problem(W.replace(base, qx=("half", 2), qy=("half", 4)), precision="fp64")
+    b = F.Problem(W.replace(base, qx=("half", 4), qy=("half", 2)), precision="fp64")
+    assert a.q == b.q == 32
+    for p in (a, b):
+        p.init_equilibrium()
+        p.step(5)
+    ck = a.checkpoint()
+    assert len(ck) == len(b.checkpoint())
+    before = b.download()
+    with pytest.raises(F.FdlbError) as e:
+        b.restore(ck)
+    assert e.value.code == F._lib.EINVAL
+    assert np.array_equal(b.download(), before)
+
+
 def test_init_from_device_fields_and_mass(F):
     import torch
     case = W.cavity(32, ny=24, kn=0.1, order=2)
