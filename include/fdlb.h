@@ -30,9 +30,11 @@
  *    rule, both rules with nodes ascending.
  *  - Host arrays of cell fields are row-major [y][x] (N_x fastest), doubles.
  *    Population arrays are [alpha][y][x], doubles, raw f_alpha (not deviations).
- *  - Device memory is owned by the caller: the library never allocates,
- *    frees or keeps device memory beyond what fdlb_bind hands it.  Host
- *    buffers passed in are owned by the caller and not retained after return.
+ *  - Device memory is owned by the caller: the library never allocates or
+ *    frees device memory, and keeps none beyond what fdlb_bind hands it except
+ *    one static array of FDLB_STATIC_SCRATCH_BYTES per GPU that its code
+ *    object carries (the workspace of fdlb_step_static).  Host buffers passed
+ *    in are owned by the caller and not retained after return.
  *  - Streams: `stream` arguments are hipStream_t values passed as void*;
  *    NULL means the default stream.  Every call that launches work enqueues
  *    it on the bound stream.  Calls documented as synchronous wait for that
@@ -222,6 +224,43 @@ int fdlb_checkpoint_load(fdlb_problem *p, const void *host_buf);
  * the control block holds every step's residual when the call's work ends.
  */
 int fdlb_step(fdlb_problem *p, int64_t nsteps);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fdlb_step
+ * on a state buffer the caller passes, with no workspace from the caller and
+ * no allocation by the library.  The moments, wall fluxes, residual partial
+ * sums, control block and velocity table live in one static device array of
+ * FDLB_STATIC_SCRATCH_BYTES per GPU, which the library holds from its first
+ * use on that GPU until the process ends.
+ *   p        a problem from fdlb_problem_create with precision FDLB_FP32 or
+ *            FDLB_FP64 (FDLB_MIXED gives FDLB_EINVAL).  It need not be bound;
+ *            if it is, its binding, state and step counter are not touched.
+ *            Its tile choice (fdlb_problem_set_tile) is used.
+ *   d_state  device buffer of fdlb_state_bytes(p) bytes, 256-byte aligned,
+ *            owned by the caller: two halves of fdlb_state_bytes(p)/2 bytes.
+ *            On entry the first half holds the populations as deviations
+ *            h_alpha = f_alpha - w_alpha in the storage type (float for
+ *            FDLB_FP32, double for FDLB_FP64), planes [alpha][y][x] in the
+ *            velocity order above (the layout of a bound state buffer after an
+ *            init).  On return of the work, the state after nsteps steps is
+ *            in half (nsteps mod 2); the other half is overwritten.  The steps
+ *            are those fdlb_step takes from the same state (bit-identical on
+ *            the same tile).
+ *   nsteps   >= 0.
+ *   stream   hipStream_t (as void*) of the current device; the work is
+ *            enqueued on it and the call returns without waiting for it.
+ * Errors: FDLB_EINVAL for a NULL or misaligned buffer, nsteps < 0, a
+ * FDLB_MIXED problem, or a problem whose workspace (without the host staging
+ * area) exceeds FDLB_STATIC_SCRATCH_BYTES (every grid of at most 512 x 512
+ * cells fits, at any Q); nothing is enqueued then.  FDLB_EHIP for HIP errors.
+ * Calls on one GPU share its array: calls whose work overlaps on one GPU
+ * (two streams, or two threads) race and give undefined results; calls in
+ * stream order do not interfere, each rewriting what it reads before it
+ * reads it.  The state buffer must hold finite values.
+ */
+#define FDLB_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+int fdlb_step_static(fdlb_problem *p, void *d_state, int64_t nsteps, void *stream);
 
 /*
  * Advance nsteps steps as fdlb_step does (same states), but with a reduction

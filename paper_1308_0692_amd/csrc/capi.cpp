@@ -19,6 +19,7 @@ size_t checkpoint_bytes(const fdlb_problem& p);
 void checkpoint_save(fdlb_problem& p, void* host);
 void checkpoint_load(fdlb_problem& p, const void* host);
 void step(fdlb_problem& p, int64_t n);
+void step_static(fdlb_problem& p, void* d_state, int64_t n, void* stream);
 void step_timed(fdlb_problem& p, int64_t n, double* ms_step, double* ms_reduce);
 void last_residual(fdlb_problem& p, double* r, int64_t* steps);
 int solve_steady(fdlb_problem& p, double tol, int64_t max_steps, int32_t check_every, int32_t use_graph,
@@ -176,6 +177,13 @@ int fdlb_checkpoint_load(fdlb_problem* p, const void* host_buf) {
 int fdlb_step(fdlb_problem* p, int64_t nsteps) {
     return guard([&] {
         step(handle(p), nsteps);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_step_static(fdlb_problem* p, void* d_state, int64_t nsteps, void* stream) {
+    return guard([&] {
+        step_static(handle(p), d_state, nsteps, stream);
         return FDLB_OK;
     });
 }

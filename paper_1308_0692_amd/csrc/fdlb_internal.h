@@ -164,6 +164,11 @@ void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 void launch_widen(const float* src, double* dst, int64_t n, hipStream_t stream);
 // out[8 i + j] = ptrs[i][j], j < 8: the first control doubles of n problems in one array.
 void launch_gather_ctrl(const double* const* ptrs, int n, double* out, hipStream_t stream);
+// The first 8 doubles of a control block: step 0, nothing recorded, no freeze request.
+void launch_ctrl_reset(double* ctrl, hipStream_t stream);
+// Device address of the library's static workspace (FDLB_STATIC_SCRATCH_BYTES) on the current
+// device, looked up on the first call per device (scratch.hip).
+char* static_scratch();
 
 // Warm-start network (mlp.hip / mlp.cpp).
 constexpr int MLP_WIDTH = 128;     // hidden width (the matrix-core tiles assume it)
@@ -231,6 +236,8 @@ struct fdlb_problem {
     fdlb::WallConst wall[4]{};
     int32_t quad_begin[5]{};
     std::vector<int> quad_order;           // velocity index of each table entry (quadrant-grouped)
+    std::vector<fdlb::VelEntry<float>> vel32;   // the device velocity tables, built once at creation
+    std::vector<fdlb::VelEntry<double>> vel64;
     int L = 0;                             // max(nx, ny): stride of the per-wall arrays
     int64_t plane = 0;                     // nx * ny
     int prec = FDLB_FP64;                  // precision the kernels run in now (FDLB_FP32 / FDLB_FP64)

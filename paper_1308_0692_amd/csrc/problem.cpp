@@ -115,6 +115,9 @@ static int heuristic_tile(const fdlb_problem& p, int precision) {
 }
 static int heuristic_tile(const fdlb_problem& p) { return heuristic_tile(p, p.prec); }
 
+template <class T>
+std::vector<VelEntry<T>> vel_table(const fdlb_problem& p);
+
 void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     if (d.nx < 1 || d.ny < 1) throw Error(FDLB_EINVAL, "nx and ny must be >= 1");
     if ((int64_t)d.nx * d.ny > (int64_t)1 << 28) throw Error(FDLB_EINVAL, "grid too large");
@@ -250,6 +253,8 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     p.work_bytes = off;
     p.tile = heuristic_tile(p);
     p.tile_alt = d.precision == FDLB_MIXED ? heuristic_tile(p, FDLB_FP64) : -1;
+    if (d.precision != FDLB_FP64) p.vel32 = vel_table<float>(p);
+    p.vel64 = vel_table<double>(p);
 }
 
 // Switch the precision the kernels run in (FDLB_MIXED only changes it); the tile of the
@@ -267,7 +272,7 @@ static void restart_precision(fdlb_problem& p) {
 }
 
 template <class T>
-static std::vector<VelEntry<T>> vel_table(const fdlb_problem& p) {
+std::vector<VelEntry<T>> vel_table(const fdlb_problem& p) {
     std::vector<VelEntry<T>> v(p.q);
     for (int e = 0; e < p.q; ++e) {
         const int a = p.quad_order[e];
@@ -311,20 +316,17 @@ void bind(fdlb_problem& p, void* d_state, void* d_work, void* stream) {
     p.d_work = (char*)d_work;
     p.stream = (hipStream_t)stream;
     if (!p.pinned) FDLB_HIP(hipHostMalloc((void**)&p.pinned, 64 * sizeof(double), hipHostMallocDefault));
-    if (p.d.precision != FDLB_FP64) {
-        auto v = vel_table<float>(p);
-        FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, p.stream));
-        FDLB_HIP(hipStreamSynchronize(p.stream));
-    }
-    auto v64 = vel_table<double>(p);
-    FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel64, v64.data(), v64.size() * sizeof(v64[0]), hipMemcpyHostToDevice,
-                            p.stream));
+    if (p.d.precision != FDLB_FP64)
+        FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel, p.vel32.data(), p.vel32.size() * sizeof(p.vel32[0]),
+                                hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel64, p.vel64.data(), p.vel64.size() * sizeof(p.vel64[0]),
+                            hipMemcpyHostToDevice, p.stream));
     if (p.d.precision == FDLB_FP64)
-        FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel, v64.data(), v64.size() * sizeof(v64[0]), hipMemcpyHostToDevice,
-                                p.stream));
+        FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_vel, p.vel64.data(), p.vel64.size() * sizeof(p.vel64[0]),
+                                hipMemcpyHostToDevice, p.stream));
     FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_wall, p.wall, sizeof(p.wall), hipMemcpyHostToDevice, p.stream));
     FDLB_HIP(hipMemcpyAsync(p.d_work + p.off_wnat, p.w.data(), p.q * sizeof(double), hipMemcpyHostToDevice, p.stream));
-    FDLB_HIP(hipStreamSynchronize(p.stream));  // host tables above are temporaries
+    FDLB_HIP(hipStreamSynchronize(p.stream));
     p.bound = true;
     p.seeded = false;
 }
@@ -652,6 +654,50 @@ void step(fdlb_problem& p, int64_t n) {
     if (n < 0) throw Error(FDLB_EINVAL, "nsteps must be >= 0");
     unfreeze(p);
     enqueue_steps(p, n);
+}
+
+// fdlb_step on a caller's state buffer with the library's static device array as the workspace
+// (for callers that cannot allocate).  The problem's binding, if any, is set aside for the call
+// and restored afterwards; nothing is allocated, and no graph is captured or replayed.
+void step_static(fdlb_problem& p, void* d_state, int64_t n, void* stream) {
+    if (!d_state) throw Error(FDLB_EINVAL, "device state buffer must not be NULL");
+    if ((uintptr_t)d_state & 255) throw Error(FDLB_EINVAL, "device state buffer must be 256-byte aligned");
+    if (n < 0) throw Error(FDLB_EINVAL, "nsteps must be >= 0");
+    if (p.d.precision == FDLB_MIXED) throw Error(FDLB_EINVAL, "fdlb_step_static takes FDLB_FP32 or FDLB_FP64 problems");
+    if (p.off_io > (size_t)FDLB_STATIC_SCRATCH_BYTES)
+        throw Error(FDLB_EINVAL, "problem needs " + std::to_string(p.off_io) + " bytes of workspace; the static scratch holds " +
+                                     std::to_string((size_t)FDLB_STATIC_SCRATCH_BYTES));
+    char* scratch = static_scratch();
+    struct Saved {
+        fdlb_problem& p;
+        char *st, *wk;
+        hipStream_t s;
+        int parity;
+        ~Saved() {
+            p.d_state = st;
+            p.d_work = wk;
+            p.stream = s;
+            p.parity = parity;
+        }
+    } saved{p, p.d_state, p.d_work, p.stream, p.parity};
+    p.d_state = (char*)d_state;
+    p.d_work = scratch;
+    p.stream = (hipStream_t)stream;
+    p.parity = 0;
+    // Everything the kernels read is written here first: tables, a fresh control block (by a
+    // kernel, not a memset), and the moments and wall fluxes of the given state.
+    // (the float kernels read the float table, the double kernels the double one: the places
+    // step_args and refresh_moments take them from)
+    if (p.prec == FDLB_FP32)
+        FDLB_HIP(hipMemcpyAsync(scratch + p.off_vel, p.vel32.data(), p.vel32.size() * sizeof(p.vel32[0]),
+                                hipMemcpyHostToDevice, p.stream));
+    else
+        FDLB_HIP(hipMemcpyAsync(scratch + p.off_vel64, p.vel64.data(), p.vel64.size() * sizeof(p.vel64[0]),
+                                hipMemcpyHostToDevice, p.stream));
+    FDLB_HIP(hipMemcpyAsync(scratch + p.off_wall, p.wall, sizeof(p.wall), hipMemcpyHostToDevice, p.stream));
+    launch_ctrl_reset(ctrl(p), p.stream);
+    refresh_moments(p);
+    enqueue_chunk(p, 0, p.tile, n);
 }
 
 void step_timed(fdlb_problem& p, int64_t n, double* ms_step, double* ms_reduce) {
