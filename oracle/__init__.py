@@ -19,9 +19,11 @@ build.py       compiles fdlb_oracle.c with gcc
 
 Parity status: every function here is pinned by tests against facts the paper
 or mathematics fixes (printed Table I, closed-form moments, closed-form
-relaxation and transport responses, conservation, free-molecular Couette,
-convergence to the semi-analytic Couette solution, the printed Eqs. 10-11,
-symmetries, dense solves).  The Table II drag/flow-rate values and the
+relaxation and transport responses, the residual of every step in closed form
+for free-molecular flow on a periodic box, conservation with half- and
+full-range walls, free-molecular Couette, convergence to the semi-analytic
+Couette solution for half- and full-range rules, the printed Eqs. 10-11,
+symmetries, grid self-convergence of the cavity, dense solves).  The Table II drag/flow-rate values and the
 figure curves are parity unpinned (their definitions and reference solvers
 are not in the paper).
 """

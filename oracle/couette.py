@@ -8,6 +8,12 @@ for the 2-nodes-per-half set (Eqs. 10-11, obtained along the lines of its
 moment-method reference); this module derives it for any number n of nodes
 per half-line, and also evaluates the printed Eqs. (10)-(11).
 
+The same derivation holds for a full-range xi_y rule (the paper's standard
+lattice) with the wall density read as the impermeability condition: the
+modes pair +xi_k with -xi_k over the positive nodes, and a zero node (odd
+full-range rules) adds w_0 to both sides of sum_k w_k / (1 + mu xi_k) = 1 and
+drops out of the dispersion relation; its amplitude is B_0 = u_x.
+
 Derivation (own).  With rho = 1 and u_y = 0 the populations are
 f_alpha = w_alpha (1 + xi_x,alpha B_k(y)), k the index of xi_y,alpha, and the
 x-momentum part obeys  xi_k B_k' = -(B_k - u_x)/Kn,  u_x = sum_k w_k B_k.
@@ -58,22 +64,35 @@ def _roots(xk, wk):
     return out
 
 
+def _positive_half(kind: str, n: int):
+    """Positive nodes (ascending) and their weights of a xi_y rule, in mpmath."""
+    if kind == "half":
+        x, w = quadrature.half_range_mp(n)
+        return list(x), list(w)
+    if kind == "full":
+        x, w = quadrature.full_range_mp(n)
+        pairs = [(xi, wi) for xi, wi in zip(x, w) if xi > mp.mpf(10) ** (-30)]
+        return [p[0] for p in pairs], [p[1] for p in pairs]
+    raise ValueError(f"unknown rule kind {kind!r}")
+
+
 class CouetteSolution:
-    """Semi-analytic steady Couette solution for the n-nodes-per-half xi_y set.
+    """Semi-analytic steady Couette solution for a xi_y rule: n nodes per half-line
+    (kind "half", the default) or an n-node full-range rule (kind "full").
 
     Only the xi_y rule matters: the odd-in-xi_x part of f is linear in xi_x, so any
     xi_x rule that integrates xi_x^2 exactly gives the same solution."""
 
-    def __init__(self, n_per_half: int, kn: float, u_w: float = 1.0):
+    def __init__(self, n_per_half: int, kn: float, u_w: float = 1.0, kind: str = "half"):
         with mp.workdps(_DPS):
-            x, w = quadrature.half_range_mp(n_per_half)
             self.kn = mp.mpf(kn)
             self.u_w = mp.mpf(u_w)
-            self.xk, self.wk = list(x), list(w)   # positive half; total weight of the half is 1/2
+            self.xk, self.wk = _positive_half(kind, n_per_half)   # positive nodes and weights
             self.mu = _roots(self.xk, self.wk)
             kn_ = self.kn
-            # Unknowns: C, D_1..D_{n-1}.  Conditions at y = 1/2 for the arriving nodes -xi_k.
-            n = n_per_half
+            # Unknowns: C, D_1..D_{m-1} (m positive nodes).  Conditions at y = 1/2 for the
+            # arriving nodes -xi_k.
+            n = len(self.xk)
             A = mp.matrix(n, n)
             rhs = mp.matrix(n, 1)
             for r, xpos in enumerate(self.xk):
@@ -117,7 +136,8 @@ class CouetteSolution:
 def free_molecular_pxy(u_w: float = 1.0) -> float:
     """Kn -> infinity: each plate's emission crosses the gap unchanged and
     p_xy = -2 u_w sum_{xi>0} w xi = -sqrt(2/pi) u_w, for any half-range set
-    (the rule integrates xi on the half-line exactly: 1/sqrt(2 pi))."""
+    (the rule integrates xi on the half-line exactly: 1/sqrt(2 pi)).  A full-range
+    rule gives -2 u_w sum_{xi>0} w xi with its own half-line sum."""
     return float(-mp.sqrt(2 / mp.pi) * u_w)
 
 

@@ -20,7 +20,10 @@
  *   - walls re-emit the populations that leave the wall (xi . n > 0, n the
  *     inward normal) as w_alpha rho_w (1 + xi_t u_w) (Eq. 8, weighted form),
  *     with rho_w from the impermeability sum of Eq. (9) over the populations
- *     that arrive at the wall (xi . n < 0).
+ *     that arrive at the wall (xi . n < 0), divided by the flux the emission
+ *     carries per unit wall density.  For a half-range rule that flux is
+ *     (2 pi)^(-1/2) and this is Eq. (9) as printed; for a full-range rule (the
+ *     paper's standard lattice with walls) it keeps the wall impermeable.
  *
  * Readings where the paper is silent:
  *   grid: cell-centred cells, walls on the outer cell faces, the wall value
@@ -54,8 +57,6 @@ typedef struct {
 } oracle_problem;
 
 #define IDX(P, a, x, y) (((size_t)(a) * (size_t)(P)->ny + (size_t)(y)) * (size_t)(P)->nx + (size_t)(x))
-
-static const double SQRT_2PI = 2.5066282746310005024157652848110452530069867406099;
 
 /* Eqs. (6)-(7): rho = sum f, rho u = sum xi f.  Output arrays of nx*ny, [y][x]. */
 void oracle_moments(const oracle_problem *P, const double *f, double *rho, double *ux, double *uy)
@@ -141,7 +142,23 @@ static int wall_active(const oracle_problem *P, int wall)
     return (wall == WALL_BOTTOM || wall == WALL_TOP) ? !P->periodic_y : !P->periodic_x;
 }
 
-/* Eq. (9) for a general wall: rho_w = -(2 pi)^(1/2) sum_{xi.n<0} (xi.n) g_alpha at the wall. */
+/* Flux leaving a wall per unit wall density under Eq. (8): sum over xi.n > 0 of (xi.n) w_alpha.
+ * (The factor 1 + xi_t u_w adds nothing: the tangential rule is symmetric.)  A half-range rule
+ * integrates xi over the half-line exactly, so there it is (2 pi)^(-1/2). */
+static double emitted_flux(const oracle_problem *P, int wall)
+{
+    double s = 0.0;
+    for (int a = 0; a < P->q; ++a) {
+        double xn = xi_normal(P, wall, a);
+        if (xn > 0.0) s += xn * P->w[a];
+    }
+    return s;
+}
+
+/* Eq. (9) for a general wall, read as the impermeability condition: the wall density whose
+ * emission carries away exactly the flux that arrives,
+ *   rho_w = -sum_{xi.n<0} (xi.n) g_alpha / sum_{xi.n>0} (xi.n) w_alpha,
+ * which is -(2 pi)^(1/2) sum_{xi.n<0} (xi.n) g_alpha for a half-range rule. */
 static double wall_density(const oracle_problem *P, const double *g, int wall, int pos)
 {
     int x, y;
@@ -151,7 +168,7 @@ static double wall_density(const oracle_problem *P, const double *g, int wall, i
         double xn = xi_normal(P, wall, a);
         if (xn < 0.0) s += xn * g[IDX(P, a, x, y)];
     }
-    return -SQRT_2PI * s;
+    return -s / emitted_flux(P, wall);
 }
 
 /* Eq. (8), weighted form: populations leaving the wall are w_alpha rho_w (1 + xi_t u_w). */
