@@ -24,8 +24,15 @@
  *  - Walls: index 0 bottom (y = 0), 1 top (y = 1), 2 left (x = 0), 3 right
  *    (x = 1).  wall_u[i] is the wall's tangential speed: along +x for the
  *    bottom/top walls, along +y for the left/right walls.  A periodic axis has
- *    no walls: the speeds given for them are ignored.  The velocity rule on a
- *    bounded axis must be half-range (see fdlb_problem_create).
+ *    no walls: the speeds given for them are ignored.  Either kind of rule
+ *    may serve either kind of axis: a half-range rule on a bounded axis is the
+ *    paper's method, a full-range one its standard lattice.
+ *  - Wall density (Eq. 9): the flux arriving at a wall face divided by the
+ *    flux the emission of Eq. (8) carries away per unit density,
+ *    rho_w = sum_{xi.n<0} |xi.n| f / sum_{xi.n>0} (xi.n) w, which keeps every
+ *    wall impermeable.  For a half-range rule the denominator is
+ *    (2 pi)^(-1/2) and this is Eq. (9) as printed.  A population moving along
+ *    a wall (xi.n = 0, odd full-range rules) neither arrives nor leaves.
  *  - Velocity order: alpha = j * Q_x + i, i indexing the x rule and j the y
  *    rule, both rules with nodes ascending.
  *  - Host arrays of cell fields are row-major [y][x] (N_x fastest), doubles.
@@ -128,10 +135,8 @@ typedef struct fdlb_problem fdlb_problem; /* opaque host handle */
  * Validate a description and build the velocity set, the time step
  * dt = cfl / max_alpha(|xi_x| N_x / l_x [x bounded] + |xi_y| N_y / l_y [y bounded])
  * and omega = dt / Kn (0 for Kn = INFINITY).  Cells are l_x / N_x by l_y / N_y.  Host only (no GPU call); the
- * handle owns only host memory.  FDLB_EINVAL for bad sizes or rules, and for
- * a full-range rule on a bounded axis (Eq. (9) makes a wall impermeable only
- * for half-range nodes: sqrt(2 pi) sum_{xi > 0} w xi = 1); full-range rules
- * serve periodic axes.  Every rule needs at least 2 nodes (per half-line
+ * handle owns only host memory.  FDLB_EINVAL for bad sizes or rules.
+ * Every rule needs at least 2 nodes (per half-line
  * for half-range) so that it integrates xi^2 exactly and the relaxation of
  * Eqs. (1), (5) conserves momentum; FDLB_EINVAL otherwise.  FDLB_EUNSTABLE if
  * cfl > 1 or omega > 1 and allow_unstable is 0.

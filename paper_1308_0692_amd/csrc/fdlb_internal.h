@@ -47,10 +47,12 @@ struct VelEntry {
 
 // Per-wall constants of Eq. (9) in deviation form (double).  For the wall's
 // inward normal n and tangent t, over the arriving half (xi . n < 0):
-// A = sum |xi_n| w, Bn = sum |xi_n| w xi_n, Bt = sum |xi_n| w xi_t, and
-// c0 = sqrt(2 pi) A - 1 (zero in exact arithmetic).
+// A = sum |xi_n| w, Bn = sum |xi_n| w xi_n, Bt = sum |xi_n| w xi_t; k = 1 / E with
+// E = sum xi_n w over the leaving half (the flux the emission carries per unit wall
+// density; (2 pi)^(-1/2) for a half-range rule), so rho_w = k (A + arriving flux of h);
+// c0 = k A - 1 (zero in exact arithmetic for the symmetric rules).
 struct WallConst {
-    double A, Bn, Bt, c0, u;
+    double A, Bn, Bt, c0, k, u;
     int32_t active;
     int32_t pad;
 };

@@ -42,7 +42,6 @@ namespace fdlb {
 
 namespace {
 
-constexpr double SQRT_2PI = 2.50662827463100050241576528481104525;
 constexpr int NUM_XCD = 8;
 
 #ifdef FDLB_MIN_WAVES  // ask the register allocator for this many waves per SIMD
@@ -312,7 +311,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
                 const double s = (1.0 - omega) * phi +
                                  omega * (A.mom_in[o] * W.A + sn * A.mom_in[plane + o] * W.Bn +
                                           A.mom_in[2 * plane + o] * W.Bt);
-                const double P = W.c0 + SQRT_2PI * s;
+                const double P = W.c0 + W.k * s;
                 Px[r] = (T)P;
                 Qx[r] = (T)(W.u * (1.0 + P));
             }
@@ -335,7 +334,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
             const double wr = A.mom_in[o], wx = A.mom_in[plane + o], wy = A.mom_in[2 * plane + o];
             const double phi = A.phi_in[yw * L + x0 + v];
             const double s = (1.0 - omega) * phi + omega * (wr * W.A + sn * wy * W.Bn + wx * W.Bt);
-            const double P = W.c0 + SQRT_2PI * s;
+            const double P = W.c0 + W.k * s;
             Py[v] = (T)P;
             Qy[v] = (T)(W.u * (1.0 + P));
         }
@@ -941,7 +940,7 @@ __global__ void __launch_bounds__(256) wall_profile_kernel(const T* __restrict__
             s += -n_ * ((1.0 - omega) * f + omega * (v.w * r + v.wx * jx + v.wy * jy));
         }
     }
-    const double P = wc.c0 + SQRT_2PI * s;  // rho_w - 1
+    const double P = wc.c0 + wc.k * s;  // rho_w - 1
     double fr = 0, ft = 0, fp = 0;
     for (int e = 0; e < q; ++e) {
         const VelEntry<double> v = vel[e];

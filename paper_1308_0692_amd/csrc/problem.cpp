@@ -21,8 +21,6 @@ namespace fdlb {
 
 namespace {
 
-constexpr double SQRT_2PI = 2.50662827463100050241576528481104525;
-
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 void rule_uncached(int kind, int n, std::vector<double>& x, std::vector<double>& w);
@@ -125,13 +123,6 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
         throw Error(FDLB_EINVAL, "a periodic axis must have exactly one cell");
     if (!d.periodic_x && d.nx < 2) throw Error(FDLB_EINVAL, "a bounded axis needs at least 2 cells");
     if (!d.periodic_y && d.ny < 2) throw Error(FDLB_EINVAL, "a bounded axis needs at least 2 cells");
-    // Eq. (9) takes the wall density as sqrt(2 pi) times the arriving flux; the wall is then
-    // impermeable because a half-range rule integrates xi over each half-line exactly (sum of
-    // w xi over xi > 0 is (2 pi)^(-1/2)).  A full-range rule does not, and such a wall creates or
-    // destroys mass (from rest: +87 % in 200 steps for 4 nodes, -75 % for 3).
-    if ((!d.periodic_x && d.qx_kind == FDLB_FULL) || (!d.periodic_y && d.qy_kind == FDLB_FULL))
-        throw Error(FDLB_EINVAL, "a bounded axis needs a half-range rule (the wall of Eq. (9) is impermeable only "
-                                 "for half-range nodes)");
     // The relaxation conserves momentum only if each rule integrates xi^2 exactly (sum w xi^2 = 1):
     // a Gauss rule of n nodes (per half-line) integrates degree 2n - 1, so n >= 2.  One node per
     // half-line gives sum w xi^2 = 2 / pi, and a one-node full-range rule has xi = 0 only.
@@ -181,13 +172,17 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     if (!d.allow_unstable && (d.cfl > 1.0 || p.omega > 1.0))
         throw Error(FDLB_EUNSTABLE, "explicit scheme unstable: need cfl <= 1 and dt/Kn <= 1 (dt/Kn = " +
                                         std::to_string(p.omega) + ")");
-    // Wall constants of Eq. (9) in deviation form.
+    // Wall constants of Eq. (9) in deviation form.  The wall density is the arriving flux over
+    // the flux its emission (Eq. 8) carries per unit density, E = sum over leaving xi of
+    // xi_n w: the wall is then impermeable for any rule.  A half-range rule integrates xi over
+    // the half-line exactly, E = (2 pi)^(-1/2), and this is Eq. (9) as printed; a full-range
+    // rule on a walled axis (the standard lattice) has its own E (0.444 for 4 nodes).
     for (int wl = 0; wl < 4; ++wl) {
         WallConst& W = p.wall[wl];
         W = WallConst{};
         W.active = (wl == BOTTOM || wl == TOP) ? !d.periodic_y : !d.periodic_x;
         W.u = d.wall_u[wl];
-        long double A = 0, Bn = 0, Bt = 0;
+        long double A = 0, Bn = 0, Bt = 0, E = 0;
         for (int a = 0; a < p.q; ++a) {
             const double xn = wl == BOTTOM ? p.xi_y[a] : wl == TOP ? -p.xi_y[a] : wl == LEFT ? p.xi_x[a] : -p.xi_x[a];
             const double xt = (wl == BOTTOM || wl == TOP) ? p.xi_x[a] : p.xi_y[a];
@@ -195,12 +190,16 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
                 A += (long double)(-xn) * p.w[a];
                 Bn += (long double)(-xn) * p.w[a] * xn;
                 Bt += (long double)(-xn) * p.w[a] * xt;
+            } else if (xn > 0) {
+                E += (long double)xn * p.w[a];
             }
         }
+        const long double k = 1.0L / E;
         W.A = (double)A;
         W.Bn = (double)Bn;
         W.Bt = (double)Bt;
-        W.c0 = (double)((long double)SQRT_2PI * A - 1.0L);
+        W.k = (double)k;
+        W.c0 = (double)(k * A - 1.0L);
     }
     // Velocity table grouped by quadrant: (+,+), (-,+), (+,-), (-,-); zero counts as +.
     p.quad_order.clear();

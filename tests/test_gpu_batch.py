@@ -162,6 +162,32 @@ def test_sweep_full_size_sampled_members_match_oracle(F):
             assert float(np.abs(rho - r0).max()) <= 2e-5, (t, i)
 
 
+def test_sweep_converged_members_match_converged_oracle(F):
+    """The whole 64-cavity sweep solved to R < 1e-8 as the benchmark solves it (one mixed-
+    precision batch on its autotuned tile, graph-captured chunks, tail re-tiling): three members
+    (Kn 0.044 with 12 x 12 velocities, Kn 0.148 and Kn 7.26 with 8 x 8, all 64^2) against the
+    oracle converged to 1e-11, within the FP32 bar of 2e-5 on rho and u."""
+    cases = W.c3_instances()
+    b = F.Batch(cases, precision="mixed")
+    b.autotune(steps=2)
+    for i in range(len(cases)):
+        b.init_equilibrium(i)
+    status, reps = b.solve(1e-8, 200000, check_every=200)
+    assert status == 0 and all(r["status"] == 0 for r in reps)
+    for i in (62, 19, 31):
+        c = cases[i]
+        assert c.nx == 64
+        op = OP.from_case(c)
+        fo, n, hist = op.solve(op.equilibrium(), 1e-11, 400000)
+        assert hist[-1] < 1e-11
+        r0, ux0, uy0 = op.moments(fo)
+        rho, ux, uy, _ = b.moments(i)
+        eu = float(np.hypot(ux - ux0, uy - uy0).max() / np.hypot(ux0, uy0).max())
+        er = float(np.abs(rho - r0).max())
+        print(f"member {i} (Kn {c.kn:.4f}, Q {c.q}): eps_u {eu:.2e}, eps_rho {er:.2e}")
+        assert eu <= 2e-5 and er <= 2e-5, (i, eu, er)
+
+
 def test_tail_retiling_keeps_results_and_restores_tiles(F):
     """With tail re-tiling the last instances switch to their single-problem tile:
     every instance still converges to its single-solve answer (the steps differ at most by the

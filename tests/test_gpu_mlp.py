@@ -7,7 +7,10 @@ rounding itself moves outputs by <= 7e-3 and gradients by <= 2.4e-3 from plain F
   outputs   vs bf16-emulating oracle: rms <= 1e-3 rms(y), max <= 1e-2 max|y|
             vs plain FP64 oracle:     max <= 3e-2 max|y|
   gradient  vs bf16-emulating oracle: ||g - g_ref|| <= 2e-4 ||g_ref||; loss within 1e-4
-            vs plain FP64 oracle:     ||g - g_ref|| <= 1e-2 ||g_ref||
+            vs plain FP64 oracle:     ||g - g_ref|| <= 1e-2 ||g_ref||, and per element
+                                      |g - g_ref| <= 6 sigma + 1e-5 (|g_ref| + max|g_ref|),
+                                      sigma the oracle's Monte Carlo spread of the bf16
+                                      rounding error on that element (loss: 6 sigma_E)
   Adam      fp32 update vs FP64 oracle: <= 1e-6 relative (three steps)
 Sizes are ragged (not multiples of the 64-sample tile)."""
 import math
@@ -69,6 +72,15 @@ def test_gradient_matches_oracle(F, n, hidden):
     assert np.linalg.norm(g - gb) <= 2e-4 * np.linalg.norm(gb), np.linalg.norm(g - gb) / np.linalg.norm(gb)
     assert abs(E - Eb) <= 1e-4 * Eb
     assert np.linalg.norm(g - g64) <= 1e-2 * np.linalg.norm(g64)
+    # element by element against plain FP64: within 6 standard deviations of the error that
+    # bf16 operands in the hidden products put on that element (Monte Carlo spread of the
+    # oracle), plus float32 rounding elsewhere; the loss likewise
+    sE, sg = mlp.rounding_spread(theta, a, t, 128, hidden, runs=32)
+    m = np.abs(g64).max()
+    bar = 6 * sg + 1e-5 * (np.abs(g64) + m)
+    worst = np.argmax(np.abs(g - g64) - bar)
+    assert np.all(np.abs(g - g64) <= bar), (worst, g[worst], g64[worst], sg[worst])
+    assert abs(E - E64) <= 6 * sE + 1e-6 * E64, (E, E64, sE)
     # every block of the parameter vector carries gradient (no layer left out)
     k = 0
     for o, i in mlp.layer_shapes(128, hidden):

@@ -78,6 +78,26 @@ def test_fp64_couette_steps(F, nsteps):
         assert np.abs(rg - ro).max() <= 1e-13
 
 
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_left_right_wall_profiles(F, prec, bar):
+    """Face state along the x walls (plates at x = 0 and 1 sliding along y), against the
+    oracle after identical step counts: density, tangential velocity and stress per face.  A
+    cavity adds all four walls with a moving lid."""
+    for case, walls in ((W.couette_x(64, kn=0.2), (LEFT, RIGHT)),
+                        (W.cavity(30, ny=26, kn=0.3, order=3), (BOTTOM, TOP, LEFT, RIGHT))):
+        gp = F.Problem(case, precision=prec)
+        op = OP.from_case(case)
+        gp.init_equilibrium()
+        gp.step(500)
+        fo = op.step(op.equilibrium(), 500)
+        for wall in walls:
+            rg, ug, pg = gp.wall_profile(wall)
+            ro, uo, po = op.wall_profile(fo, wall)
+            assert np.abs(ug - uo).max() <= bar * np.abs(uo).max(), (case.name, wall)
+            assert np.abs(pg - po).max() <= bar * np.abs(po).max(), (case.name, wall)
+            assert np.abs(rg - ro).max() <= bar, (case.name, wall)
+
+
 def _fitting_tiles(F, case, prec):
     p = F.Problem(case, precision=prec, bind=False)
     out = []
@@ -184,9 +204,11 @@ def test_free_molecular_cavity(F, prec, bar):
 
 def test_fp64_couette_converged(F):
     """C1 to R < 1e-13 with a per-step check.  Near 1e-13 the residual itself carries
-    rounding noise (the per-step change is a difference of nearly equal velocities), so
-    the first step below the tolerance may differ by one; the states are compared at the
-    oracle's step count, and the residual histories where they are well above round-off."""
+    rounding noise (the per-step change is a difference of nearly equal velocities, ~1e-14
+    absolute here), and R falls by only 0.4 % per step, so the first step below the tolerance
+    may differ by a few steps: it may differ only over steps where R lies within that noise of
+    the tolerance.  The states are compared at the oracle's step count, and the residual
+    histories where they are well above round-off."""
     gp = F.Problem(W.C1, precision="fp64")
     op = OP.from_case(W.C1)
     gp.init_equilibrium()
@@ -194,9 +216,11 @@ def test_fp64_couette_converged(F):
     fo, n, hist = op.solve(op.equilibrium(), 1e-13, 100000)
     assert rep["status"] == 0
     assert rep["first_below"] == rep["steps"]
-    assert abs(rep["first_below"] - n) <= 1
     assert gp.last_residual()[1] == rep["steps"]
     h = rep["history"]
+    lo, hi = sorted((rep["first_below"], n))
+    for k in range(lo, hi + 1):
+        assert abs(hist[min(k, n) - 1] - 1e-13) <= 1e-14 and abs(h[min(k, len(h)) - 1] - 1e-13) <= 1e-14, k
     # The per-step change carries absolute rounding noise of ~1e-16 |u|, so R agrees to
     # ~1e-16 / R relative: bound the difference by 1e-11 R + 1e-14.
     for k in (1, 2, 10, 100, 1000, 3000, 6000):

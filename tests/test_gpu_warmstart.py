@@ -63,6 +63,28 @@ def test_warm_start_saves_steps_on_held_out_kn(F, trained):
             assert float(np.abs(rho - r0).max()) <= 2e-5
 
 
+def test_warm_started_solve_matches_converged_oracle_at_every_kn(F, trained):
+    """A warm-started mixed-precision solve of a 64^2 cavity with 8 x 8 velocities (a finer grid
+    and a larger velocity set than the network was trained on) converges to the oracle's answer
+    at small, middle and large Kn: within 2e-5 on rho and u of the oracle converged to 1e-11."""
+    from paper_1308_0692_amd import warmstart
+    net, train_kn = trained
+    for kn in (0.013, 0.21, 4.7):
+        case = W.cavity(64, kn=kn, u_w=0.01, order=4)
+        p = F.Problem(case, precision="mixed")
+        warmstart.seed(p, net, kn, 0.01)
+        rep = p.solve(1e-8, 400000, check_every=200)
+        assert rep["status"] == 0
+        rho, ux, uy, _ = p.moments()
+        op = OP.from_case(case)
+        fo, _, hist = op.solve(op.equilibrium(), 1e-11, 400000)
+        assert hist[-1] < 1e-11
+        r0, ux0, uy0 = op.moments(fo)
+        eu, er = eps_u(ux, uy, ux0, uy0), float(np.abs(rho - r0).max())
+        print(f"Kn {kn}: warm start {rep['steps']} steps, eps_u {eu:.2e}, eps_rho {er:.2e}")
+        assert eu <= 2e-5 and er <= 2e-5, (kn, eu, er)
+
+
 def test_warm_start_keeps_the_mass(F, trained):
     from paper_1308_0692_amd import warmstart
     net, _ = trained

@@ -343,15 +343,21 @@ def test_problems_created_from_many_threads_at_once(F):
     assert sorted(results) == sorted(orders)
 
 
-def test_full_range_rule_on_a_bounded_axis_is_rejected(F):
-    """Walls need half-range nodes on their normal axis (Eq. 9 is impermeable only then); a
-    full-range rule is accepted on a periodic axis (the channel's GH3 in x)."""
+def test_full_range_rule_on_a_bounded_axis_is_accepted(F):
+    """Walls take either kind of rule on their normal axis: Eq. (9) read as impermeability
+    divides by the rule's own leaving flux (the standard lattice D2Q16 is 4 x 4 full-range
+    nodes).  The time step follows the rule's largest speed as for half-range sets."""
     from paper_1308_0692_amd import _lib
-    for qx, qy in ((("full", 4), ("half", 4)), (("half", 4), ("full", 3)), (("full", 4), ("full", 4))):
+    for qx, qy in ((("full", 4), ("half", 4)), (("half", 4), ("full", 3)), (("full", 4), ("full", 4)),
+                   (("full", 5), ("full", 6))):
         d = _lib.make_desc(16, 16, False, False, (0.0, 0.01, 0.0, 0.0), 0.1, qx, qy)
         h = C.c_void_p()
-        assert _lib.lib.fdlb_problem_create(C.byref(d), C.byref(h)) == _lib.EINVAL, (qx, qy)
-        assert not h.value and b"half-range rule" in _lib.lib.fdlb_last_error()
+        assert _lib.lib.fdlb_problem_create(C.byref(d), C.byref(h)) == _lib.OK, (qx, qy)
+        xs, _ = _lib.quad_full_range(qx[1]) if qx[0] == "full" else _lib.quad_half_range(qx[1])
+        ys, _ = _lib.quad_full_range(qy[1]) if qy[0] == "full" else _lib.quad_half_range(qy[1])
+        assert _lib.lib.fdlb_problem_dt(h) == pytest.approx(0.9 / (16 * (np.abs(xs).max() + np.abs(ys).max())),
+                                                            rel=1e-15)
+        _lib.lib.fdlb_problem_destroy(h)
     for case in (W.C1, W.couette_x(40, qy=("full", 3)), W.couette(30, qx=("full", 2))):
         assert F.Problem(case, bind=False).q > 0
 

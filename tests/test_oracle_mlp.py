@@ -1,6 +1,7 @@
 """Pins of the FP64 warm-start network oracle (oracle/mlp.py) against facts fixed by the
 mathematics: finite differences, closed-form forward passes, the output-bias gradient,
-Adam's first step, and bfloat16 rounding of values whose rounding is known."""
+Adam's first step, bfloat16 rounding of values whose rounding is known, and the spread of the
+rounding error against the error of exact bfloat16 rounding."""
 import numpy as np
 import pytest
 
@@ -134,6 +135,37 @@ def test_bf16_products_stay_close_to_fp64():
     _, g = mlp.gradient(theta, a, t)
     _, gb = mlp.gradient(theta, a, t, bf16=True)
     assert np.linalg.norm(gb - g) <= 3e-2 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("n,hidden", [(777, 4), (130, 2), (65, 4), (1, 3), (3000, 4)])
+def test_rounding_spread_predicts_the_bf16_error(n, hidden):
+    """The Monte Carlo spread of the gradient under random operand errors of the bf16 rounding's
+    size predicts the actual error of exact bfloat16 rounding at those points, element by
+    element: every element within 6 sigma of plain FP64, and the normalised errors neither far
+    below 1 (a spread that would hide real faults) nor above it (one that would be too tight)."""
+    f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)  # noqa: E731
+    theta = f32(W.mlp_params(3 + n, 128, hidden))
+    a, t = W.mlp_samples(n, 13 + n)
+    a, t = f32(a), f32(t)
+    Eb, gb = mlp.gradient(theta, a, t, 128, hidden, bf16=True)
+    E64, g64 = mlp.gradient(theta, a, t, 128, hidden)
+    sE, sg = mlp.rounding_spread(theta, a, t, 128, hidden, runs=32)
+    assert np.all(np.abs(gb - g64) <= 6 * sg)
+    assert abs(Eb - E64) <= 6 * sE
+    z = (gb - g64)[sg > 0] / sg[sg > 0]
+    assert 0.4 <= np.sqrt(np.mean(z * z)) <= 1.2
+    # the spread is linear in the rounding size and vanishes without rounding
+    _, sg2 = mlp.rounding_spread(theta, a, t, 128, hidden, runs=32, u=2.0 ** -9)
+    assert 0.4 <= np.median(sg2[sg > 0] / sg[sg > 0]) <= 0.6
+    assert np.all(mlp.rounding_spread(theta, a, t, 128, hidden, runs=2, u=0.0)[1] == 0)
+
+
+def test_rounding_spread_is_zero_without_hidden_products():
+    """One hidden layer has no 128 x 128 product, so nothing is rounded to bf16."""
+    theta = W.mlp_params(5, 128, 1)
+    a, t = W.mlp_samples(50, 6)
+    sE, sg = mlp.rounding_spread(theta, a, t, 128, 1, runs=4)
+    assert sE == 0 and np.all(sg == 0)
 
 
 def test_training_lowers_the_loss():
