@@ -411,6 +411,8 @@ int fdlb_batch_init_equilibrium_dev(fdlb_batch *b, int i, const float *d_rho, co
 int fdlb_batch_solve(fdlb_batch *b, double tol, int64_t max_steps, int32_t check_every,
                      int32_t use_graph, fdlb_report *reports);
 int fdlb_batch_moments(fdlb_batch *b, int i, double *rho, double *ux, double *uy, double *pxy);
+/* Face state along one wall of instance i, as fdlb_wall_profile gives it for a problem. */
+int fdlb_batch_wall_profile(fdlb_batch *b, int i, int wall, double *rho, double *u_t, double *pxy);
 int fdlb_batch_state_download(fdlb_batch *b, int i, double *f_host);
 /* Number of velocities of instance i (the Q of its state layout), or FDLB_EINVAL for an index
  * out of range. */

@@ -289,6 +289,14 @@ class Batch:
         check(_lib.lib.fdlb_batch_moments(self._h, int(i), *[_lib._dp(a) for a in out]))
         return tuple(out)
 
+    def wall_profile(self, i: int, wall: int):
+        """(rho, u_t, p_xy) of the face state along one wall of instance i."""
+        nx, ny = self.shapes[i]
+        n = nx if wall in (BOTTOM, TOP) else ny
+        out = [np.empty(n) for _ in range(3)]
+        check(_lib.lib.fdlb_batch_wall_profile(self._h, int(i), int(wall), *[_lib._dp(a) for a in out]))
+        return tuple(out)
+
     def upload(self, i: int, f: np.ndarray):
         nx, ny = self.shapes[i]
         f = np.ascontiguousarray(f, dtype=np.float64)

@@ -104,6 +104,7 @@ def _load():
         "fdlb_batch_init_equilibrium_dev": (C.c_int, [vp, C.c_int, fp, fp, fp, C.c_int]),
         "fdlb_batch_solve": (C.c_int, [vp, C.c_double, i64, i32, i32, C.POINTER(Report)]),
         "fdlb_batch_moments": (C.c_int, [vp, C.c_int, dp, dp, dp, dp]),
+        "fdlb_batch_wall_profile": (C.c_int, [vp, C.c_int, C.c_int, dp, dp, dp]),
         "fdlb_batch_state_download": (C.c_int, [vp, C.c_int, dp]),
         "fdlb_batch_state_upload": (C.c_int, [vp, C.c_int, dp]),
         "fdlb_batch_problem_q": (C.c_int, [vp, C.c_int]),

@@ -30,6 +30,7 @@ void bind(fdlb_problem& p, void* d_state, void* d_work, void* stream);
 void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, const double* uy, int renorm);
 void init_equilibrium_dev(fdlb_problem& p, const float* rho, const float* ux, const float* uy, int renorm);
 void moments(fdlb_problem& p, double* rho, double* ux, double* uy, double* pxy);
+void wall_profile(fdlb_problem& p, int wall, double* rho, double* ut, double* pxy);
 void state_download(fdlb_problem& p, double* f);
 void state_upload(fdlb_problem& p, const double* f);
 }  // namespace fdlb
@@ -231,6 +232,9 @@ void batch_init_equilibrium_dev(fdlb_batch& b, int i, const float* rho, const fl
 }
 void batch_moments(fdlb_batch& b, int i, double* rho, double* ux, double* uy, double* pxy) {
     moments(inst(b, i), rho, ux, uy, pxy);
+}
+void batch_wall_profile(fdlb_batch& b, int i, int wall, double* rho, double* ut, double* pxy) {
+    wall_profile(inst(b, i), wall, rho, ut, pxy);
 }
 void batch_state_download(fdlb_batch& b, int i, double* f) { state_download(inst(b, i), f); }
 void batch_state_upload(fdlb_batch& b, int i, const double* f) { state_upload(inst(b, i), f); }
@@ -704,6 +708,13 @@ int fdlb_batch_solve(fdlb_batch* b, double tol, int64_t max_steps, int32_t check
 int fdlb_batch_moments(fdlb_batch* b, int i, double* rho, double* ux, double* uy, double* pxy) {
     return guard_call([&] {
         batch_moments(bh(b), i, rho, ux, uy, pxy);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_wall_profile(fdlb_batch* b, int i, int wall, double* rho, double* u_t, double* pxy) {
+    return guard_call([&] {
+        batch_wall_profile(bh(b), i, wall, rho, u_t, pxy);
         return FDLB_OK;
     });
 }
