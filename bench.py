@@ -99,14 +99,21 @@ def time_to_residual(F, W):
     return out
 
 
+SOLO_STEPS = {}  # plain FP64 steps of every sweep instance, for the CPU extrapolation
+
+
 def sweep_c3(F, W, torch, net=None):
     """The 64-cavity sweep to R < 1e-8: one mixed-precision batch (autotuned float tile,
-    graph-captured chunks) against plain FP64 single-instance solves of the same cases (each
-    with its graph captured beforehand, outside the timing).  Error of every batch member
-    against its FP64 solution, at the same tolerance.  With a trained warm-start network the
-    batch is solved a second time from the network's seeds (seeding inside the timing)."""
+    graph-captured chunks) against plain FP64 single-instance solves of the same cases, timed
+    twice: with every instance's graph captured beforehand (outside the timing) and launched
+    step by step without graphs.  Every result's error is stated against the instance's FP64
+    solution continued to R < 1e-11 (untimed; the FP64 path equals the oracle to 1e-12 at equal
+    step counts): per instance for the batch (and the warm-started batch), and for the plain
+    FP64 solves stopped at 1e-8, whose own stopping error is of the same size.  With a trained
+    warm-start network the batch is solved a second time from the network's seeds (seeding
+    inside the timing)."""
     cases = W.c3_instances()
-    solo_wall, solo_steps, ref = 0.0, [], []
+    solo_wall, solo_steps, ref, solo_eps = 0.0, [], [], []
     for c in cases:
         p = F.Problem(c, precision="fp64")
         p.init_equilibrium()
@@ -117,13 +124,30 @@ def sweep_c3(F, W, torch, net=None):
         solo_steps.append(rep["steps"])
         if rep["status"] != 0:
             raise RuntimeError(f"{c.name}: plain FP64 solve did not converge")
+        at8 = p.moments()[:3]
+        r11 = p.solve(1e-11, 2000000, check_every=500)
+        if r11["status"] != 0:
+            raise RuntimeError(f"{c.name}: FP64 reference did not reach 1e-11")
         ref.append(p.moments()[:3])
+        solo_eps.append((eps_u(at8[1], at8[2], ref[-1][1], ref[-1][2]), float(abs(at8[0] - ref[-1][0]).max())))
         p.close()
+    SOLO_STEPS["c3"] = solo_steps
     log(f"  plain FP64, one instance at a time: {solo_wall:.2f} s, {sum(solo_steps)} steps")
+    nograph_wall = 0.0
+    for c in cases:
+        p = F.Problem(c, precision="fp64")
+        p.init_equilibrium()
+        rep = p.solve(1e-8, 200000, check_every=200, use_graph=False)
+        nograph_wall += rep["wall_s"]
+        p.close()
+    log(f"  plain FP64 without graph capture: {nograph_wall:.2f} s")
     b = F.Batch(cases, precision="mixed")
     ms = b.autotune(steps=3)
-    out = {"instances": len(cases), "tol": 1e-8,
-           "plain_fp64_solo": {"wall_s": round(solo_wall, 3), "steps": sum(solo_steps)}}
+    out = {"instances": len(cases), "tol": 1e-8, "reference": "each instance in FP64 continued to R < 1e-11",
+           "plain_fp64_solo": {"wall_s": round(solo_wall, 3), "steps": sum(solo_steps),
+                               "max_eps_u_vs_ref": max(e[0] for e in solo_eps),
+                               "max_eps_rho_vs_ref": max(e[1] for e in solo_eps)},
+           "plain_fp64_solo_no_graph": {"wall_s": round(nograph_wall, 3)}}
     for key in ("mixed_batch", "mixed_batch_warm"):
         if key == "mixed_batch_warm" and net is None:
             break
@@ -137,43 +161,92 @@ def sweep_c3(F, W, torch, net=None):
                 warmstart.seed_batch(b, i, net, c.kn, c.wall_u[1])
         status, reps = b.solve(1e-8, 200000, check_every=200)
         wall = time.perf_counter() - t0
-        eu, er = 0.0, 0.0
+        eu, er = [], []
         for i in range(len(cases)):
             rho, ux, uy, _ = b.moments(i)
-            eu = max(eu, eps_u(ux, uy, ref[i][1], ref[i][2]))
-            er = max(er, float(abs(rho - ref[i][0]).max()))
+            eu.append(eps_u(ux, uy, ref[i][1], ref[i][2]))
+            er.append(float(abs(rho - ref[i][0]).max()))
         steps = [r["steps"] for r in reps]
         f32 = [r["steps_fp32"] for r in reps]
         log(f"  {key}: {wall:.2f} s (status {status}), {sum(steps)} steps of which {sum(f32)} in float; "
-            f"max eps_u vs FP64 {eu:.2e}")
+            f"max eps_u vs the 1e-11 reference {max(eu):.2e}")
         out[key] = {"wall_s": round(wall, 3), "status": status, "steps": sum(steps),
                     "steps_fp32": sum(f32), "converged": sum(r["status"] == 0 for r in reps),
                     "tile": F.tile_describe("fp32", b.tile), "autotune_ms_per_step": round(ms, 4),
-                    "max_eps_u_vs_fp64": eu, "max_eps_rho_vs_fp64": er,
-                    "speedup_vs_plain_fp64": round(solo_wall / wall, 3)}
+                    "max_eps_u_vs_ref": max(eu), "max_eps_rho_vs_ref": max(er),
+                    "eps_u_vs_ref": [float(f"{v:.3e}") for v in eu],
+                    "eps_rho_vs_ref": [float(f"{v:.3e}") for v in er],
+                    "speedup_vs_plain_fp64": round(solo_wall / wall, 3),
+                    "speedup_vs_plain_fp64_no_graph": round(nograph_wall / wall, 3)}
     b.close()
     return out
 
 
+def kn_sweeps():
+    """Model columns of the paper's Couette figures and cavity table from this solver: slip and
+    p_xy / p_fm of Couette flow over Kn, and lid drag D and flow rate G of the cavity, for the
+    half-range lattice D2Q^h_16 and the standard lattice D2Q_16 (definitions in
+    paper_1308_0692_amd/sweeps.py; Kn of Eq. (1), the paper's is sqrt(2) times larger)."""
+    from paper_1308_0692_amd import sweeps
+    out = {"kn_convention": "Eq. (1); kn_printed = sqrt(2) kn", "couette": {}, "cavity": {}}
+    kns = [0.01, 0.03, 0.1, 0.3, 1.0, 3.0, 10.0]
+    t0 = time.perf_counter()
+    for lat in ("D2Qh16", "D2Q16"):
+        rows = sweeps.couette_sweep(kns, lattice=lat, ny=100, refine=True)
+        out["couette"][lat] = [{"kn": r["kn"], "slip": round(r["slip"], 6),
+                                "pxy_over_pfm": round(r["pxy_over_pfm"], 6)} for r in rows]
+    for lat in ("D2Qh16", "D2Q16"):
+        rows = sweeps.cavity_sweep([0.05, 0.1, 0.2, 0.4], lattice=lat, n=64, refine=True)
+        out["cavity"][lat] = [{"kn": r["kn"], "D": round(r["D"], 5), "G": round(r["G"], 5),
+                               "D_64": round(r["D_N"], 5), "G_64": round(r["G_N"], 5)} for r in rows]
+    out["wall_s"] = round(time.perf_counter() - t0, 2)
+    for lat in ("D2Qh16", "D2Q16"):
+        c = {r["kn"]: r for r in out["couette"][lat]}
+        log(f"  {lat}: Kn 0.1 slip {c[0.1]['slip']:.4f} p/p_fm {c[0.1]['pxy_over_pfm']:.4f}; "
+            f"Kn 1 slip {c[1.0]['slip']:.4f} p/p_fm {c[1.0]['pxy_over_pfm']:.4f}")
+    return out
+
+
 def copy_ceiling(F, torch, nbytes=4 << 30, reps=10):
+    """Achievable streaming bandwidth on this device: the library's probes over 4 GiB, copies with
+    each mix of plain / non-temporal loads and stores (the step kernels load plainly and store
+    non-temporally), a pure read and a pure write.  GB/s counts the bytes moved (2 x nbytes for a
+    copy)."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     s = torch.cuda.current_stream()
-    F.stream_copy(dst, src, nbytes, s)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        F.stream_copy(dst, src, nbytes, s)
-    e1.record(s)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    out = {}
+    for mode in ("nt", "plain", "nt_load", "nt_store", "read", "write"):
+        F.stream_probe(dst, src, nbytes, mode, s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            F.stream_probe(dst, src, nbytes, mode, s)
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        moved = nbytes * (1 if mode in ("read", "write") else 2)
+        out[mode] = round(moved / (ms * 1e-3) / 1e9, 1)
     del src, dst
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return out
 
 
-def cpu_baseline(case, target_s: float = 15.0):
-    """The FP64 oracle on the same workload, a bounded number of steps."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, W, target_s: float = 15.0):
+    """The FP64 oracle as it stands, on the host cores: a bounded number of steps of the same
+    workload on every core and on one core, the small cases solved to their tolerance, and the
+    64-cavity sweep as the sum of its single-instance solves, extrapolated from a few timed
+    steps per instance and the step counts of the library's plain FP64 solves."""
     from oracle import scheme
     P = scheme.Problem.from_case(case)
     f = P.equilibrium()
@@ -185,9 +258,44 @@ def cpu_baseline(case, target_s: float = 15.0):
     f = P.step(f, n)
     dt = time.perf_counter() - t0
     ups = case.nx * case.ny * P.q * n / dt
-    return {"value": ups, "unit": "cell-velocity updates/s", "cores": scheme.threads(), "kind": "oracle",
-            "sample": f"{n} FP64 steps of the {case.nx}x{case.ny} cavity with {P.q} velocities "
-                      f"(after 1 untimed step), {dt:.1f} s"}
+    cores = scheme.threads()
+    out = {"value": ups, "unit": "cell-velocity updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} FP64 steps of the {case.nx}x{case.ny} cavity with {P.q} velocities "
+                     f"(after 1 untimed step), {dt:.1f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    try:
+        scheme.set_threads(1)
+        t0 = time.perf_counter()
+        f = P.step(f, 1)
+        dt1 = time.perf_counter() - t0
+        out["value_1core"] = case.nx * case.ny * P.q / dt1
+        out["ns_per_update_1core"] = round(dt1 / (case.nx * case.ny * P.q) * 1e9, 3)
+    finally:
+        scheme.set_threads(cores)
+    del f
+    ttr = {}
+    for c, tol in ((W.C1, 1e-10), (W.C2, 1e-8)):
+        Pc = scheme.Problem.from_case(c)
+        t0 = time.perf_counter()
+        _, steps, hist = Pc.solve(Pc.equilibrium(), tol, 400000)
+        ttr[c.name] = {"tol": tol, "wall_s": round(time.perf_counter() - t0, 3), "steps": steps}
+    out["time_to_residual"] = ttr
+    solo = SOLO_STEPS.get("c3")
+    if solo:
+        total, sampled = 0.0, 0.0
+        for c, steps in zip(W.c3_instances(), solo):
+            Pc = scheme.Problem.from_case(c)
+            f0 = Pc.equilibrium()
+            k = max(2, int(2e8 // (c.nx * c.ny * Pc.q)))  # ~0.2 s of work per instance
+            t0 = time.perf_counter()
+            Pc.step(f0, k)
+            d = time.perf_counter() - t0
+            sampled += d
+            total += d / k * steps
+        out["sweep64_solo_extrapolated"] = {"wall_s": round(total, 1), "extrapolated": True,
+                                            "timed_s": round(sampled, 2),
+                                            "how": "oracle s/step of each instance x its plain FP64 step count"}
+    return out
 
 
 def main():
@@ -203,6 +311,7 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip training the warm-start network on 2000 solver-generated 64^2 cavities, the warm "
                          "versus uniform starts on held-out Kn at 128^2 and 256^2, and the warm-started sweep")
+    ap.add_argument("--no-kn-sweeps", action="store_true", help="skip the Couette and cavity Kn sweeps")
     ap.add_argument("--heldout", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=20)
     args = ap.parse_args()
@@ -250,15 +359,23 @@ def main():
     updates_per_step = cells * q
     ms_per_step = ms_total / args.steps
     value = updates_per_step * args.steps / (ms_total * 1e-3)
-    # algorithmic bytes of one step-kernel launch: populations read + written (4 B each),
-    # per-cell moments read + written (3 + 3 doubles), wall fluxes (4 walls x N doubles, in + out)
-    alg_bytes = updates_per_step * 8 + cells * 6 * 8 + 2 * 4 * max(case.nx, case.ny) * 8
+    # Algorithmic bytes of one step-kernel launch, in the measurement plan's convention: every
+    # population read once and written once (4 B each) and the three moments of every cell read
+    # and written once at 4 B; wall fluxes and partial sums (O(perimeter)) are left out.  The
+    # kernel carries its moments in double (24 B more per cell, 0.1 B per update here): that
+    # figure is reported beside it.
+    alg_bytes = updates_per_step * 8 + cells * 6 * 4
+    alg_bytes_fp64m = updates_per_step * 8 + cells * 6 * 8 + 2 * 4 * max(case.nx, case.ny) * 8
     avg_kernel_s = ms_step_k * 1e-3 / args.steps
     achieved = alg_bytes / avg_kernel_s / 1e9
     traffic = measured_traffic(alg_bytes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "step_kernel", "alg_bytes_per_launch": alg_bytes,
+                "bytes_convention": "8 B per update (FP32 population read + write) + 24 B per cell "
+                                    "(three moments read + written at 4 B)",
+                "alg_bytes_fp64_moments": alg_bytes_fp64m,
+                "frac_fp64_moments": round(alg_bytes_fp64m / avg_kernel_s / 1e9 / HBM_PEAK_GBPS, 4),
                 "avg_kernel_ms": round(avg_kernel_s * 1e3, 5)}
     log(f"[bench] {value:.4e} updates/s; step kernel {achieved:.0f} GB/s = {achieved/HBM_PEAK_GBPS:.3f} of peak")
 
@@ -292,8 +409,12 @@ def main():
     part("large_cavity_fp64", large_cavity_fp64)
     if not args.no_copy:
         def copy():
-            extra["copy_GBps"] = round(copy_ceiling(F, torch), 1)
-            log(f"[bench] streaming copy: {extra['copy_GBps']} GB/s")
+            probes = copy_ceiling(F, torch)
+            extra["copy_GBps"] = probes["nt"]
+            extra["stream_probes_GBps"] = probes
+            roofline["ceiling_streaming_GBps"] = max(probes.values())
+            roofline["frac_of_ceiling"] = round(achieved / max(probes.values()), 4)
+            log(f"[bench] streaming probes (GB/s): {probes}")
         part("copy_GBps", copy)
     if not args.no_ttr:
         log("[bench] time to residual:")
@@ -318,11 +439,16 @@ def main():
         r = part("sweep64", lambda: sweep_c3(F, W, torch, net))
         if r is not None:
             extra["sweep64"] = r
+    if not args.no_kn_sweeps:
+        log("[bench] Kn sweeps (Couette slip and stress, cavity D and G):")
+        r = part("kn_sweeps", kn_sweeps)
+        if r is not None:
+            extra["kn_sweeps"] = r
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
-        cpu = part("cpu_baseline", lambda: cpu_baseline(case))
+        cpu = part("cpu_baseline", lambda: cpu_baseline(case, W))
         failed = extra.pop("cpu_baseline", None)
         if cpu is None:
             cpu = failed

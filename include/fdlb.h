@@ -537,6 +537,26 @@ int fdlb_batch_field_samples(fdlb_batch *b, int i, float *d_in, float *d_target)
  * (for the achievable-bandwidth ceiling); asynchronous on the stream. */
 int fdlb_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *stream);
 
+/*
+ * Streaming probes of the achievable HBM bandwidth, one kernel per mode, each
+ * thread keeping four 16-byte accesses in flight:
+ *   FDLB_COPY_PLAIN     copy, plain loads and stores
+ *   FDLB_COPY_NT_LOAD   copy, non-temporal loads, plain stores
+ *   FDLB_COPY_NT_STORE  copy, plain loads, non-temporal stores (the step kernels' mix)
+ *   FDLB_COPY_NT        copy, non-temporal loads and stores (fdlb_stream_copy)
+ *   FDLB_COPY_READ      read d_src only; d_dst receives one 16-byte sum per block
+ *                       (it must hold 512 KiB)
+ *   FDLB_COPY_WRITE     write d_dst only (d_src unused)
+ * FDLB_EINVAL for another mode.  Asynchronous on the stream.
+ */
+#define FDLB_COPY_PLAIN 0
+#define FDLB_COPY_NT_LOAD 1
+#define FDLB_COPY_NT_STORE 2
+#define FDLB_COPY_NT 3
+#define FDLB_COPY_READ 4
+#define FDLB_COPY_WRITE 5
+int fdlb_stream_probe(void *d_dst, const void *d_src, size_t bytes, int mode, void *stream);
+
 /* Message for the last error on the calling thread ("" if none). */
 const char *fdlb_last_error(void);
 

@@ -387,3 +387,15 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the parallel loops from now on (at least 1); returns the number in effect. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

@@ -60,6 +60,8 @@ def lib():
         L.oracle_wall_profile.restype = C.c_int
         L.oracle_equilibrium.argtypes = [pp, dp, dp, dp, dp]
         L.oracle_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -193,3 +195,8 @@ class Problem:
 
 def threads() -> int:
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the number in effect."""
+    return int(lib().oracle_set_threads(int(n)))

@@ -18,7 +18,7 @@ from ._lib import (BOTTOM, LEFT, RIGHT, TOP, FdlbError, check, desc_from_case, m
                    quad_full_range, quad_half_range, tile_count, tile_describe)
 
 __all__ = ["Problem", "Batch", "Mlp", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
-           "RIGHT", "tile_count", "tile_describe", "stream_copy"]
+           "RIGHT", "tile_count", "tile_describe", "stream_copy", "stream_probe"]
 
 
 def _torch():
@@ -222,6 +222,17 @@ def stream_copy(dst, src, nbytes: int, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     check(_lib.lib.fdlb_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
                                     int(nbytes), C.c_void_p(s.cuda_stream)))
+
+
+PROBE_MODES = {"plain": 0, "nt_load": 1, "nt_store": 2, "nt": 3, "read": 4, "write": 5}
+
+
+def stream_probe(dst, src, nbytes: int, mode: str, stream=None):
+    """One streaming probe kernel (fdlb_stream_probe) over nbytes; mode is a key of PROBE_MODES."""
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    check(_lib.lib.fdlb_stream_probe(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr() if src is not None else 0),
+                                     int(nbytes), int(PROBE_MODES[mode]), C.c_void_p(s.cuda_stream)))
 
 
 class Batch:

@@ -284,6 +284,15 @@ int fdlb_stream_copy(void* d_dst, const void* d_src, size_t bytes, void* stream)
     });
 }
 
+int fdlb_stream_probe(void* d_dst, const void* d_src, size_t bytes, int mode, void* stream) {
+    return guard([&] {
+        if (mode < FDLB_COPY_PLAIN || mode > FDLB_COPY_WRITE) throw Error(FDLB_EINVAL, "unknown probe mode");
+        if (!d_dst || (mode != FDLB_COPY_WRITE && !d_src)) throw Error(FDLB_EINVAL, "NULL device buffer");
+        launch_copy(d_dst, d_src, bytes, (hipStream_t)stream, mode);
+        return FDLB_OK;
+    });
+}
+
 const char* fdlb_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

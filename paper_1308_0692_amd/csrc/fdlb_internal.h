@@ -162,7 +162,7 @@ template <class T>
 void launch_from_raw(const double* f, const double* w_nat, int a0, int a1, int64_t plane, T* h,
                      hipStream_t stream);
 void launch_mass_scale(const float* frho, int64_t cells, double* scale_out, hipStream_t stream);
-void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream, int mode = FDLB_COPY_NT);
 void launch_widen(const float* src, double* dst, int64_t n, hipStream_t stream);
 // out[8 i + j] = ptrs[i][j], j < 8: the first control doubles of n problems in one array.
 void launch_gather_ctrl(const double* const* ptrs, int n, double* out, hipStream_t stream);

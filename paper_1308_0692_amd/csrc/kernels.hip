@@ -993,9 +993,11 @@ __global__ void __launch_bounds__(256) gather_ctrl_kernel(const double* const* _
     if (k < 8 * n) out[k] = ptrs[k / 8][k % 8];
 }
 
-// Streaming copy for the bandwidth ceiling: each thread keeps 4 x 16-byte loads in flight.
+// Streaming copy for the bandwidth ceiling: each thread keeps 4 x 16-byte loads in flight.  NTL /
+// NTS: non-temporal loads / stores (the step kernels load plainly and store non-temporally).
 constexpr int COPY_UNROLL = 4;
 typedef float copy_vec_t __attribute__((ext_vector_type(4)));
+template <bool NTL, bool NTS>
 __global__ void __launch_bounds__(256) copy_kernel(copy_vec_t* __restrict__ dst, const copy_vec_t* __restrict__ src,
                                                    int64_t n16) {
     const int64_t chunk = (int64_t)blockDim.x * COPY_UNROLL;
@@ -1004,12 +1006,54 @@ __global__ void __launch_bounds__(256) copy_kernel(copy_vec_t* __restrict__ dst,
 #pragma unroll
         for (int u = 0; u < COPY_UNROLL; ++u) {
             const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
-            if (i < n16) v[u] = __builtin_nontemporal_load(src + i);
+            if (i < n16) {
+                if constexpr (NTL) v[u] = __builtin_nontemporal_load(src + i);
+                else v[u] = src[i];
+            }
         }
 #pragma unroll
         for (int u = 0; u < COPY_UNROLL; ++u) {
             const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
-            if (i < n16) __builtin_nontemporal_store(v[u], dst + i);
+            if (i < n16) {
+                if constexpr (NTS) __builtin_nontemporal_store(v[u], dst + i);
+                else dst[i] = v[u];
+            }
+        }
+    }
+}
+
+// Read-only stream (plain loads): every thread sums its 16-byte vectors; one vector per block
+// is written (dst must hold gridDim.x vectors), so the loads cannot be dropped.
+__global__ void __launch_bounds__(256) read_stream_kernel(copy_vec_t* __restrict__ dst,
+                                                          const copy_vec_t* __restrict__ src, int64_t n16) {
+    const int64_t chunk = (int64_t)blockDim.x * COPY_UNROLL;
+    copy_vec_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t base = (int64_t)blockIdx.x * chunk; base < n16; base += (int64_t)gridDim.x * chunk) {
+#pragma unroll
+        for (int u = 0; u < COPY_UNROLL; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i < n16) acc += src[i];
+        }
+    }
+    __shared__ copy_vec_t s[256];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        copy_vec_t t = s[0];
+        for (int k = 1; k < 256; ++k) t += s[k];
+        dst[blockIdx.x] = t;
+    }
+}
+
+// Write-only stream (non-temporal stores of a constant).
+__global__ void __launch_bounds__(256) write_stream_kernel(copy_vec_t* __restrict__ dst, int64_t n16) {
+    const int64_t chunk = (int64_t)blockDim.x * COPY_UNROLL;
+    const copy_vec_t v = {1.f, 2.f, 3.f, 4.f};
+    for (int64_t base = (int64_t)blockIdx.x * chunk; base < n16; base += (int64_t)gridDim.x * chunk) {
+#pragma unroll
+        for (int u = 0; u < COPY_UNROLL; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x + threadIdx.x;
+            if (i < n16) __builtin_nontemporal_store(v, dst + i);
         }
     }
 }
@@ -1236,18 +1280,27 @@ void launch_gather_ctrl(const double* const* ptrs, int n, double* out, hipStream
     FDLB_HIP(hipGetLastError());
 }
 
-void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream, int mode) {
     const int64_t n16 = (int64_t)(bytes / 16);
     if (n16 > 0) {
         // 4 loads in flight per thread over 32768 blocks measured fastest on MI355X for multi-GiB
         // copies (5.7 TB/s; 8 per thread or fewer blocks: 5.0-5.5 TB/s).
         const int64_t blocks = std::min<int64_t>(32768, (n16 + 256 * COPY_UNROLL - 1) / (256 * COPY_UNROLL));
-        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, (copy_vec_t*)dst,
-                           (const copy_vec_t*)src, n16);
+        copy_vec_t* d = (copy_vec_t*)dst;
+        const copy_vec_t* sv = (const copy_vec_t*)src;
+        switch (mode) {
+            case FDLB_COPY_PLAIN: hipLaunchKernelGGL((copy_kernel<false, false>), dim3((unsigned)blocks), dim3(256), 0, stream, d, sv, n16); break;
+            case FDLB_COPY_NT_LOAD: hipLaunchKernelGGL((copy_kernel<true, false>), dim3((unsigned)blocks), dim3(256), 0, stream, d, sv, n16); break;
+            case FDLB_COPY_NT_STORE: hipLaunchKernelGGL((copy_kernel<false, true>), dim3((unsigned)blocks), dim3(256), 0, stream, d, sv, n16); break;
+            case FDLB_COPY_NT: hipLaunchKernelGGL((copy_kernel<true, true>), dim3((unsigned)blocks), dim3(256), 0, stream, d, sv, n16); break;
+            case FDLB_COPY_READ: hipLaunchKernelGGL(read_stream_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, d, sv, n16); break;
+            case FDLB_COPY_WRITE: hipLaunchKernelGGL(write_stream_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, d, n16); break;
+            default: throw Error(FDLB_EINVAL, "unknown copy mode");
+        }
         FDLB_HIP(hipGetLastError());
     }
     const int64_t tail = (int64_t)bytes - n16 * 16;
-    if (tail > 0) {
+    if (tail > 0 && mode <= FDLB_COPY_NT) {
         hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(16), 0, stream, (char*)dst + n16 * 16,
                            (const char*)src + n16 * 16, tail);
         FDLB_HIP(hipGetLastError());
