@@ -10,12 +10,13 @@
 //     procedure on a composite Gauss-Legendre discretisation of the weight
 //     over [0, 24] (the tail beyond is below 1e-120 of the mass);
 //     full-range: the known recurrence a_k = 0, b_k = k;
-//   * nodes as eigenvalues of the Jacobi matrix (Golub-Welsch) by an
-//     implicit symmetric QL iteration;
+//   * nodes as the zeros of the n-th orthogonal polynomial (the eigenvalues of
+//     the Jacobi matrix) by bisection on Sturm counts;
 //   * one Newton polish of each node on the recurrence, and weights from the
 //     Christoffel numbers 1 / sum_k p_k(x)^2 / ||p_k||^2.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <stdexcept>
 #include <vector>
 
@@ -92,64 +93,59 @@ void half_range_recurrence(int n, std::vector<ld>& a, std::vector<ld>& b) {
     b[0] = 0.5L;  // exact mass of the half-line
 }
 
-// Eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e[i]
-// between i and i+1) by implicit QL with Wilkinson shifts, in place in d.
-void tridiag_ql(std::vector<ld>& d, std::vector<ld> e) {
-    const int n = (int)d.size();
-    e.push_back(0);
-    for (int l = 0; l < n; ++l) {
-        for (int iter = 0; iter < 200; ++iter) {
-            int m = l;
-            for (; m < n - 1; ++m) {
-                ld dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= 1e-22L * dd) break;
-            }
-            if (m == l) break;
-            ld g = (d[l + 1] - d[l]) / (2 * e[l]);
-            ld r = std::hypot(g, (ld)1);
-            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-            ld s = 1, c = 1, p = 0;
-            int i = m - 1;
-            for (; i >= l; --i) {
-                ld f = s * e[i], bb = c * e[i];
-                r = std::hypot(f, g);
-                e[i + 1] = r;
-                if (r == 0) {
-                    d[i + 1] -= p;
-                    e[m] = 0;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2 * c * bb;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - bb;
-            }
-            if (r == 0 && i >= l) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0;
-        }
+// Zeros of p_n, the n-th monic orthogonal polynomial of the recurrence
+//   p_{k+1}(t) = (t - a_k) p_k(t) - b_k p_{k-1}(t),
+// which are the eigenvalues of the Jacobi matrix, by bisection on Sturm counts (the
+// eigenvalue-counting method of Givens; see Wilkinson, The Algebraic Eigenvalue Problem,
+// 1965, ch. 5): the ratios q_k = p_{k+1}(t) / p_k(t) = (t - a_k) - b_k / q_{k-1} change sign
+// once for every zero below t, so the number of negative ratios counts the zeros of p_n below
+// t.  Each zero is isolated in its own interval of the Gershgorin bound and halved to the
+// resolution of long double.  Ascending.
+int zeros_below(const std::vector<ld>& a, const std::vector<ld>& b, ld t) {
+    int count = 0;
+    ld q = 1;
+    for (size_t k = 0; k < a.size(); ++k) {
+        q = (a[k] - t) - (k ? b[k] / q : 0);
+        // (a ratio that vanishes is nudged by one rounding unit: a zero exactly at t counts
+        // on one side consistently)
+        if (q == 0) q = -std::numeric_limits<ld>::epsilon() * (std::fabs(a[k]) + std::fabs(t) + 1);
+        if (q < 0) ++count;
     }
+    return count;
+}
+
+std::vector<ld> recurrence_zeros(const std::vector<ld>& a, const std::vector<ld>& b) {
+    const int n = (int)a.size();
+    ld lo = 0, hi = 0;  // Gershgorin interval of the Jacobi matrix
+    for (int k = 0; k < n; ++k) {
+        const ld r = (k ? std::sqrt(b[k]) : 0) + (k + 1 < n ? std::sqrt(b[k + 1]) : 0);
+        lo = (k == 0) ? a[k] - r : std::min(lo, a[k] - r);
+        hi = (k == 0) ? a[k] + r : std::max(hi, a[k] + r);
+    }
+    std::vector<ld> z(n);
+    for (int j = 0; j < n; ++j) {  // zero j: the smallest t with at least j + 1 zeros below it
+        ld l = lo, h = hi;
+        for (int it = 0; it < 200 && l < h; ++it) {
+            const ld m = l + (h - l) / 2;
+            if (m <= l || m >= h) break;
+            if (zeros_below(a, b, m) > j) h = m;
+            else l = m;
+        }
+        z[j] = l + (h - l) / 2;
+    }
+    return z;
 }
 
 // Gauss rule from a recurrence: nodes ascending and weights (total mass b[0]).
-void golub_welsch(const std::vector<ld>& a, const std::vector<ld>& b, std::vector<ld>& x,
+void gauss_from_recurrence(const std::vector<ld>& a, const std::vector<ld>& b, std::vector<ld>& x,
                   std::vector<ld>& w) {
     const int n = (int)a.size();
-    std::vector<ld> d(a.begin(), a.end()), e(n > 1 ? n - 1 : 0);
-    for (int i = 0; i + 1 < n; ++i) e[i] = std::sqrt(b[i + 1]);
-    tridiag_ql(d, e);
-    std::vector<int> idx(n);
-    for (int i = 0; i < n; ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](int i, int j) { return d[i] < d[j]; });
+    const std::vector<ld> d = recurrence_zeros(a, b);
     x.resize(n);
     w.resize(n);
     for (int k = 0; k < n; ++k) {
         // Newton polish on p_n, then Christoffel weight.
-        ld t = d[idx[k]];
+        ld t = d[k];
         for (int it = 0; it < 3; ++it) {
             ld pm = 0, pc = 1, dm = 0, dc = 0;
             for (int j = 0; j < n; ++j) {
@@ -182,7 +178,7 @@ void quad_half_range(int n, double* nodes, double* weights) {
     if (n < 1 || n > 16) throw Error(FDLB_EINVAL, "half-range order must be 1..16 nodes per half");
     std::vector<ld> a, b, x, w;
     half_range_recurrence(n, a, b);
-    golub_welsch(a, b, x, w);
+    gauss_from_recurrence(a, b, x, w);
     for (int i = 0; i < n; ++i) {
         nodes[n - 1 - i] = -(double)x[i];
         nodes[n + i] = (double)x[i];
@@ -195,7 +191,7 @@ void quad_full_range(int n, double* nodes, double* weights) {
     std::vector<ld> a(n, 0), b(n), x, w;
     b[0] = 1;
     for (int k = 1; k < n; ++k) b[k] = k;
-    golub_welsch(a, b, x, w);
+    gauss_from_recurrence(a, b, x, w);
     // The rule is symmetric: impose it exactly (an odd n has the node 0).
     for (int i = 0; i < n; ++i) {
         ld xs = (x[i] - x[n - 1 - i]) / 2, ws = (w[i] + w[n - 1 - i]) / 2;
