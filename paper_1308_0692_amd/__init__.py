@@ -189,6 +189,16 @@ class Problem:
         """Mixed precision: widen the float state to double now (fdlb_promote)."""
         check(_lib.lib.fdlb_promote(self._h))
 
+    # -- steady iteration ------------------------------------------------------------------
+    def set_pseudo_time(self, on: bool = True):
+        """Velocity-local pseudo-time steps for later steps and solves (fdlb_set_pseudo_time)."""
+        check(_lib.lib.fdlb_set_pseudo_time(self._h, int(bool(on))))
+
+    def pseudo_weights(self) -> np.ndarray:
+        out = np.empty(self.q)
+        check(_lib.lib.fdlb_problem_pseudo_weights(self._h, _lib._dp(out)))
+        return out
+
     # -- tiles ------------------------------------------------------------------------
     @property
     def tile(self) -> int:
@@ -337,6 +347,10 @@ class Batch:
 
     def active_precision(self, i: int) -> str:
         return _lib.PRECISION_NAMES[check(_lib.lib.fdlb_batch_active_precision(self._h, int(i)), allow=(0, 1))]
+
+    def set_pseudo_time(self, on: bool = True):
+        """Velocity-local pseudo-time steps for every instance (fdlb_batch_set_pseudo_time)."""
+        check(_lib.lib.fdlb_batch_set_pseudo_time(self._h, int(bool(on))))
 
     def set_retile(self, max_members: int):
         """Tail re-tiling threshold of the solves (fdlb_batch_set_retile); 0 disables."""

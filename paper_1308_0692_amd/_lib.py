@@ -82,6 +82,9 @@ def _load():
         "fdlb_checkpoint_load": (C.c_int, [vp, vp]),
         "fdlb_step": (C.c_int, [vp, i64]),
         "fdlb_step_static": (C.c_int, [vp, vp, i64, vp]),
+        "fdlb_set_pseudo_time": (C.c_int, [vp, C.c_int]),
+        "fdlb_problem_pseudo_weights": (C.c_int, [vp, dp]),
+        "fdlb_batch_set_pseudo_time": (C.c_int, [vp, C.c_int]),
         "fdlb_step_timed": (C.c_int, [vp, i64, dp, dp]),
         "fdlb_last_residual": (C.c_int, [vp, dp, C.POINTER(i64)]),
         "fdlb_solve_steady": (C.c_int, [vp, C.c_double, i64, i32, i32, C.POINTER(Report)]),

@@ -258,6 +258,7 @@ static StepArgs<T> batch_step_args(fdlb_problem& p, int parity, int tile, bool p
     a.partials = partials_of(p, parity);
     a.prev_partials = partials_of(p, parity ^ 1);
     a.prev_nb = prev && nb <= INLINE_REDUCE_MAX_BLOCKS ? nb : 0;
+    a.pseudo = p.pseudo ? 1 : 0;
     a.ctrl = ctrl_of(p);
     a.vel = (const VelEntry<T>*)(p.d_work + (f32 ? p.off_vel : p.off_vel64));
     for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
@@ -751,6 +752,13 @@ int fdlb_batch_set_retile(fdlb_batch* b, int max_members) {
     return guard_call([&] {
         if (max_members < 0) throw Error(FDLB_EINVAL, "max_members must be >= 0");
         bh(b).retile_members = max_members;
+        return FDLB_OK;
+    });
+}
+
+int fdlb_batch_set_pseudo_time(fdlb_batch* b, int on) {
+    return guard_call([&] {
+        for (auto& p : bh(b).probs) p->pseudo = on != 0;  // the next solve uploads the step arguments
         return FDLB_OK;
     });
 }

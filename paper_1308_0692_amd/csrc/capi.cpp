@@ -27,6 +27,7 @@ int solve_steady(fdlb_problem& p, double tol, int64_t max_steps, int32_t check_e
 void moments(fdlb_problem& p, double* rho, double* ux, double* uy, double* pxy);
 void wall_profile(fdlb_problem& p, int wall, double* rho, double* ut, double* pxy);
 void set_tile(fdlb_problem& p, int tile);
+void set_pseudo_time(fdlb_problem& p, int on);
 double autotune(fdlb_problem& p, int steps);
 void promote(fdlb_problem& p);
 void field_samples(fdlb_problem& p, float* in, float* target);
@@ -251,6 +252,22 @@ int fdlb_problem_set_tile(fdlb_problem* p, int tile) {
 }
 
 int fdlb_problem_get_tile(const fdlb_problem* p) { return p ? p->tile : FDLB_EINVAL; }
+
+int fdlb_set_pseudo_time(fdlb_problem* p, int on) {
+    return guard([&] {
+        set_pseudo_time(handle(p), on);
+        return FDLB_OK;
+    });
+}
+
+int fdlb_problem_pseudo_weights(const fdlb_problem* p, double* stretch) {
+    return guard([&] {
+        if (!p) throw Error(FDLB_EINVAL, "NULL problem handle");
+        if (!stretch) throw Error(FDLB_EINVAL, "NULL output array");
+        for (int a = 0; a < p->q; ++a) stretch[a] = p->pt[a];
+        return FDLB_OK;
+    });
+}
 
 int fdlb_problem_active_precision(const fdlb_problem* p) { return p ? p->prec : FDLB_EINVAL; }
 

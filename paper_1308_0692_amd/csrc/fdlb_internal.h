@@ -38,7 +38,7 @@ struct VelEntry {
     T xx, xy;         // xi_x, xi_y
     T nux, nuy;       // dt |xi_x| N_x, dt |xi_y| N_y (0 along a periodic single-cell axis)
     int32_t alpha;    // plane index of this velocity in the state
-    int32_t pad;
+    float pt;         // pseudo-time stretch of this velocity (steady iterations with local steps)
     // byte offset of that plane in a population buffer of type T (alpha * plane * sizeof(T)); held
     // at 4-byte alignment so that the float table keeps the alignment, and the compiler the load
     // grouping, that the bandwidth-bound tiles were tuned with
@@ -74,6 +74,7 @@ struct StepArgs {
     int32_t nx, ny, L;
     int32_t tiles_x, tiles_y;
     int32_t prev_nb;      // blocks of the previous step whose partials are still unreduced, or 0
+    int32_t pseudo;       // 1: store h + pt (S h - h) instead of S h (velocity-local pseudo-time steps)
     int64_t plane;        // nx * ny
     T omega;              // dt / Kn in the storage type
     T pad1;
@@ -110,6 +111,13 @@ struct ReduceArgs {
     int32_t nb;          // <= 0: skip
     int32_t wave_order;  // 1: sum in the single-wave order of the inline reduction
 };
+
+// Velocity-local pseudo-time steps: the largest stretch of a velocity's step, and the largest
+// stretched relaxation rate omega * stretch (the iteration h + stretch (S h - h) was stable in
+// every case tried with this margin; at 0.5 and 1 it diverged on 12 x 12 and 8 x 8 velocity sets
+// at Kn = 0.1).
+constexpr double FDLB_PSEUDO_MAX = 64.0;
+constexpr double FDLB_PSEUDO_OMEGA_MAX = 0.25;
 
 // Residual partials of a launch with at most this many blocks are reduced inside the next step
 // kernel (every wave of it sums them in the same order) instead of by a kernel of their own;
@@ -234,6 +242,8 @@ struct fdlb_problem {
     int q = 0;
     std::vector<double> xi_x, xi_y, w;     // velocity order of the ABI
     double dt = 0, omega = 0;
+    std::vector<double> pt;                // pseudo-time stretch per velocity (ABI order)
+    bool pseudo = false;                   // steps use velocity-local pseudo-time steps
     double nux_scale = 0, nuy_scale = 0;   // N along a bounded axis, 0 along a periodic single-cell one
     fdlb::WallConst wall[4]{};
     int32_t quad_begin[5]{};

@@ -120,6 +120,7 @@ __device__ __forceinline__ VelEntry<T> load_vel(const VelEntry<T>* p, const int 
     v.nux = q->nux;
     v.nuy = q->nuy;
     v.alpha = q->alpha;
+    v.pt = q->pt;
     return v;
 }
 template <class T>
@@ -507,6 +508,32 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
                         if (r == r_top_in) gy = c.w * Py[v] + c.wx * Qy[v];
                     }
                     fn[r][v] = gc - c.nux * (gc - gx) - c.nuy * (gc - gy);
+                }
+            }
+            if (A.pseudo) {
+                // Velocity-local pseudo-time steps (steady iterations only): the state moves by
+                // pt times the step's change, h + pt (S h - h), which keeps the fixed point of S.
+                // The change (relaxation increment minus the transport differences) is formed
+                // again from its parts, not as S h - h, so that pt does not magnify the rounding
+                // of S h.
+                const T pt = (T)c.pt;
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        const T gc = gr[r][v];
+                        T gx, gy;
+                        if constexpr (SX > 0) gx = (v > 0) ? gr[r][v - 1] : xb[r];
+                        else gx = (v < VX - 1) ? gr[r][v + 1] : xb[r];
+                        if constexpr (SY > 0) {
+                            gy = (r > 0) ? gr[r - 1][v] : yb[v];
+                        } else {
+                            gy = (r < K - 1) ? gr[r + 1][v] : yb[v];
+                            if (r == r_top_in) gy = c.w * Py[v] + c.wx * Qy[v];
+                        }
+                        const T inc = (c.ow * mr[r][v] + c.owx * mx[r][v] + c.owy * my[r][v]) - om * g[r][v];
+                        fn[r][v] = g[r][v] + pt * ((inc - c.nux * (gc - gx)) - c.nuy * (gc - gy));
+                    }
                 }
             }
 #pragma unroll

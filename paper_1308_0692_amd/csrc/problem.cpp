@@ -172,6 +172,18 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     if (!d.allow_unstable && (d.cfl > 1.0 || p.omega > 1.0))
         throw Error(FDLB_EUNSTABLE, "explicit scheme unstable: need cfl <= 1 and dt/Kn <= 1 (dt/Kn = " +
                                         std::to_string(p.omega) + ")");
+    // Pseudo-time stretch of each velocity for steady iterations with local steps: the factor
+    // that brings its own Courant number up to the problem's, limited so that the stretched
+    // relaxation rate stays at FDLB_PSEUDO_OMEGA_MAX and the factor at FDLB_PSEUDO_MAX.
+    p.pt.assign(p.q, 1.0);
+    for (int a = 0; a < p.q; ++a) {
+        const double nu = p.dt * (std::fabs(p.xi_x[a]) * p.nux_scale + std::fabs(p.xi_y[a]) * p.nuy_scale);
+        double f = FDLB_PSEUDO_MAX;
+        if (nu > 0) f = std::min(f, d.cfl / nu);
+        if (p.omega > 0) f = std::min(f, FDLB_PSEUDO_OMEGA_MAX / p.omega);
+        if (nu == 0 && p.omega == 0) f = 1.0;  // a population that never changes
+        p.pt[a] = (double)(float)std::max(1.0, f);  // the kernels' table holds it as a float
+    }
     // Wall constants of Eq. (9) in deviation form.  The wall density is the arriving flux over
     // the flux its emission (Eq. 8) carries per unit density, E = sum over leaving xi of
     // xi_n w: the wall is then impermeable for any rule.  A half-range rule integrates xi over
@@ -289,6 +301,7 @@ std::vector<VelEntry<T>> vel_table(const fdlb_problem& p) {
         c.nux = (T)(p.dt * std::fabs(x) * p.nux_scale);
         c.nuy = (T)(p.dt * std::fabs(y) * p.nuy_scale);
         c.alpha = a;
+        c.pt = (float)p.pt[a];
         c.off = (int64_t)a * p.plane * (int64_t)sizeof(T);
     }
     return v;
@@ -562,6 +575,7 @@ static StepArgs<T> step_args(fdlb_problem& p, int parity, int tile, bool prev) {
     a.partials = part_buf(p, parity);
     a.prev_partials = part_buf(p, parity ^ 1);
     a.prev_nb = prev ? nblocks_of(p, tile) : 0;
+    a.pseudo = p.pseudo ? 1 : 0;
     a.ctrl = ctrl(p);
     a.vel = (const VelEntry<T>*)(p.d_work + (f32 ? p.off_vel : p.off_vel64));
     for (int i = 0; i < 5; ++i) a.quad_begin[i] = p.quad_begin[i];
@@ -899,6 +913,13 @@ void field_samples(fdlb_problem& p, float* in, float* target) {
 // ---------------------------------------------------------------------------
 // Tiles.
 // ---------------------------------------------------------------------------
+void set_pseudo_time(fdlb_problem& p, int on) {
+    if (p.pseudo == (on != 0)) return;
+    p.pseudo = on != 0;
+    for (auto& kv : p.graphs) (void)hipGraphExecDestroy(kv.second);  // their launches carry the flag
+    p.graphs.clear();
+}
+
 void set_tile(fdlb_problem& p, int tile) {
     if (tile < 0) {
         p.tile = heuristic_tile(p);

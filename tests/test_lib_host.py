@@ -376,3 +376,23 @@ def test_one_node_rules_are_rejected(F):
     x, w = _lib.quad_half_range(1)
     assert np.allclose(x, [-np.sqrt(2 / np.pi), np.sqrt(2 / np.pi)]) and np.allclose(w, [0.5, 0.5])
     assert abs(float(np.sum(w * x * x)) - 2 / np.pi) < 1e-15
+
+
+def test_pseudo_time_stretches_follow_their_definition(F):
+    """s_alpha = max(1, min(cfl / nu_alpha, 0.25 / omega, 64)) with nu_alpha the velocity's own
+    Courant number over the bounded axes; the fastest velocity keeps s = 1."""
+    for case in (W.cavity(48, kn=0.05, order=4), W.cavity(20, ny=12, kn=3.0, order=6),
+                 W.couette(40, kn=float("inf"), qy=("half", 8)),
+                 W.with_(W.cavity(16, kn=0.2), qx=("full", 5), qy=("full", 5))):
+        p = F.Problem(case, precision="fp64", bind=False)
+        x, y, w = p.velocities()
+        nu = p.dt * (np.abs(x) * (0 if case.periodic_x else case.nx) + np.abs(y) * (0 if case.periodic_y else case.ny))
+        want = np.full(p.q, 64.0)
+        want = np.where(nu > 0, np.minimum(want, case.cfl / np.where(nu > 0, nu, 1)), want)
+        if p.omega > 0:
+            want = np.minimum(want, 0.25 / p.omega)
+        else:
+            want = np.where(nu == 0, 1.0, want)
+        want = np.maximum(want, 1.0)
+        assert np.array_equal(p.pseudo_weights(), want.astype(np.float32).astype(np.float64)), case.name
+        assert p.pseudo_weights()[np.argmax(nu)] == 1.0
