@@ -71,13 +71,15 @@ def time_to_residual(F, W):
     out = {}
     c2 = W.C2
     ref = None
-    for prec, graph in (("fp64", True), ("fp64", False), ("fp32", True), ("mixed", True)):
+    for prec, graph, pseudo in (("fp64", True, False), ("fp64", False, False), ("fp32", True, False),
+                                ("mixed", True, False), ("mixed", True, True), ("fp64", True, True)):
         p = F.Problem(c2, precision=prec)
+        p.set_pseudo_time(pseudo)
         p.init_equilibrium()
         p.solve(1e-8, 400, check_every=200, use_graph=graph)  # warm-up (graph capture)
         p.init_equilibrium()
         rep = p.solve(1e-8, 200000, check_every=200, use_graph=graph)
-        key = f"cavity128_q64_{prec}{'_graph' if graph else ''}"
+        key = f"cavity128_q64_{prec}{'_pseudo' if pseudo else ''}{'_graph' if graph else ''}"
         rho, ux, uy, _ = p.moments()
         if ref is None:
             ref = (rho, ux, uy)
@@ -111,7 +113,8 @@ def sweep_c3(F, W, torch, net=None):
     step counts): per instance for the batch (and the warm-started batch), and for the plain
     FP64 solves stopped at 1e-8, whose own stopping error is of the same size.  With a trained
     warm-start network the batch is solved a second time from the network's seeds (seeding
-    inside the timing)."""
+    inside the timing).  Each is also solved with velocity-local pseudo-time steps (the same fixed
+    point, reached in fewer iterations)."""
     cases = W.c3_instances()
     solo_wall, solo_steps, ref, solo_eps = 0.0, [], [], []
     for c in cases:
@@ -142,20 +145,23 @@ def sweep_c3(F, W, torch, net=None):
         p.close()
     log(f"  plain FP64 without graph capture: {nograph_wall:.2f} s")
     b = F.Batch(cases, precision="mixed")
+    t0 = time.perf_counter()
     ms = b.autotune(steps=3)
+    tune_s = time.perf_counter() - t0
     out = {"instances": len(cases), "tol": 1e-8, "reference": "each instance in FP64 continued to R < 1e-11",
            "plain_fp64_solo": {"wall_s": round(solo_wall, 3), "steps": sum(solo_steps),
                                "max_eps_u_vs_ref": max(e[0] for e in solo_eps),
                                "max_eps_rho_vs_ref": max(e[1] for e in solo_eps)},
-           "plain_fp64_solo_no_graph": {"wall_s": round(nograph_wall, 3)}}
-    for key in ("mixed_batch", "mixed_batch_warm"):
-        if key == "mixed_batch_warm" and net is None:
-            break
+           "plain_fp64_solo_no_graph": {"wall_s": round(nograph_wall, 3)}, "autotune_s": round(tune_s, 3)}
+    for key in ("mixed_batch", "mixed_batch_pseudo", "mixed_batch_warm", "mixed_batch_warm_pseudo"):
+        if "warm" in key and net is None:
+            continue
         from paper_1308_0692_amd import warmstart
+        b.set_pseudo_time("pseudo" in key)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, c in enumerate(cases):
-            if key == "mixed_batch":
+            if "warm" not in key:
                 b.init_equilibrium(i)
             else:
                 warmstart.seed_batch(b, i, net, c.kn, c.wall_u[1])
@@ -313,6 +319,8 @@ def main():
                          "versus uniform starts on held-out Kn at 128^2 and 256^2, and the warm-started sweep")
     ap.add_argument("--no-kn-sweeps", action="store_true", help="skip the Couette and cavity Kn sweeps")
     ap.add_argument("--heldout", type=int, default=16)
+    ap.add_argument("--tune-cache", default=None,
+                    help="file caching autotuned tiles (default: the library's user cache file; '' disables)")
     ap.add_argument("--epochs", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -324,12 +332,18 @@ def main():
     import paper_1308_0692_amd as F
     import workloads as W
 
+    tune_cache = F.default_tune_cache() if args.tune_cache is None else args.tune_cache
+    F.set_tune_cache(tune_cache)
     case = W.C4
     log(f"[bench] workload {case.name}: {case.nx}x{case.ny} cells, Q={case.q}, Kn={case.kn}")
     p = F.Problem(case, precision="fp32")
+    tune_s = None
     if args.tile == -2:
+        t0 = time.perf_counter()
         ms = p.autotune(steps=5)
-        log(f"[bench] autotuned tile {p.tile} ({F.tile_describe('fp32', p.tile)}): {ms:.3f} ms/step")
+        tune_s = time.perf_counter() - t0
+        log(f"[bench] autotuned tile {p.tile} ({F.tile_describe('fp32', p.tile)}): {ms:.3f} ms/step "
+            f"({tune_s:.2f} s of tuning; cache {tune_cache or 'off'})")
     elif args.tile >= 0:
         p.set_tile(args.tile)
     tile_index = p.tile
@@ -461,7 +475,8 @@ def main():
             "data": "synthetic",
             "config": {"workload": case.name, "nx": case.nx, "ny": case.ny, "q": q, "kn": case.kn,
                        "lid_u": case.wall_u[1], "velocities": "half-range Gauss-Hermite 8 per half, tensor",
-                       "tile": tile_desc, "tile_index": tile_index},
+                       "tile": tile_desc, "tile_index": tile_index,
+                       "autotune_s": None if tune_s is None else round(tune_s, 3), "tune_cache": bool(tune_cache)},
             "roofline": roofline, "cpu_baseline": cpu, **extra}
     print(json.dumps(line), flush=True)
 

@@ -321,13 +321,15 @@ int fdlb_solve_steady(fdlb_problem *p, double tol, int64_t max_steps, int32_t ch
  * S the step of the scheme, instead of h <- S h.  A fixed point of one is a fixed point
  * of the other, so a steady solve reaches the same steady state (to the tolerance of
  * its residual); the iterates are then pseudo-time levels, not the time evolution.
- * The stretch s_alpha >= 1 brings each velocity's Courant number,
+ * The stretch s_alpha >= 1 is as large as a Fourier analysis of one velocity's update
+ * (equilibrium held fixed) allows with the problem's own margin:
+ *   s_alpha = max(1, min(cfl / (nu_alpha (1 - omega) + omega / 2), 1 / omega, 64)),
  *   nu_alpha = dt (|xi_x| N_x / l_x + |xi_y| N_y / l_y)  (bounded axes only),
- * up to the problem's cfl:  s_alpha = max(1, min(cfl / nu_alpha, 0.25 / omega, 64))
- * (the slow velocities no longer wait for the fastest one's step; 0.25 / omega keeps the
- * stretched relaxation rate at 0.25, a margin found stable on every problem tried; no
- * proof of stability is known).  Typical gains: 1.2-5x fewer iterations for Kn >= 0.1,
- * little below 0.03 where the relaxation bound dominates.  fdlb_problem_pseudo_weights
+ * so that s (omega + 2 nu (1 - omega)) <= 2 cfl and the stretched relaxation rate s omega <= 1
+ * (the slow velocities no longer wait for the fastest one's step).  The coupling of the
+ * velocities through the equilibrium is not covered by that analysis; the iteration was
+ * stable on every problem tried.  Typical gains: 2-5x fewer iterations for Kn >= 0.05,
+ * less at smaller Kn where 1 / omega bounds the stretch.  fdlb_problem_pseudo_weights
  * copies s_alpha as the kernels use it (rounded to float; Q doubles, velocity order of the
  * ABI).  Off by default; host only.
  */
@@ -374,6 +376,18 @@ int fdlb_tile_describe(int precision, int tile, char *buf, size_t len);
 int fdlb_problem_set_tile(fdlb_problem *p, int tile);
 int fdlb_problem_get_tile(const fdlb_problem *p);
 int fdlb_autotune(fdlb_problem *p, int steps, double *best_ms_per_step);
+
+/*
+ * On-disk cache of the tile choices of fdlb_autotune and fdlb_batch_autotune: with a
+ * non-empty path (a text file, created if absent), a tuning first looks up its key -- the
+ * device (architecture and name), a hash of the compiled tile shapes, the precision and the
+ * problem's sizes (every member's for a batch) -- and, on a hit whose tile still fits, sets
+ * that tile (and re-seeds as a tuning does) without timing anything, returning the cached
+ * time per step; otherwise it times the shapes and appends the result.  Lines that do not
+ * parse, and files that cannot be read or written, are ignored.  NULL or "" disables the
+ * cache (the default).  Process-wide; safe to call from any thread.
+ */
+int fdlb_set_tune_cache(const char *path);
 
 /* ---- mixed precision (FDLB_MIXED) ------------------------------------------------- */
 

@@ -18,7 +18,8 @@ from ._lib import (BOTTOM, LEFT, RIGHT, TOP, FdlbError, check, desc_from_case, m
                    quad_full_range, quad_half_range, tile_count, tile_describe)
 
 __all__ = ["Problem", "Batch", "Mlp", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
-           "RIGHT", "tile_count", "tile_describe", "stream_copy", "stream_probe"]
+           "RIGHT", "tile_count", "tile_describe", "stream_copy", "stream_probe", "set_tune_cache",
+           "default_tune_cache"]
 
 
 def _torch():
@@ -232,6 +233,26 @@ def stream_copy(dst, src, nbytes: int, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     check(_lib.lib.fdlb_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
                                     int(nbytes), C.c_void_p(s.cuda_stream)))
+
+
+def default_tune_cache() -> str:
+    """$FDLB_TUNE_CACHE if set (empty: no cache), else <user cache dir>/fdlb/tiles.txt."""
+    import os
+    if "FDLB_TUNE_CACHE" in os.environ:
+        return os.environ["FDLB_TUNE_CACHE"]
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "fdlb", "tiles.txt")
+
+
+def set_tune_cache(path: Optional[str]):
+    """Cache autotuned tile choices in this text file (fdlb_set_tune_cache); None or "" disables."""
+    import os
+    if path:
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        except OSError:
+            pass
+    check(_lib.lib.fdlb_set_tune_cache(path.encode() if path else None))
 
 
 PROBE_MODES = {"plain": 0, "nt_load": 1, "nt_store": 2, "nt": 3, "read": 4, "write": 5}

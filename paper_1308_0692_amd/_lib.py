@@ -98,6 +98,7 @@ def _load():
         "fdlb_problem_active_precision": (C.c_int, [vp]),
         "fdlb_promote": (C.c_int, [vp]),
         "fdlb_stream_copy": (C.c_int, [vp, vp, C.c_size_t, vp]),
+        "fdlb_set_tune_cache": (C.c_int, [C.c_char_p]),
         "fdlb_stream_probe": (C.c_int, [vp, vp, C.c_size_t, C.c_int, vp]),
         "fdlb_batch_create": (C.c_int, [C.POINTER(ProblemDesc), C.c_int, C.POINTER(vp)]),
         "fdlb_batch_destroy": (None, [vp]),

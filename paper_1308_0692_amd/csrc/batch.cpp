@@ -12,6 +12,7 @@
 // that step; the host drops it from the block map at the next check, so the remaining
 // problems keep the chip.  Chunks of `check_every` steps are replayed as captured graphs.
 #include <algorithm>
+#include <cstdio>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -56,6 +57,7 @@ struct fdlb_batch {
     bool end_reduce = false;        // some member reduces inline (closed at the end of a chunk)
     size_t off_ctrlptr = 0, off_ctrlbuf = 0;
     int retile_members = 8;         // re-choose tiles once at most this many instances remain (0: never)
+    bool pseudo = false;            // every member steps with velocity-local pseudo-time steps
     char* d_state = nullptr;
     char* d_work = nullptr;
     hipStream_t stream = nullptr;
@@ -366,10 +368,10 @@ static void enqueue_batch_step(fdlb_batch& b, int parity, bool prev) {
         const BlockMap* map = (const BlockMap*)(b.d_work + G.off_map);
         if (g == 0)
             launch_batch_step<float>(G.tile, map, (const StepArgs<float>*)(b.d_work + G.off_args) + v, G.map_blocks,
-                                     b.stream);
+                                     b.pseudo, b.stream);
         else
             launch_batch_step<double>(G.tile, map, (const StepArgs<double>*)(b.d_work + G.off_args) + v,
-                                      G.map_blocks, b.stream);
+                                      G.map_blocks, b.pseudo, b.stream);
     }
     if (b.step_reduce)
         launch_batch_reduce((const ReduceArgs*)(b.d_work + b.off_rargs) + (size_t)(parity * 2) * n, n, b.stream);
@@ -758,7 +760,9 @@ int fdlb_batch_set_retile(fdlb_batch* b, int max_members) {
 
 int fdlb_batch_set_pseudo_time(fdlb_batch* b, int on) {
     return guard_call([&] {
-        for (auto& p : bh(b).probs) p->pseudo = on != 0;  // the next solve uploads the step arguments
+        fdlb_batch& B = bh(b);
+        B.pseudo = on != 0;
+        for (auto& p : B.probs) p->pseudo = on != 0;  // the next solve uploads the step arguments
         return FDLB_OK;
     });
 }
@@ -777,8 +781,41 @@ int fdlb_batch_active_precision(const fdlb_batch* b, int i) {
 
 int fdlb_batch_autotune(fdlb_batch* b, int steps, double* best_ms_per_step) {
     return guard_call([&] {
-        const double ms = batch_autotune(bh(b), steps);
-        batch_autotune_promoted(bh(b), steps);
+        fdlb_batch& B = bh(b);
+        std::string key;
+        if (tune_cache_enabled()) {
+            // the batch's whole make-up: every member's grid, velocity count and axes
+            std::string members;
+            for (auto& p : B.probs)
+                members += std::to_string(p->d.nx) + "x" + std::to_string(p->d.ny) + "q" + std::to_string(p->q) +
+                           (p->d.periodic_x ? "p" : "") + (p->d.periodic_y ? "P" : "") + ",";
+            uint64_t h = 1469598103934665603ULL;
+            for (char c : members) h = (h ^ (unsigned char)c) * 1099511628211ULL;
+            char hx[32];
+            std::snprintf(hx, sizeof(hx), "%016llx", (unsigned long long)h);
+            key = tune_key_prefix() + "/batch/prec" + std::to_string(B.precision) + "/n" +
+                  std::to_string(B.probs.size()) + "/" + hx;
+            int t = -1, ta = -1;
+            double ms = 0;
+            if (B.bound && tune_cache_get(key, t, ta, ms)) {
+                const int g = primary_group(B);
+                const bool ok = t < (int)tile_shapes(prec_of_group(g)).size() && tile_fits_all(B, g, t) &&
+                                (ta < 0 || !B.grp[1].used || g == 1 ||
+                                 (ta < (int)tile_shapes(FDLB_FP64).size() && tile_fits_all(B, 1, ta)));
+                if (ok) {
+                    group_set_tile(B, g, t);
+                    if (ta >= 0 && B.grp[1].used && g != 1) group_set_tile(B, 1, ta);
+                    for (auto& p : B.probs) init_equilibrium(*p, nullptr, nullptr, nullptr, 0);
+                    if (best_ms_per_step) *best_ms_per_step = ms;
+                    return FDLB_OK;
+                }
+            }
+        }
+        const double ms = batch_autotune(B, steps);
+        batch_autotune_promoted(B, steps);
+        if (!key.empty())
+            tune_cache_put(key, B.grp[primary_group(B)].tile,
+                           B.precision == FDLB_MIXED && B.grp[1].used ? B.grp[1].tile : -1, ms);
         if (best_ms_per_step) *best_ms_per_step = ms;
         return FDLB_OK;
     });

@@ -286,6 +286,13 @@ int fdlb_autotune(fdlb_problem* p, int steps, double* best_ms_per_step) {
     });
 }
 
+int fdlb_set_tune_cache(const char* path) {
+    return guard([&] {
+        set_tune_cache_path(path);
+        return FDLB_OK;
+    });
+}
+
 int fdlb_field_samples(fdlb_problem* p, float* d_in, float* d_target) {
     return guard([&] {
         field_samples(handle(p), d_in, d_target);

@@ -74,7 +74,7 @@ struct StepArgs {
     int32_t nx, ny, L;
     int32_t tiles_x, tiles_y;
     int32_t prev_nb;      // blocks of the previous step whose partials are still unreduced, or 0
-    int32_t pseudo;       // 1: store h + pt (S h - h) instead of S h (velocity-local pseudo-time steps)
+    int32_t pseudo;       // 1: store h + pt (S h - h) instead of S h (selects the kernel variant)
     int64_t plane;        // nx * ny
     T omega;              // dt / Kn in the storage type
     T pad1;
@@ -112,12 +112,8 @@ struct ReduceArgs {
     int32_t wave_order;  // 1: sum in the single-wave order of the inline reduction
 };
 
-// Velocity-local pseudo-time steps: the largest stretch of a velocity's step, and the largest
-// stretched relaxation rate omega * stretch (the iteration h + stretch (S h - h) was stable in
-// every case tried with this margin; at 0.5 and 1 it diverged on 12 x 12 and 8 x 8 velocity sets
-// at Kn = 0.1).
+// Velocity-local pseudo-time steps: the largest stretch of a velocity's step.
 constexpr double FDLB_PSEUDO_MAX = 64.0;
-constexpr double FDLB_PSEUDO_OMEGA_MAX = 0.25;
 
 // Residual partials of a launch with at most this many blocks are reduced inside the next step
 // kernel (every wave of it sums them in the same order) instead of by a kernel of their own;
@@ -146,7 +142,8 @@ void launch_step(int tile, const StepArgs<T>& a, int nblocks, hipStream_t stream
 void launch_reduce(const double* partials, int nblocks, double* ctrl, int64_t inc, hipStream_t stream);
 void launch_reduce_wave(const double* partials, int nblocks, double* ctrl, hipStream_t stream);
 template <class T>
-void launch_batch_step(int tile, const BlockMap* map, const StepArgs<T>* args, int nblocks, hipStream_t stream);
+void launch_batch_step(int tile, const BlockMap* map, const StepArgs<T>* args, int nblocks, bool pseudo,
+                       hipStream_t stream);
 void launch_batch_reduce(const ReduceArgs* ra, int n, hipStream_t stream);
 template <class T>
 void launch_seed(T* h, int q, int64_t plane, const VelEntry<double>* vel, const double* rho,
@@ -176,6 +173,13 @@ void launch_widen(const float* src, double* dst, int64_t n, hipStream_t stream);
 void launch_gather_ctrl(const double* const* ptrs, int n, double* out, hipStream_t stream);
 // The first 8 doubles of a control block: step 0, nothing recorded, no freeze request.
 void launch_ctrl_reset(double* ctrl, hipStream_t stream);
+// On-disk cache of autotuned tiles (tunecache.cpp): enabled by a non-empty path.
+void set_tune_cache_path(const char* path);
+bool tune_cache_enabled();
+std::string tune_key_prefix();  // device and compiled tile table
+bool tune_cache_get(const std::string& key, int& tile, int& tile_alt, double& ms);
+void tune_cache_put(const std::string& key, int tile, int tile_alt, double ms);
+
 // Device address of the library's static workspace (FDLB_STATIC_SCRATCH_BYTES) on the current
 // device, looked up on the first call per device (scratch.hip).
 char* static_scratch();

@@ -231,7 +231,7 @@ __device__ __forceinline__ void record_step(double* __restrict__ ctrl, double nu
 // latency instead of four; otherwise it takes every WA-th velocity of each quadrant.
 // bid/nb: this block's index among the blocks of its problem; part: where its residual
 // partials go.
-template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD>
+template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD, bool PS>
 __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, const int nb,
                                           double* __restrict__ part) {
     constexpr int LY = 64 / LX;
@@ -510,7 +510,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
                     fn[r][v] = gc - c.nux * (gc - gx) - c.nuy * (gc - gy);
                 }
             }
-            if (A.pseudo) {
+            if constexpr (PS) {
                 // Velocity-local pseudo-time steps (steady iterations only): the state moves by
                 // pt times the step's change, h + pt (S h - h), which keeps the fixed point of S.
                 // The change (relaxation increment minus the transport differences) is formed
@@ -735,19 +735,19 @@ __device__ __forceinline__ void reduce_previous(const StepArgs<T>& A) {
     if (threadIdx.x == 0) record_step(A.ctrl, num, den, um, 1);
 }
 
-template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD>
+template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD, bool PS>
 __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR step_kernel(const StepArgs<T> A) {
     const int nb = (int)gridDim.x - (A.prev_nb > 0 ? 1 : 0);  // the last block reduces, if any
     if ((int)blockIdx.x == nb) {
         reduce_previous(A);
         return;
     }
-    step_body<T, VX, K, LX, WPB, WA, WX, NT, PD>(A, blockIdx.x, nb, A.partials + 3 * blockIdx.x);
+    step_body<T, VX, K, LX, WPB, WA, WX, NT, PD, PS>(A, blockIdx.x, nb, A.partials + 3 * blockIdx.x);
 }
 
 // Many problems in one launch: block g works on tile map[g].local of problem map[g].inst.
 // Each problem's blocks start at a multiple of 8, so the XCD-aware tile order holds per problem.
-template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD>
+template <class T, int VX, int K, int LX, int WPB, int WA, int WX, bool NT, int PD, bool PS>
 __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR batch_step_kernel(const BlockMap* __restrict__ map,
                                                                         const StepArgs<T>* __restrict__ args) {
     const BlockMap m = map[blockIdx.x];
@@ -757,7 +757,7 @@ __global__ void __launch_bounds__(64 * WX * WPB * WA) FDLB_WAVES_ATTR batch_step
         if (A.prev_nb > 0) reduce_previous(A);
         return;
     }
-    step_body<T, VX, K, LX, WPB, WA, WX, NT, PD>(A, m.local, m.nb, A.partials + 3 * m.local);
+    step_body<T, VX, K, LX, WPB, WA, WX, NT, PD, PS>(A, m.local, m.nb, A.partials + 3 * m.local);
 }
 
 // ---------------------------------------------------------------------------
@@ -1163,10 +1163,14 @@ const std::vector<TileShape>& tile_shapes(int precision) {
 template <>
 void launch_step<float>(int tile, const StepArgs<float>& a, int nblocks, hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                              \
-    case id:                                                                                             \
-        hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
-                           stream, a);                                                                   \
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                         \
+    case id:                                                                                                \
+        if (a.pseudo)                                                                                       \
+            hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD, true>), dim3(nblocks),       \
+                               dim3(64 * WX * WPB * WA), 0, stream, a);                                     \
+        else                                                                                                \
+            hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD, false>), dim3(nblocks),      \
+                               dim3(64 * WX * WPB * WA), 0, stream, a);                                     \
         break;
         FDLB_TILES_FP32(FDLB_CASE)
 #undef FDLB_CASE
@@ -1178,10 +1182,14 @@ void launch_step<float>(int tile, const StepArgs<float>& a, int nblocks, hipStre
 template <>
 void launch_step<double>(int tile, const StepArgs<double>& a, int nblocks, hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                              \
-    case id:                                                                                             \
-        hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
-                           stream, a);                                                                   \
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                         \
+    case id:                                                                                                \
+        if (a.pseudo)                                                                                       \
+            hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD, true>), dim3(nblocks),       \
+                               dim3(64 * WX * WPB * WA), 0, stream, a);                                     \
+        else                                                                                                \
+            hipLaunchKernelGGL((step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD, false>), dim3(nblocks),      \
+                               dim3(64 * WX * WPB * WA), 0, stream, a);                                     \
         break;
         FDLB_TILES_FP64(FDLB_CASE)
 #undef FDLB_CASE
@@ -1191,13 +1199,17 @@ void launch_step<double>(int tile, const StepArgs<double>& a, int nblocks, hipSt
 }
 
 template <>
-void launch_batch_step<float>(int tile, const BlockMap* map, const StepArgs<float>* args, int nblocks,
+void launch_batch_step<float>(int tile, const BlockMap* map, const StepArgs<float>* args, int nblocks, bool pseudo,
                               hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                                    \
-    case id:                                                                                                   \
-        hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
-                           stream, map, args);                                                                 \
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                         \
+    case id:                                                                                                \
+        if (pseudo)                                                                                         \
+            hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD, true>), dim3(nblocks), \
+                               dim3(64 * WX * WPB * WA), 0, stream, map, args);                             \
+        else                                                                                                \
+            hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD, false>), dim3(nblocks),\
+                               dim3(64 * WX * WPB * WA), 0, stream, map, args);                             \
         break;
         FDLB_TILES_FP32(FDLB_CASE)
 #undef FDLB_CASE
@@ -1207,13 +1219,17 @@ void launch_batch_step<float>(int tile, const BlockMap* map, const StepArgs<floa
 }
 
 template <>
-void launch_batch_step<double>(int tile, const BlockMap* map, const StepArgs<double>* args, int nblocks,
-                               hipStream_t stream) {
+void launch_batch_step<double>(int tile, const BlockMap* map, const StepArgs<double>* args, int nblocks, bool pseudo,
+                              hipStream_t stream) {
     switch (tile) {
-#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                                    \
-    case id:                                                                                                   \
-        hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD>), dim3(nblocks), dim3(64 * WX * WPB * WA), 0, \
-                           stream, map, args);                                                                 \
+#define FDLB_CASE(id, T, VX, K, LX, WPB, WA, WX, NT, PD)                                                         \
+    case id:                                                                                                \
+        if (pseudo)                                                                                         \
+            hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD, true>), dim3(nblocks), \
+                               dim3(64 * WX * WPB * WA), 0, stream, map, args);                             \
+        else                                                                                                \
+            hipLaunchKernelGGL((batch_step_kernel<T, VX, K, LX, WPB, WA, WX, NT, PD, false>), dim3(nblocks),\
+                               dim3(64 * WX * WPB * WA), 0, stream, map, args);                             \
         break;
         FDLB_TILES_FP64(FDLB_CASE)
 #undef FDLB_CASE

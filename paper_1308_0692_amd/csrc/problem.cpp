@@ -172,15 +172,21 @@ void build_problem(fdlb_problem& p, const fdlb_problem_desc& d) {
     if (!d.allow_unstable && (d.cfl > 1.0 || p.omega > 1.0))
         throw Error(FDLB_EUNSTABLE, "explicit scheme unstable: need cfl <= 1 and dt/Kn <= 1 (dt/Kn = " +
                                         std::to_string(p.omega) + ")");
-    // Pseudo-time stretch of each velocity for steady iterations with local steps: the factor
-    // that brings its own Courant number up to the problem's, limited so that the stretched
-    // relaxation rate stays at FDLB_PSEUDO_OMEGA_MAX and the factor at FDLB_PSEUDO_MAX.
+    // Pseudo-time stretch s of each velocity for steady iterations with local steps.  For one
+    // velocity, with the equilibrium held fixed, the update h + s (S h - h) multiplies a Fourier
+    // mode by 1 - s omega - s nu (1 - omega) z, z = 1 - e^{-i theta} (nu = nu_x + nu_y with a
+    // z per axis), a circle that stays in the unit disk while s (omega + 2 nu (1 - omega)) <= 2.
+    // s is taken as large as the problem's own margin allows, s (omega + 2 nu (1 - omega)) = 2 cfl
+    // (the plain scheme has s = 1 and omega + 2 nu (1 - omega) <= 2 cfl for its fastest
+    // velocity), with the stretched relaxation rate s omega <= 1 as in the plain scheme and
+    // s <= FDLB_PSEUDO_MAX.
     p.pt.assign(p.q, 1.0);
     for (int a = 0; a < p.q; ++a) {
         const double nu = p.dt * (std::fabs(p.xi_x[a]) * p.nux_scale + std::fabs(p.xi_y[a]) * p.nuy_scale);
         double f = FDLB_PSEUDO_MAX;
-        if (nu > 0) f = std::min(f, d.cfl / nu);
-        if (p.omega > 0) f = std::min(f, FDLB_PSEUDO_OMEGA_MAX / p.omega);
+        const double den = nu * (1.0 - p.omega) + 0.5 * p.omega;
+        if (den > 0) f = std::min(f, d.cfl / den);
+        if (p.omega > 0) f = std::min(f, 1.0 / p.omega);
         if (nu == 0 && p.omega == 0) f = 1.0;  // a population that never changes
         p.pt[a] = (double)(float)std::max(1.0, f);  // the kernels' table holds it as a float
     }
@@ -933,11 +939,29 @@ void set_tile(fdlb_problem& p, int tile) {
     p.tile = tile;
 }
 
+static std::string tune_key(const fdlb_problem& p) {
+    return tune_key_prefix() + "/problem/prec" + std::to_string(p.d.precision) + "/" + std::to_string(p.d.nx) + "x" +
+           std::to_string(p.d.ny) + "/q" + std::to_string(p.q) + "/per" + std::to_string(p.d.periodic_x) +
+           std::to_string(p.d.periodic_y);
+}
+
 double autotune(fdlb_problem& p, int steps) {
     require_bound(p);
     if (steps < 1) throw Error(FDLB_EINVAL, "steps must be >= 1");
     restart_precision(p);  // a mixed-precision problem tunes its float phase
     const auto& shapes = tile_shapes(p.prec);
+    std::string key;
+    if (tune_cache_enabled()) {
+        key = tune_key(p);
+        int t = -1, ta = -1;
+        double ms = 0;
+        if (tune_cache_get(key, t, ta, ms) && t < (int)shapes.size() &&
+            tile_fits(shapes[t], p.d.nx, p.d.ny, p.d.periodic_x, p.d.periodic_y) && nblocks_of(p, t) <= p.max_blocks) {
+            p.tile = t;
+            init_equilibrium(p, nullptr, nullptr, nullptr, 0);
+            return ms;
+        }
+    }
     hipEvent_t e0, e1;
     FDLB_HIP(hipEventCreate(&e0));
     FDLB_HIP(hipEventCreate(&e1));
@@ -969,6 +993,7 @@ double autotune(fdlb_problem& p, int steps) {
     (void)hipEventDestroy(e1);
     p.tile = best_tile;
     init_equilibrium(p, nullptr, nullptr, nullptr, 0);
+    if (!key.empty()) tune_cache_put(key, best_tile, -1, best);
     return best;
 }
 
