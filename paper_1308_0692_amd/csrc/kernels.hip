@@ -1124,7 +1124,8 @@ __global__ void copy_tail_kernel(char* __restrict__ dst, const char* __restrict_
     X(26, float, 1, 1, 1, 1, 8, 1, 0, 1) \
     X(27, float, 1, 2, 1, 1, 4, 1, 0, 1) \
     X(28, float, 4, 2, 16, 1, 4, 1, 1, 1) \
-    X(29, float, 4, 1, 16, 1, 4, 1, 1, 1)
+    X(29, float, 4, 1, 16, 1, 4, 1, 1, 1) \
+    X(30, float, 4, 2, 16, 1, 2, 1, 1, 1)
 #endif
 
 #ifndef FDLB_TILES_FP64
