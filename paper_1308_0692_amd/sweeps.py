@@ -15,8 +15,9 @@ Conventions (all in the units of Eq. (1); Kn is Eq. (1)'s Knudsen number):
   D             drag on the lid: -(1/u_w) times the mean over the lid's faces of the face xy
                 stress (the tangential force per unit lid length; > 0)
   G             recirculating flow rate: (1/u_w) times the integral over the vertical mid-line
-                of the positive part of u_x (the net flux through the line is zero at steady
-                state); on an even grid the mid-line is the average of columns N/2 - 1, N/2
+                of |u_x| (the net flux through the line is zero at steady state, so this is twice
+                the flow carried each way); on an even grid the mid-line is the average of
+                columns N/2 - 1, N/2
 The paper's own definitions of D and G are in a cited work it does not reproduce, so these are
 stated here rather than taken from it.
 
@@ -152,7 +153,7 @@ def cavity_sweep(kns: Sequence[float], lattice="D2Qh16", n: int = 64, refine: bo
             _, ux, _, _ = b.moments(i)
             mid = _midline(ux) / u_w
             row["D" + tag] = -float(np.mean(pw)) / u_w
-            row["G" + tag] = float(np.sum(np.clip(mid, 0.0, None)) / m)
+            row["G" + tag] = float(np.sum(np.abs(mid)) / m)
             row["steps" + tag] = int(reps[i]["steps"])
             if g == 0:
                 row["u_mid"] = mid.tolist()
