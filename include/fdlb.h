@@ -568,6 +568,109 @@ int fdlb_mlp_predict_fields(fdlb_mlp *m, double kn, int nx, int ny, double u_w, 
 int fdlb_field_samples(fdlb_problem *p, float *d_in, float *d_target);
 int fdlb_batch_field_samples(fdlb_batch *b, int i, float *d_in, float *d_target);
 
+/* ---- hybrid half-range / full-range channel ------------------------------------------
+ *
+ * The coupling the paper proposes in its closing remarks: away from walls a half-range
+ * model with N velocities behaves like a full-range one with N/2^d, so half-range nodes are
+ * kept only in the Knudsen layers next to the walls and the bulk runs on the cheaper
+ * full-range set.  Built here for the planar Couette channel (plates at y = 0 and y = 1,
+ * x periodic with one cell, the geometry of Eqs. 10-11), one channel per workgroup with the
+ * whole state resident in LDS for the duration of a launch.
+ *
+ * Scheme: ny cells across the channel; the first and the last `layer` cells carry the x rule
+ * times a half-range y rule of n_half nodes per half-line (the layer set, Q_l = Q_x 2 n_half
+ * velocities), the others the x rule times an n_full-node full-range y rule (the bulk set,
+ * Q_b = Q_x n_full).  Each cell relaxes with its own set (Eqs. 1, 5-7), the plates act on
+ * the layer cells as the walls of the plain scheme (Eqs. 8-9), and every population then
+ * moves by the donor cell in y.  A donor cell in the other zone is seen through that zone's
+ * post-relaxation distribution carried to this zone's y nodes, for each x node, by a
+ * truncated Hermite expansion: c_m = (1/m!) sum_a g_a He_m(xi_a) over the source nodes,
+ * g'_k = w'_k sum_{m <= K} c_m He_m(xi'_k), with K = n_full - 1 from bulk to layer (the
+ * polynomial through the bulk values) and K = min(n_half, n_full) - 1 from layer to bulk
+ * (the degree whose coefficients the half-range rule integrates exactly).  Both maps carry
+ * every w * polynomial of degree <= K exactly, the equilibrium among them; the interface is
+ * conservative only to that extent (the defect vanishes with the Knudsen layer's remnant at
+ * the interface).  dt = cfl / (ny max |xi_y|) over the y rules present, omega = dt / Kn.
+ * With 2 layer == ny there is no bulk and the channel is the plain half-range scheme.
+ *
+ * State layout (doubles, raw f): the 2 layer cells' populations plane by plane,
+ * [alpha][c] with alpha = y node * Q_x + x node and c over the layer cells in ascending y
+ * (bottom layer, then top layer), followed by the bulk cells' populations [k][b] the same
+ * way.  One channel holds 2 layer Q_l + (ny - 2 layer) Q_b doubles.
+ */
+typedef struct fdlb_hybrid_desc {
+    int32_t ny;              /* cells across the channel, 2..4096 */
+    int32_t layer;           /* half-range cells next to each plate, 1..ny/2 */
+    double kn;               /* Knudsen number of Eq. (1), > 0; INFINITY allowed */
+    double u_bottom, u_top;  /* tangential plate speeds along +x */
+    double cfl;              /* Courant number in (0, 1] */
+    int32_t qx_kind, qx_n;   /* x rule (FDLB_HALF or FDLB_FULL, at least 2 nodes per rule / half) */
+    int32_t n_half;          /* half-range y nodes per half-line in the layers, 2..8 */
+    int32_t n_full;          /* full-range y nodes in the bulk, 2..16 */
+} fdlb_hybrid_desc;
+
+typedef struct fdlb_hybrid fdlb_hybrid; /* opaque: a batch of channels */
+
+/* Validate n descriptions (1..65536) and build the velocity sets, time steps and interface
+ * maps.  Host only.  FDLB_EINVAL for a bad description, FDLB_EUNSTABLE for omega > 1 or
+ * cfl > 1; Q_x 2 n_half <= 512. */
+int fdlb_hybrid_create(const fdlb_hybrid_desc *descs, int n, fdlb_hybrid **out);
+void fdlb_hybrid_destroy(fdlb_hybrid *h); /* NULL is a no-op; no GPU call */
+
+/* Sizes, in bytes, of the caller-provided device state arena (every channel's populations,
+ * 256-byte aligned each) and workspace (tables, control blocks, staging). */
+size_t fdlb_hybrid_state_bytes(const fdlb_hybrid *h);
+size_t fdlb_hybrid_workspace_bytes(const fdlb_hybrid *h);
+/* Layout of channel i: velocities of the layer and bulk sets, doubles of its state, dt and
+ * omega.  Any pointer may be NULL. */
+int fdlb_hybrid_info(const fdlb_hybrid *h, int i, int32_t *q_layer, int32_t *q_bulk,
+                     int64_t *state_doubles, double *dt, double *omega);
+
+/* Bind the arenas (256-byte aligned) and a stream; uploads the tables (synchronous).
+ * FDLB_EINVAL if a channel's LDS footprint (16 bytes per population plus 40 per cell and
+ * its tables) exceeds what one workgroup may hold on the current device. */
+int fdlb_hybrid_bind(fdlb_hybrid *h, void *d_state, void *d_workspace, void *stream);
+
+/* Seed channel i at f = w (rho + xi . rho u) on each cell's own set from host arrays of ny
+ * doubles (NULL: rho = 1, u = 0).  Synchronous. */
+int fdlb_hybrid_init_equilibrium(fdlb_hybrid *h, int i, const double *rho, const double *ux,
+                                 const double *uy);
+/* Copy channel i's state (layout above) from / to a host array.  Synchronous. */
+int fdlb_hybrid_set_state(fdlb_hybrid *h, int i, const double *host_state);
+int fdlb_hybrid_get_state(fdlb_hybrid *h, int i, double *host_state);
+
+/* Advance every channel by exactly nsteps steps.  Asynchronous. */
+int fdlb_hybrid_step(fdlb_hybrid *h, int64_t nsteps);
+
+/*
+ * March every channel until the residual of a step, R = ||u^{n+1} - u^n||_2 / ||u^{n+1}||_2
+ * over the channel's cells, falls below tol (the state is that step's) or max_steps steps
+ * have been taken.  The residual is evaluated every step inside the launch; a launch runs
+ * at most `chunk` steps (<= 0: 100000) and converged channels leave the next launch.
+ * reps (may be NULL) receives n reports: steps, first_below, residual, wall_s, updates/s
+ * (cells x own velocities x steps / wall_s), status; history (if given) the residual of
+ * every step up to its capacity.  Synchronous.  FDLB_OK if every channel converged,
+ * FDLB_ENOTCONVERGED or FDLB_EDIVERGED (a non-finite residual) otherwise.
+ */
+int fdlb_hybrid_solve(fdlb_hybrid *h, double tol, int64_t max_steps, int64_t chunk,
+                      fdlb_report *reps);
+
+/* Cell fields of channel i (host arrays of ny doubles, any may be NULL): rho, u_x, u_y
+ * (Eqs. 6-7 over the cell's own set) and the xy stress of the post-relaxation state.
+ * Synchronous. */
+int fdlb_hybrid_moments(fdlb_hybrid *h, int i, double *rho, double *ux, double *uy, double *pxy);
+
+/*
+ * Face values of channel i into out[8]: u_x and p_xy of the face state at the bottom plate
+ * (arriving populations of the wall cell after relaxation, emission of Eq. 8), the same at
+ * the top plate, then the y-flux of x-momentum through the lower interface as the layer
+ * cell's and as the bulk cell's update transport it, and through the upper interface as the
+ * bulk cell's and the layer cell's update do (NaN without a bulk).  At a steady state the
+ * flux is uniform inside each zone; the two values at an interface differ by the coupling's
+ * conservation defect.  Synchronous.
+ */
+int fdlb_hybrid_faces(fdlb_hybrid *h, int i, double *out);
+
 /* ---- measurement helpers ------------------------------------------------------------ */
 
 /* Copy `bytes` bytes device-to-device with the library's streaming copy kernel

@@ -323,8 +323,8 @@ class HybridChannel:
         then top layer), then the bulk cells' populations the same way."""
         lay = np.nonzero(self.in_layer)[0]
         blk = np.nonzero(~self.in_layer)[0]
-        h = state[0][lay].reshape(len(lay), -1).T
-        f = state[1][blk].reshape(len(blk), -1).T
+        h = state[0][lay].reshape(len(lay), state[0].shape[1] * state[0].shape[2]).T
+        f = state[1][blk].reshape(len(blk), state[1].shape[1] * state[1].shape[2]).T
         return np.concatenate([h.ravel(), f.ravel()])
 
     def unpack(self, flat: np.ndarray):

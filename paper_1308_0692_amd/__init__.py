@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (BOTTOM, LEFT, RIGHT, TOP, FdlbError, check, desc_from_case, make_desc,
                    quad_full_range, quad_half_range, tile_count, tile_describe)
 
-__all__ = ["Problem", "Batch", "Mlp", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
+__all__ = ["Problem", "Batch", "Mlp", "Hybrid", "FdlbError", "quad_half_range", "quad_full_range", "BOTTOM", "TOP", "LEFT",
            "RIGHT", "tile_count", "tile_describe", "stream_copy", "stream_probe", "set_tune_cache",
            "default_tune_cache"]
 
@@ -393,6 +393,100 @@ class Batch:
         if getattr(self, "_h", None):
             self._stream.synchronize()
             _lib.lib.fdlb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hybrid:
+    """Couette channels with half-range layers at the plates and a full-range bulk (one
+    workgroup per channel, state resident in LDS).  ``channels`` is a list of dicts with the
+    keys of ``_lib.make_hybrid_desc`` (ny, layer, kn, u_w, n_half, n_full, qx, cfl)."""
+
+    def __init__(self, channels, *, device="cuda:0", stream=None, poison: bool = False):
+        torch = _torch()
+        descs = [_lib.make_hybrid_desc(**c) for c in channels]
+        self.n = len(descs)
+        arr = (_lib.HybridDesc * self.n)(*descs)
+        h = C.c_void_p()
+        check(_lib.lib.fdlb_hybrid_create(arr, self.n, C.byref(h)))
+        self._h = h
+        self.ny = [d.ny for d in descs]
+        self.info = []
+        for i in range(self.n):
+            ql, qb, sd = C.c_int32(), C.c_int32(), C.c_int64()
+            dt, om = C.c_double(), C.c_double()
+            check(_lib.lib.fdlb_hybrid_info(h, i, C.byref(ql), C.byref(qb), C.byref(sd), C.byref(dt), C.byref(om)))
+            self.info.append(dict(q_layer=ql.value, q_bulk=qb.value, state_doubles=sd.value, dt=dt.value,
+                                  omega=om.value))
+        self.device = device
+        self._stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self._state_t, self._state = _alloc(_lib.lib.fdlb_hybrid_state_bytes(h), device, poison)
+        self._work_t, self._work = _alloc(_lib.lib.fdlb_hybrid_workspace_bytes(h), device, poison)
+        check(_lib.lib.fdlb_hybrid_bind(h, C.c_void_p(self._state), C.c_void_p(self._work),
+                                        C.c_void_p(self._stream.cuda_stream)))
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def init_equilibrium(self, i: int, rho=None, ux=None, uy=None):
+        arr = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny[i])
+               for a in (rho, ux, uy)]
+        check(_lib.lib.fdlb_hybrid_init_equilibrium(self._h, int(i), *[_lib._dp(a) for a in arr]))
+
+    def init_all(self):
+        for i in range(self.n):
+            self.init_equilibrium(i)
+
+    def set_state(self, i: int, flat: np.ndarray):
+        flat = np.ascontiguousarray(flat, dtype=np.float64)
+        assert flat.shape == (self.info[i]["state_doubles"],)
+        check(_lib.lib.fdlb_hybrid_set_state(self._h, int(i), _lib._dp(flat)))
+
+    def state(self, i: int) -> np.ndarray:
+        out = np.empty(self.info[i]["state_doubles"])
+        check(_lib.lib.fdlb_hybrid_get_state(self._h, int(i), _lib._dp(out)))
+        return out
+
+    def step(self, n: int):
+        check(_lib.lib.fdlb_hybrid_step(self._h, int(n)))
+
+    def solve(self, tol: float, max_steps: int, chunk: int = 0, history_cap: int = 0):
+        """Returns (status, [report dict per channel])."""
+        reps = (_lib.Report * self.n)()
+        hists = [np.zeros(max(history_cap, 1)) for _ in range(self.n)]
+        for r, h in zip(reps, hists):
+            r.history_cap = history_cap
+            r.history = _lib._dp(h) if history_cap else None
+        code = _lib.lib.fdlb_hybrid_solve(self._h, float(tol), int(max_steps), int(chunk), reps)
+        check(code, allow=(_lib.OK, _lib.ENOTCONVERGED, _lib.EDIVERGED))
+        out = [dict(status=r.status, steps=r.steps, first_below=r.first_below, residual=r.residual,
+                    wall_s=r.wall_s, updates_per_s=r.updates_per_s, history=h[:r.history_len].copy())
+               for r, h in zip(reps, hists)]
+        return code, out
+
+    def moments(self, i: int):
+        """(rho, u_x, u_y, p_xy) per cell, bottom to top."""
+        out = [np.empty(self.ny[i]) for _ in range(4)]
+        check(_lib.lib.fdlb_hybrid_moments(self._h, int(i), *[_lib._dp(a) for a in out]))
+        return tuple(out)
+
+    def faces(self, i: int) -> np.ndarray:
+        """[u_x, p_xy at the bottom plate, u_x, p_xy at the top plate, lower interface flux from
+        the layer / bulk cell, upper interface flux from the bulk / layer cell]."""
+        out = np.empty(8)
+        check(_lib.lib.fdlb_hybrid_faces(self._h, int(i), _lib._dp(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._stream.synchronize()
+            _lib.lib.fdlb_hybrid_destroy(self._h)
             self._h = None
 
     def __del__(self):

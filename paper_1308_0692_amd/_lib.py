@@ -52,6 +52,15 @@ class Report(C.Structure):
     ]
 
 
+class HybridDesc(C.Structure):
+    _fields_ = [
+        ("ny", C.c_int32), ("layer", C.c_int32),
+        ("kn", C.c_double), ("u_bottom", C.c_double), ("u_top", C.c_double), ("cfl", C.c_double),
+        ("qx_kind", C.c_int32), ("qx_n", C.c_int32),
+        ("n_half", C.c_int32), ("n_full", C.c_int32),
+    ]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with python paper_1308_0692_amd/build.py")
@@ -133,6 +142,19 @@ def _load():
         "fdlb_mlp_predict_fields": (C.c_int, [vp, C.c_double, C.c_int, C.c_int, C.c_double, vp, vp, vp]),
         "fdlb_field_samples": (C.c_int, [vp, vp, vp]),
         "fdlb_batch_field_samples": (C.c_int, [vp, C.c_int, vp, vp]),
+        "fdlb_hybrid_create": (C.c_int, [C.POINTER(HybridDesc), C.c_int, C.POINTER(vp)]),
+        "fdlb_hybrid_destroy": (None, [vp]),
+        "fdlb_hybrid_state_bytes": (C.c_size_t, [vp]),
+        "fdlb_hybrid_workspace_bytes": (C.c_size_t, [vp]),
+        "fdlb_hybrid_info": (C.c_int, [vp, C.c_int, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), dp, dp]),
+        "fdlb_hybrid_bind": (C.c_int, [vp, vp, vp, vp]),
+        "fdlb_hybrid_init_equilibrium": (C.c_int, [vp, C.c_int, dp, dp, dp]),
+        "fdlb_hybrid_set_state": (C.c_int, [vp, C.c_int, dp]),
+        "fdlb_hybrid_get_state": (C.c_int, [vp, C.c_int, dp]),
+        "fdlb_hybrid_step": (C.c_int, [vp, i64]),
+        "fdlb_hybrid_solve": (C.c_int, [vp, C.c_double, i64, i64, C.POINTER(Report)]),
+        "fdlb_hybrid_moments": (C.c_int, [vp, C.c_int, dp, dp, dp, dp]),
+        "fdlb_hybrid_faces": (C.c_int, [vp, C.c_int, dp]),
         "fdlb_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -184,6 +206,20 @@ def make_desc(nx, ny, periodic_x, periodic_y, wall_u, kn, qx, qy, cfl=0.9, preci
     d.qy_kind, d.qy_n = kinds[qy[0]], int(qy[1])
     d.precision = PRECISIONS[precision]
     d.allow_unstable = int(bool(allow_unstable))
+    return d
+
+
+def make_hybrid_desc(ny, layer, kn, u_w=(-0.01, 0.01), n_half=4, n_full=None, qx=("full", 3),
+                     cfl=0.9) -> HybridDesc:
+    kinds = {"half": HALF, "full": FULL}
+    d = HybridDesc()
+    d.ny, d.layer = int(ny), int(layer)
+    d.kn = float(kn)
+    d.u_bottom, d.u_top = float(u_w[0]), float(u_w[1])
+    d.cfl = float(cfl)
+    d.qx_kind, d.qx_n = kinds[qx[0]], int(qx[1])
+    d.n_half = int(n_half)
+    d.n_full = int(n_half if n_full is None else n_full)
     return d
 
 

@@ -279,3 +279,47 @@ struct fdlb_problem {
     std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
     ~fdlb_problem();
 };
+
+// ---- hybrid half-range / full-range channel (hybrid.hip, hybrid.cpp) ---------------------
+namespace fdlb {
+
+// One channel of a hybrid batch as the kernels see it.  Its table (doubles, at tab_off) holds
+// x nodes, x weights, layer y nodes, layer y weights, layer Courant numbers, bulk y nodes, bulk
+// y weights, bulk Courant numbers, the layer->bulk map [nf][nh] and the bulk->layer map
+// [nh][nf], in that order.
+struct HybChan {
+    int32_t ny, layer, nx, nh, nf, qh, qf, active;  // nh, nf: y nodes of the layer / bulk sets
+    int64_t state_off;   // doubles into the state arena
+    int64_t tab_off;     // doubles into the table
+    int64_t hist_off;    // doubles into the residual ring
+    int32_t ntab, pad;
+    double omega;        // dt / Kn
+    double e_inv;        // 1 / sum_{xi_y > 0} xi_y w over the layer set (wall density per arriving flux)
+    double u_bottom, u_top;
+};
+
+// Per-channel control block, written by the march kernel.
+struct HybCtl {
+    int64_t steps;        // steps taken since seeding
+    int64_t first_below;  // step count at which the residual first fell below tol, or -1
+    double residual;      // residual of the last step
+    int32_t status;       // 0 marching, 1 converged, 2 non-finite residual
+    int32_t pad;
+};
+
+constexpr int HYB_THREADS = 256;
+constexpr int HYB_RING = 1024;   // residuals kept per channel (the most recent ones)
+
+// LDS bytes a channel's march needs.
+size_t hybrid_lds_bytes(const HybChan& c);
+
+// Launchers (hybrid.hip); asynchronous on `stream`.
+void launch_hybrid_march(const HybChan* d_chans, int n, const double* d_tab, double* d_state, HybCtl* d_ctl,
+                         double* d_ring, int64_t nsteps, double tol, int solve, size_t lds, hipStream_t stream);
+void launch_hybrid_seed(const HybChan* d_chans, int ch, int ny, const double* d_tab, double* d_state,
+                        const double* d_fields, hipStream_t stream);
+void launch_hybrid_post(const HybChan* d_chans, int ch, const double* d_tab, const double* d_state,
+                        double* d_out, size_t lds, hipStream_t stream);
+void hybrid_allow_lds(size_t bytes);
+
+}  // namespace fdlb

@@ -1,0 +1,473 @@
+// Hybrid half-range / full-range channel: one workgroup per channel, the whole state resident
+// in LDS for a launch.
+//
+// A channel is a 1-D column of ny cells between two plates (x periodic with one cell, so only
+// y transport acts).  The first and last `layer` cells use the x rule times a half-range y
+// rule (the paper's method, where the Knudsen layers live); the cells between use the x rule
+// times a full-range y rule, the cheaper set that the paper's closing remarks propose for the
+// bulk.  Per step, each thread owns cells j = tid, tid + 256, ...:
+//   relax   g = f + omega (w (rho + xi . j) - f) in place, with the moments carried from the
+//           previous step (Eqs. 1, 5-7); a wall cell also forms the emission of its plate
+//           (Eq. 8) from the arriving flux of its own relaxed populations (Eq. 9)
+//   barrier
+//   move    donor cell in y into the other LDS buffer; an upwind cell of the other zone is
+//           read through the interface map (a small matrix over that cell's y nodes, for
+//           each x node), formed on the fly by the thread that needs it
+//   moments of the new state for the next relaxation, and the residual terms
+//   barrier (the residual: wave sums, then every thread adds the wave partials in order)
+// Two barriers per step and no global memory traffic inside the loop: a small channel's step
+// costs a few microseconds of one CU instead of a kernel launch, and a batch of channels (a Kn
+// sweep) fills the chip with one workgroup each.
+#include "fdlb_internal.h"
+
+namespace fdlb {
+namespace {
+
+constexpr int NWAVES = HYB_THREADS / 64;
+
+struct HybView {
+    int ny, L, nl, nb, nx, nh, nf, qh, qf;
+    const double *xx, *wx, *yh, *wh, *nuh, *yf, *wf, *nuf, *A, *B;
+};
+
+__device__ inline HybView hyb_view(const HybChan& C, const double* tb) {
+    HybView v;
+    v.ny = C.ny;
+    v.L = C.layer;
+    v.nl = 2 * C.layer;
+    v.nb = C.ny - 2 * C.layer;
+    v.nx = C.nx;
+    v.nh = C.nh;
+    v.nf = C.nf;
+    v.qh = C.qh;
+    v.qf = C.qf;
+    v.xx = tb;
+    v.wx = v.xx + v.nx;
+    v.yh = v.wx + v.nx;
+    v.wh = v.yh + v.nh;
+    v.nuh = v.wh + v.nh;
+    v.yf = v.nuh + v.nh;
+    v.wf = v.yf + v.nf;
+    v.nuf = v.wf + v.nf;
+    v.A = v.nuf + v.nf;
+    v.B = v.A + v.nf * v.nh;
+    return v;
+}
+
+__device__ inline bool in_layer(const HybView& v, int j) { return j < v.L || j >= v.ny - v.L; }
+// index of a layer cell among the layer cells (bottom layer, then top layer)
+__device__ inline int lcell(const HybView& v, int j) { return j < v.L ? j : j - v.nb; }
+// LDS index of layer velocity alpha (= a nx + i) in layer cell j, of bulk velocity kappa in bulk cell j
+__device__ inline int lidx(const HybView& v, int alpha, int j) { return alpha * v.nl + lcell(v, j); }
+__device__ inline int bidx(const HybView& v, int kappa, int j) { return v.nl * v.qh + kappa * v.nb + (j - v.L); }
+
+__device__ inline void cell_moments(const HybView& v, const double* f, int j, double& r, double& jx, double& jy) {
+    r = 0.0;
+    jx = 0.0;
+    jy = 0.0;
+    if (in_layer(v, j)) {
+        for (int a = 0; a < v.nh; ++a) {
+            double s = 0.0, sx = 0.0;
+            for (int i = 0; i < v.nx; ++i) {
+                const double p = f[lidx(v, a * v.nx + i, j)];
+                s += p;
+                sx += v.xx[i] * p;
+            }
+            r += s;
+            jx += sx;
+            jy += v.yh[a] * s;
+        }
+    } else {
+        for (int k = 0; k < v.nf; ++k) {
+            double s = 0.0, sx = 0.0;
+            for (int i = 0; i < v.nx; ++i) {
+                const double p = f[bidx(v, k * v.nx + i, j)];
+                s += p;
+                sx += v.xx[i] * p;
+            }
+            r += s;
+            jx += sx;
+            jy += v.yf[k] * s;
+        }
+    }
+}
+
+// Relax cell j in place; a wall cell also writes its plate's emission into ghost[wall][alpha].
+__device__ inline void cell_relax(const HybView& v, double* f, int j, double r, double jx, double jy,
+                                  const HybChan& C, double* ghost) {
+    const double om = C.omega;
+    if (in_layer(v, j)) {
+        double flux_down = 0.0, flux_up = 0.0;
+        for (int a = 0; a < v.nh; ++a) {
+            const double y = v.yh[a];
+            for (int i = 0; i < v.nx; ++i) {
+                const int idx = lidx(v, a * v.nx + i, j);
+                const double W = v.wh[a] * v.wx[i];
+                const double feq = W * (r + v.xx[i] * jx + y * jy);
+                const double g = f[idx] + om * (feq - f[idx]);
+                f[idx] = g;
+                if (y < 0.0) flux_down -= y * g;
+                else flux_up += y * g;
+            }
+        }
+        if (j == 0) {  // bottom plate: arriving xi_y < 0, emission into xi_y > 0
+            const double rho_w = flux_down * C.e_inv;
+            for (int a = 0; a < v.nh; ++a)
+                if (v.yh[a] > 0.0)
+                    for (int i = 0; i < v.nx; ++i)
+                        ghost[a * v.nx + i] = v.wh[a] * v.wx[i] * rho_w * (1.0 + v.xx[i] * C.u_bottom);
+        }
+        if (j == v.ny - 1) {  // top plate: arriving xi_y > 0, emission into xi_y < 0
+            const double rho_w = flux_up * C.e_inv;
+            for (int a = 0; a < v.nh; ++a)
+                if (v.yh[a] < 0.0)
+                    for (int i = 0; i < v.nx; ++i)
+                        ghost[v.qh + a * v.nx + i] = v.wh[a] * v.wx[i] * rho_w * (1.0 + v.xx[i] * C.u_top);
+        }
+    } else {
+        for (int k = 0; k < v.nf; ++k) {
+            const double y = v.yf[k];
+            for (int i = 0; i < v.nx; ++i) {
+                const int idx = bidx(v, k * v.nx + i, j);
+                const double W = v.wf[k] * v.wx[i];
+                const double feq = W * (r + v.xx[i] * jx + y * jy);
+                f[idx] = f[idx] + om * (feq - f[idx]);
+            }
+        }
+    }
+}
+
+// Donor-cell transport of cell j from the relaxed state g into fn.
+__device__ inline void cell_transport(const HybView& v, const double* g, double* fn, int j, const double* ghost) {
+    if (in_layer(v, j)) {
+        for (int a = 0; a < v.nh; ++a) {
+            const double y = v.yh[a];
+            const double nu = v.nuh[a];
+            const int up = y > 0.0 ? j - 1 : j + 1;  // half-range nodes are never 0
+            const double* brow = v.B + a * v.nf;
+            for (int i = 0; i < v.nx; ++i) {
+                const int idx = lidx(v, a * v.nx + i, j);
+                const double gs = g[idx];
+                double gu;
+                if (up < 0) {
+                    gu = ghost[a * v.nx + i];
+                } else if (up >= v.ny) {
+                    gu = ghost[v.qh + a * v.nx + i];
+                } else if (in_layer(v, up)) {
+                    gu = g[lidx(v, a * v.nx + i, up)];
+                } else {  // a bulk donor seen on the layer nodes
+                    gu = 0.0;
+                    for (int k = 0; k < v.nf; ++k) gu += brow[k] * g[bidx(v, k * v.nx + i, up)];
+                }
+                fn[idx] = gs - nu * (gs - gu);
+            }
+        }
+    } else {
+        for (int k = 0; k < v.nf; ++k) {
+            const double y = v.yf[k];
+            const double nu = v.nuf[k];
+            const double* arow = v.A + k * v.nh;
+            for (int i = 0; i < v.nx; ++i) {
+                const int idx = bidx(v, k * v.nx + i, j);
+                const double gs = g[idx];
+                if (y == 0.0) {
+                    fn[idx] = gs;
+                    continue;
+                }
+                const int up = y > 0.0 ? j - 1 : j + 1;  // inside the channel: layer >= 1
+                double gu;
+                if (!in_layer(v, up)) {
+                    gu = g[bidx(v, k * v.nx + i, up)];
+                } else {  // a layer donor seen on the bulk nodes
+                    gu = 0.0;
+                    for (int a = 0; a < v.nh; ++a) gu += arow[a] * g[lidx(v, a * v.nx + i, up)];
+                }
+                fn[idx] = gs - nu * (gs - gu);
+            }
+        }
+    }
+}
+
+__device__ inline double wave_sum(double x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// LDS carve shared by the march and post kernels (doubles).
+struct Carve {
+    double *tb, *fa, *fb, *mom, *uo, *ghost, *red;
+};
+
+__device__ inline Carve carve(double* lds, const HybChan& C, int S) {
+    Carve c;
+    c.tb = lds;
+    c.fa = c.tb + C.ntab;
+    c.fb = c.fa + S;
+    c.mom = c.fb + S;
+    c.uo = c.mom + 3 * C.ny;
+    c.ghost = c.uo + 2 * C.ny;
+    c.red = c.ghost + 2 * C.qh;
+    return c;
+}
+
+__device__ inline int state_doubles(const HybChan& C) {
+    return 2 * C.layer * C.qh + (C.ny - 2 * C.layer) * C.qf;
+}
+
+// March every active channel: at most nsteps steps; with solve, stop at the first step whose
+// residual is below tol or not finite.  Block-uniform control throughout: every thread
+// computes the same residual from the same wave partials, so all leave the loop together.
+__global__ void __launch_bounds__(HYB_THREADS) hybrid_march_kernel(const HybChan* __restrict__ chans,
+                                                                   const double* __restrict__ tab,
+                                                                   double* __restrict__ state,
+                                                                   HybCtl* __restrict__ ctl,
+                                                                   double* __restrict__ ring, int64_t nsteps,
+                                                                   double tol, int solve) {
+    extern __shared__ double lds[];
+    const HybChan C = chans[blockIdx.x];
+    if (!C.active) return;
+    HybCtl ct = ctl[blockIdx.x];
+    if (solve && ct.status != 0) return;
+    const int tid = threadIdx.x;
+    const int S = state_doubles(C);
+    const Carve m = carve(lds, C, S);
+    for (int i = tid; i < C.ntab; i += HYB_THREADS) m.tb[i] = tab[C.tab_off + i];
+    double* gs = state + C.state_off;
+    for (int i = tid; i < S; i += HYB_THREADS) m.fa[i] = gs[i];
+    __syncthreads();
+    const HybView v = hyb_view(C, m.tb);
+    const int ny = v.ny;
+    for (int j = tid; j < ny; j += HYB_THREADS) {
+        double r, jx, jy;
+        cell_moments(v, m.fa, j, r, jx, jy);
+        m.mom[j] = r;
+        m.mom[ny + j] = jx;
+        m.mom[2 * ny + j] = jy;
+        m.uo[j] = jx / r;
+        m.uo[ny + j] = jy / r;
+    }
+    double* cur = m.fa;
+    double* nxt = m.fb;
+    int64_t taken = 0;
+    int stop = 0;
+    double R = ct.residual;
+    while (taken < nsteps) {
+        for (int j = tid; j < ny; j += HYB_THREADS)
+            cell_relax(v, cur, j, m.mom[j], m.mom[ny + j], m.mom[2 * ny + j], C, m.ghost);
+        __syncthreads();
+        double du = 0.0, uu = 0.0;
+        for (int j = tid; j < ny; j += HYB_THREADS) {
+            cell_transport(v, cur, nxt, j, m.ghost);
+            double r, jx, jy;
+            cell_moments(v, nxt, j, r, jx, jy);
+            m.mom[j] = r;
+            m.mom[ny + j] = jx;
+            m.mom[2 * ny + j] = jy;
+            const double ux = jx / r, uy = jy / r;
+            const double dx = ux - m.uo[j], dy = uy - m.uo[ny + j];
+            du += dx * dx + dy * dy;
+            uu += ux * ux + uy * uy;
+            m.uo[j] = ux;
+            m.uo[ny + j] = uy;
+        }
+        du = wave_sum(du);
+        uu = wave_sum(uu);
+        if ((tid & 63) == 0) {
+            m.red[2 * (tid >> 6)] = du;
+            m.red[2 * (tid >> 6) + 1] = uu;
+        }
+        __syncthreads();
+        double sdu = 0.0, suu = 0.0;
+        for (int w = 0; w < NWAVES; ++w) {
+            sdu += m.red[2 * w];
+            suu += m.red[2 * w + 1];
+        }
+        R = suu > 0.0 ? sqrt(sdu) / sqrt(suu) : (sdu == 0.0 ? 0.0 : INFINITY);
+        ++taken;
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+        if (tid == 0) ring[C.hist_off + (ct.steps + taken - 1) % HYB_RING] = R;
+        if (solve) {
+            if (!isfinite(R)) {
+                stop = 2;
+                break;
+            }
+            if (R < tol) {
+                stop = 1;
+                break;
+            }
+        }
+    }
+    // every write to `cur` happened before the last barrier (or the load's)
+    for (int i = tid; i < S; i += HYB_THREADS) gs[i] = cur[i];
+    if (tid == 0) {
+        ct.steps += taken;
+        if (taken > 0) ct.residual = R;
+        if (solve) {
+            ct.status = stop;
+            if (stop == 1 && ct.first_below < 0) ct.first_below = ct.steps;
+        } else {
+            ct.status = 0;
+            ct.first_below = -1;
+        }
+        ctl[blockIdx.x] = ct;
+    }
+}
+
+// f = w (rho + xi_x rho u_x + xi_y rho u_y) on each cell's own set, from fields [3][ny].
+__global__ void __launch_bounds__(HYB_THREADS) hybrid_seed_kernel(const HybChan* __restrict__ chans, int ch,
+                                                                  const double* __restrict__ tab,
+                                                                  double* __restrict__ state,
+                                                                  const double* __restrict__ fields) {
+    const HybChan C = chans[ch];
+    const HybView v = hyb_view(C, tab + C.tab_off);
+    double* f = state + C.state_off;
+    for (int j = threadIdx.x; j < v.ny; j += HYB_THREADS) {
+        const double r = fields[j], jx = r * fields[v.ny + j], jy = r * fields[2 * v.ny + j];
+        if (in_layer(v, j)) {
+            for (int a = 0; a < v.nh; ++a)
+                for (int i = 0; i < v.nx; ++i)
+                    f[lidx(v, a * v.nx + i, j)] = v.wh[a] * v.wx[i] * (r + v.xx[i] * jx + v.yh[a] * jy);
+        } else {
+            for (int k = 0; k < v.nf; ++k)
+                for (int i = 0; i < v.nx; ++i)
+                    f[bidx(v, k * v.nx + i, j)] = v.wf[k] * v.wx[i] * (r + v.xx[i] * jx + v.yf[k] * jy);
+        }
+    }
+}
+
+// Outputs of one channel into out: rho, u_x, u_y, p_xy per cell ([4][ny]) and the eight face
+// values (bottom plate u_x, p_xy; top plate u_x, p_xy; lower interface flux from the layer cell,
+// from the bulk cell; upper interface flux from the bulk cell, from the layer cell).
+__global__ void __launch_bounds__(HYB_THREADS) hybrid_post_kernel(const HybChan* __restrict__ chans, int ch,
+                                                                  const double* __restrict__ tab,
+                                                                  const double* __restrict__ state,
+                                                                  double* __restrict__ out) {
+    extern __shared__ double lds[];
+    const HybChan C = chans[ch];
+    const int tid = threadIdx.x;
+    const int S = state_doubles(C);
+    const Carve m = carve(lds, C, S);
+    for (int i = tid; i < C.ntab; i += HYB_THREADS) m.tb[i] = tab[C.tab_off + i];
+    const double* gs = state + C.state_off;
+    for (int i = tid; i < S; i += HYB_THREADS) m.fa[i] = gs[i];
+    __syncthreads();
+    const HybView v = hyb_view(C, m.tb);
+    const int ny = v.ny;
+    for (int j = tid; j < ny; j += HYB_THREADS) {
+        double r, jx, jy;
+        cell_moments(v, m.fa, j, r, jx, jy);
+        out[j] = r;
+        out[ny + j] = jx / r;
+        out[2 * ny + j] = jy / r;
+        cell_relax(v, m.fa, j, r, jx, jy, C, m.ghost);
+        double p = 0.0;
+        if (in_layer(v, j)) {
+            for (int a = 0; a < v.nh; ++a)
+                for (int i = 0; i < v.nx; ++i) p += v.xx[i] * v.yh[a] * m.fa[lidx(v, a * v.nx + i, j)];
+        } else {
+            for (int k = 0; k < v.nf; ++k)
+                for (int i = 0; i < v.nx; ++i) p += v.xx[i] * v.yf[k] * m.fa[bidx(v, k * v.nx + i, j)];
+        }
+        out[3 * ny + j] = p;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double* face = out + 4 * ny;
+    const double* g = m.fa;
+    for (int wall = 0; wall < 2; ++wall) {
+        const int j = wall == 0 ? 0 : ny - 1;
+        double r = 0.0, jx = 0.0, p = 0.0;
+        for (int a = 0; a < v.nh; ++a) {
+            const double y = v.yh[a];
+            const bool arriving = wall == 0 ? y < 0.0 : y > 0.0;
+            for (int i = 0; i < v.nx; ++i) {
+                const double val = arriving ? g[lidx(v, a * v.nx + i, j)] : m.ghost[wall * v.qh + a * v.nx + i];
+                r += val;
+                jx += v.xx[i] * val;
+                p += v.xx[i] * y * val;
+            }
+        }
+        face[2 * wall] = jx / r;
+        face[2 * wall + 1] = p;
+    }
+    if (v.nb == 0) {
+        for (int q = 4; q < 8; ++q) face[q] = NAN;
+        return;
+    }
+    // y-flux of x-momentum through the face between cells lo and lo + 1 as the update of the
+    // cell on `side` (0: lo, 1: lo + 1) transports it
+    for (int q = 0; q < 4; ++q) {
+        const int lo = q < 2 ? v.L - 1 : ny - v.L - 1;
+        const int side = (q == 0 || q == 2) ? 0 : 1;
+        const int own = lo + side;
+        double flux = 0.0;
+        if (in_layer(v, own)) {
+            for (int a = 0; a < v.nh; ++a) {
+                const double y = v.yh[a];
+                const int src = y > 0.0 ? lo : lo + 1;
+                for (int i = 0; i < v.nx; ++i) {
+                    double val;
+                    if (in_layer(v, src)) {
+                        val = g[lidx(v, a * v.nx + i, src)];
+                    } else {
+                        val = 0.0;
+                        for (int k = 0; k < v.nf; ++k) val += v.B[a * v.nf + k] * g[bidx(v, k * v.nx + i, src)];
+                    }
+                    flux += v.xx[i] * y * val;
+                }
+            }
+        } else {
+            for (int k = 0; k < v.nf; ++k) {
+                const double y = v.yf[k];
+                if (y == 0.0) continue;
+                const int src = y > 0.0 ? lo : lo + 1;
+                for (int i = 0; i < v.nx; ++i) {
+                    double val;
+                    if (!in_layer(v, src)) {
+                        val = g[bidx(v, k * v.nx + i, src)];
+                    } else {
+                        val = 0.0;
+                        for (int a = 0; a < v.nh; ++a) val += v.A[k * v.nh + a] * g[lidx(v, a * v.nx + i, src)];
+                    }
+                    flux += v.xx[i] * y * val;
+                }
+            }
+        }
+        face[4 + q] = flux;
+    }
+}
+
+}  // namespace
+
+void hybrid_allow_lds(size_t bytes) {
+    FDLB_HIP(hipFuncSetAttribute((const void*)hybrid_march_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)bytes));
+    FDLB_HIP(hipFuncSetAttribute((const void*)hybrid_post_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)bytes));
+}
+
+void launch_hybrid_march(const HybChan* d_chans, int n, const double* d_tab, double* d_state, HybCtl* d_ctl,
+                         double* d_ring, int64_t nsteps, double tol, int solve, size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL(hybrid_march_kernel, dim3(n), dim3(HYB_THREADS), lds, stream, d_chans, d_tab, d_state, d_ctl,
+                       d_ring, nsteps, tol, solve);
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_hybrid_seed(const HybChan* d_chans, int ch, int ny, const double* d_tab, double* d_state,
+                        const double* d_fields, hipStream_t stream) {
+    (void)ny;
+    hipLaunchKernelGGL(hybrid_seed_kernel, dim3(1), dim3(HYB_THREADS), 0, stream, d_chans, ch, d_tab, d_state,
+                       d_fields);
+    FDLB_HIP(hipGetLastError());
+}
+
+void launch_hybrid_post(const HybChan* d_chans, int ch, const double* d_tab, const double* d_state, double* d_out,
+                        size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL(hybrid_post_kernel, dim3(1), dim3(HYB_THREADS), lds, stream, d_chans, ch, d_tab, d_state,
+                       d_out);
+    FDLB_HIP(hipGetLastError());
+}
+
+}  // namespace fdlb

@@ -400,3 +400,49 @@ def test_pseudo_time_stretches_follow_their_definition(F):
         s = p.pseudo_weights()
         assert np.all(s * (p.omega + 2 * nu * (1 - p.omega)) <= 2 * case.cfl * (1 + 1e-6) + 1e-12)
         assert np.all(s * p.omega <= 1 + 1e-6)
+
+
+def _hybrid_create(F, descs):
+    L = F._lib
+    arr = (L.HybridDesc * len(descs))(*descs)
+    h = C.c_void_p()
+    code = L.lib.fdlb_hybrid_create(arr, len(descs), C.byref(h))
+    return code, h
+
+
+def test_hybrid_layout_time_step_and_errors(F):
+    """Host side of the hybrid channel: time step and omega equal the oracle's to the last bit,
+    the state holds 2 layer Q_layer + (ny - 2 layer) Q_bulk doubles, bad descriptions are
+    refused, and calls before binding are state errors."""
+    from oracle.hybrid import HybridChannel
+    L = F._lib
+    cases = [(200, 40, 0.1, 4, 4, ("full", 3)), (37, 1, 0.05, 4, 3, ("full", 3)), (30, 15, 0.2, 3, 3, ("half", 2)),
+             (64, 12, math.inf, 2, 7, ("full", 2))]
+    descs = [L.make_hybrid_desc(ny, lay, kn, (-0.01, 0.01), nh, nf, qx) for ny, lay, kn, nh, nf, qx in cases]
+    code, h = _hybrid_create(F, descs)
+    assert code == 0
+    total = 0
+    for i, (ny, lay, kn, nh, nf, qx) in enumerate(cases):
+        ql, qb, sd = C.c_int32(), C.c_int32(), C.c_int64()
+        dt, om = C.c_double(), C.c_double()
+        assert L.lib.fdlb_hybrid_info(h, i, C.byref(ql), C.byref(qb), C.byref(sd), C.byref(dt), C.byref(om)) == 0
+        o = HybridChannel(ny, lay, kn, (-0.01, 0.01), n_half=nh, n_full=nf, qx=qx)
+        nx = len(o.xx)
+        assert (ql.value, qb.value) == (nx * 2 * nh, nx * nf)
+        assert sd.value == 2 * lay * ql.value + (ny - 2 * lay) * qb.value == o.pack(o.equilibrium()).size
+        assert dt.value == o.dt and om.value == o.omega
+        total += (sd.value * 8 + 255) // 256 * 256
+    assert L.lib.fdlb_hybrid_state_bytes(h) == total
+    assert L.lib.fdlb_hybrid_step(h, 1) == L.ESTATE
+    assert L.lib.fdlb_hybrid_info(h, 9, None, None, None, None, None) == L.EINVAL
+    L.lib.fdlb_hybrid_destroy(h)
+    bad = [dict(ny=1, layer=1), dict(ny=20, layer=0), dict(ny=20, layer=11), dict(kn=0.0), dict(n_half=1),
+           dict(n_half=9), dict(n_full=1), dict(n_full=17), dict(qx=("full", 1)), dict(qx=("half", 1))]
+    base = dict(ny=20, layer=4, kn=0.1, u_w=(-0.01, 0.01), n_half=2, n_full=2, qx=("full", 3))
+    for b in bad:
+        code, _ = _hybrid_create(F, [L.make_hybrid_desc(**dict(base, **b))])
+        assert code == L.EINVAL, b
+    for b in (dict(cfl=1.5), dict(kn=1e-4)):
+        code, _ = _hybrid_create(F, [L.make_hybrid_desc(**dict(base, **b))])
+        assert code == L.EUNSTABLE, b
+    assert L.lib.fdlb_hybrid_create(None, 1, C.byref(C.c_void_p())) == L.EINVAL
