@@ -213,6 +213,59 @@ def kn_sweeps():
     return out
 
 
+def hybrid_channel(F):
+    """The half-range / full-range hybrid (one workgroup per channel, state in LDS for a whole
+    launch) on the Couette channel of 200 cells, 4 nodes per half in the layers x GH3 in x,
+    Kn 0.1, plates at -+0.01, FP64, to R < 1e-10: with the layers filling the channel (the plain
+    half-range scheme of the 24-velocity Couette workload), and with layers of 40 and 20 cells
+    around a bulk on 4 or 3 full-range nodes (12 or 9 velocities instead of 24).  Then Kn sweeps
+    of 1,024 channels (Kn log-spaced over [0.01, 10]) solved by one launch each.  Slip and
+    stress are compared with the layers-filling solution of the same Kn."""
+    import numpy as np
+    out = {}
+    base = dict(ny=200, kn=0.1, u_w=(-0.01, 0.01), n_half=4, qx=("full", 3))
+    ref = None
+    for name, layer, nf in (("layers_fill", 100, 4), ("layer40_bulk4", 40, 4), ("layer40_bulk3", 40, 3),
+                            ("layer20_bulk4", 20, 4)):
+        h = F.Hybrid([dict(base, layer=layer, n_full=nf)])
+        h.init_all()
+        h.solve(1e-10, 50)  # first launch (module load)
+        h.init_all()
+        code, reps = h.solve(1e-10, 400000)
+        r = reps[0]
+        f = h.faces(0)
+        slip, pxy = 1.0 - f[2] / 0.01, f[3]
+        if ref is None:
+            ref = (slip, pxy)
+        out[name] = {"wall_s": round(r["wall_s"], 5), "steps": r["steps"],
+                     "us_per_step": round(r["wall_s"] / max(r["steps"], 1) * 1e6, 3),
+                     "updates_per_step": h.info[0]["state_doubles"], "status": r["status"],
+                     "slip": round(slip, 8), "pxy": pxy,
+                     "slip_rel_vs_layers_fill": abs(slip / ref[0] - 1), "pxy_rel_vs_layers_fill": abs(pxy / ref[1] - 1)}
+        log(f"  {name}: {r['steps']} steps in {r['wall_s'] * 1e3:.2f} ms "
+            f"({out[name]['us_per_step']} us/step, {out[name]['updates_per_step']} updates/step), "
+            f"slip {slip:.6f}, p_xy rel. to layers-fill {out[name]['pxy_rel_vs_layers_fill']:.1e}")
+        h.close()
+    kns = np.logspace(-2, 1, 1024)
+    sweep_ref = None
+    for name, layer in (("sweep1024_layers_fill", 100), ("sweep1024_layer40_bulk4", 40)):
+        h = F.Hybrid([dict(base, kn=float(k), layer=layer, n_full=4) for k in kns])
+        h.init_all()
+        code, reps = h.solve(1e-10, 1_000_000)
+        wall = reps[0]["wall_s"]
+        upd = sum(h.info[i]["state_doubles"] * reps[i]["steps"] for i in range(h.n))
+        pxy = np.array([h.faces(i)[3] for i in range(h.n)])
+        if sweep_ref is None:
+            sweep_ref = pxy
+        out[name] = {"channels": h.n, "wall_s": round(wall, 4), "converged": int(sum(r["status"] == 0 for r in reps)),
+                     "steps_max": int(max(r["steps"] for r in reps)), "updates": int(upd),
+                     "updates_per_s": upd / wall, "pxy_rel_vs_layers_fill_max": float(np.abs(pxy / sweep_ref - 1).max())}
+        log(f"  {name}: {h.n} channels in {wall:.3f} s ({upd / wall:.3e} updates/s), "
+            f"max steps {out[name]['steps_max']}, p_xy rel. max {out[name]['pxy_rel_vs_layers_fill_max']:.1e}")
+        h.close()
+    return out
+
+
 def copy_ceiling(F, torch, nbytes=4 << 30, reps=10):
     """Achievable streaming bandwidth on this device: the library's probes over 4 GiB, copies with
     each mix of plain / non-temporal loads and stores (the step kernels load plainly and store
@@ -318,6 +371,7 @@ def main():
                     help="skip training the warm-start network on 2000 solver-generated 64^2 cavities, the warm "
                          "versus uniform starts on held-out Kn at 128^2 and 256^2, and the warm-started sweep")
     ap.add_argument("--no-kn-sweeps", action="store_true", help="skip the Couette and cavity Kn sweeps")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid half/full-range channel runs")
     ap.add_argument("--heldout", type=int, default=16)
     ap.add_argument("--tune-cache", default=None,
                     help="file caching autotuned tiles (default: the library's user cache file; '' disables)")
@@ -458,6 +512,12 @@ def main():
         r = part("kn_sweeps", kn_sweeps)
         if r is not None:
             extra["kn_sweeps"] = r
+
+    if not args.no_hybrid:
+        log("[bench] hybrid half-range / full-range channel:")
+        r = part("hybrid_channel", lambda: hybrid_channel(F))
+        if r is not None:
+            extra["hybrid_channel"] = r
 
     cpu = None
     if not args.no_cpu_baseline:

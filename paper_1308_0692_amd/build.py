@@ -3,7 +3,8 @@
 Every HIP source is compiled with packed-FP32 instructions disabled
 (-Xclang -target-feature -Xclang -packed-fp32-ops); objects go to _build/.  The compiler's
 resource report for every kernel (registers, scratch, waves per SIMD) is kept in
-_build/kernel_resources.json, and the build fails if a step kernel uses scratch memory: a
+_build/kernel_resources.json, and the build fails if a step kernel (or the hybrid channel's
+march kernel) uses scratch memory: a
 spilled or stack-held value in the velocity loop is a performance bug that no test would see.
 """
 from __future__ import annotations
@@ -81,7 +82,8 @@ def build(jobs: int = 8) -> str:
         res.update(r)
     with open(os.path.join(BUILD, "kernel_resources.json"), "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)
-    spilled = sorted(k for k, v in res.items() if "step_kernel" in k and v.get("scratch", 0) > 0)
+    spilled = sorted(k for k, v in res.items()
+                     if ("step_kernel" in k or "hybrid_march" in k) and v.get("scratch", 0) > 0)
     if spilled:
         raise RuntimeError("step kernels use scratch memory (spills or a stack copy): " + ", ".join(spilled))
     tmp = LIB + ".tmp"

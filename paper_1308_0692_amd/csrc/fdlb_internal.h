@@ -296,6 +296,10 @@ struct HybChan {
     double omega;        // dt / Kn
     double e_inv;        // 1 / sum_{xi_y > 0} xi_y w over the layer set (wall density per arriving flux)
     double u_bottom, u_top;
+    // per plate (0 bottom, 1 top), sums over its arriving half of the layer set:
+    // A = sum |xi_y| w, Bx = sum |xi_y| xi_x w, By = sum |xi_y| xi_y w (the arriving flux of an
+    // equilibrium w (rho + xi . j) is rho A + j_x Bx + j_y By)
+    double wA[2], wBx[2], wBy[2];
 };
 
 // Per-channel control block, written by the march kernel.
@@ -307,7 +311,8 @@ struct HybCtl {
     int32_t pad;
 };
 
-constexpr int HYB_THREADS = 256;
+constexpr int HYB_THREADS = 256;         // seeding and output kernels
+constexpr int HYB_MARCH_THREADS = 1024;  // the march kernel: one thread per population
 constexpr int HYB_RING = 1024;   // residuals kept per channel (the most recent ones)
 
 // LDS bytes a channel's march needs.

@@ -149,6 +149,20 @@ void create(fdlb_hybrid& h, const fdlb_hybrid_desc* descs, int n) {
         C.e_inv = 1.0 / (leave * sx);
         C.u_bottom = d.u_bottom;
         C.u_top = d.u_top;
+        double sxx = 0;
+        for (int i = 0; i < nx; ++i) sxx += xx[i] * wx[i];
+        for (int wall = 0; wall < 2; ++wall) {
+            double A = 0, By = 0;
+            for (int a = 0; a < nh; ++a) {
+                const bool arriving = wall == 0 ? yh[a] < 0 : yh[a] > 0;
+                if (!arriving) continue;
+                A += std::fabs(yh[a]) * wh[a];
+                By += std::fabs(yh[a]) * yh[a] * wh[a];
+            }
+            C.wA[wall] = A * sx;
+            C.wBx[wall] = A * sxx;
+            C.wBy[wall] = By * sx;
+        }
         const int64_t S = 2 * (int64_t)d.layer * C.qh + (int64_t)(d.ny - 2 * d.layer) * C.qf;
         C.state_off = (int64_t)(state_total / sizeof(double));
         state_total += align256((size_t)S * sizeof(double));
@@ -364,7 +378,8 @@ void post(fdlb_hybrid& h, int i, std::vector<double>& out) {
 
 size_t hybrid_lds_bytes(const HybChan& c) {
     const size_t S = 2 * (size_t)c.layer * c.qh + (size_t)(c.ny - 2 * c.layer) * c.qf;
-    return sizeof(double) * ((size_t)c.ntab + 2 * S + 5 * (size_t)c.ny + 2 * (size_t)c.qh + 2 * (HYB_THREADS / 64));
+    return sizeof(double) * ((size_t)c.ntab + 2 * S + 5 * (size_t)c.ny + 2 * (size_t)c.qh + 4 * (HYB_MARCH_THREADS / 64) + 2 +
+                             2 * ((size_t)c.qh + c.qf));
 }
 
 int guard_call(const std::function<int()>& f);

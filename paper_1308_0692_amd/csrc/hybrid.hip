@@ -5,25 +5,18 @@
 // y transport acts).  The first and last `layer` cells use the x rule times a half-range y
 // rule (the paper's method, where the Knudsen layers live); the cells between use the x rule
 // times a full-range y rule, the cheaper set that the paper's closing remarks propose for the
-// bulk.  Per step, each thread owns cells j = tid, tid + 256, ...:
-//   relax   g = f + omega (w (rho + xi . j) - f) in place, with the moments carried from the
-//           previous step (Eqs. 1, 5-7); a wall cell also forms the emission of its plate
-//           (Eq. 8) from the arriving flux of its own relaxed populations (Eq. 9)
-//   barrier
-//   move    donor cell in y into the other LDS buffer; an upwind cell of the other zone is
-//           read through the interface map (a small matrix over that cell's y nodes, for
-//           each x node), formed on the fly by the thread that needs it
-//   moments of the new state for the next relaxation, and the residual terms
-//   barrier (the residual: wave sums, then every thread adds the wave partials in order)
-// Two barriers per step and no global memory traffic inside the loop: a small channel's step
-// costs a few microseconds of one CU instead of a kernel launch, and a batch of channels (a Kn
-// sweep) fills the chip with one workgroup each.
+// bulk.  The march kernel keeps the populations and each cell's moments in LDS; a step is one
+// pass with a thread per population (relax the population and its donor from the moments of
+// their cells, transport by the donor cell, the donor seen through the interface map when it
+// lies in the other zone, the plate emission at a wall) and one pass with a thread per cell
+// (moments of the new state, the residual terms, the next emission density), two barriers in
+// all and no global memory traffic inside the loop.  A small channel's step is a few
+// microseconds of one CU instead of a kernel launch, and a batch of channels (a Kn sweep) fills
+// the chip with one workgroup each.
 #include "fdlb_internal.h"
 
 namespace fdlb {
 namespace {
-
-constexpr int NWAVES = HYB_THREADS / 64;
 
 struct HybView {
     int ny, L, nl, nb, nx, nh, nf, qh, qf;
@@ -137,57 +130,6 @@ __device__ inline void cell_relax(const HybView& v, double* f, int j, double r, 
     }
 }
 
-// Donor-cell transport of cell j from the relaxed state g into fn.
-__device__ inline void cell_transport(const HybView& v, const double* g, double* fn, int j, const double* ghost) {
-    if (in_layer(v, j)) {
-        for (int a = 0; a < v.nh; ++a) {
-            const double y = v.yh[a];
-            const double nu = v.nuh[a];
-            const int up = y > 0.0 ? j - 1 : j + 1;  // half-range nodes are never 0
-            const double* brow = v.B + a * v.nf;
-            for (int i = 0; i < v.nx; ++i) {
-                const int idx = lidx(v, a * v.nx + i, j);
-                const double gs = g[idx];
-                double gu;
-                if (up < 0) {
-                    gu = ghost[a * v.nx + i];
-                } else if (up >= v.ny) {
-                    gu = ghost[v.qh + a * v.nx + i];
-                } else if (in_layer(v, up)) {
-                    gu = g[lidx(v, a * v.nx + i, up)];
-                } else {  // a bulk donor seen on the layer nodes
-                    gu = 0.0;
-                    for (int k = 0; k < v.nf; ++k) gu += brow[k] * g[bidx(v, k * v.nx + i, up)];
-                }
-                fn[idx] = gs - nu * (gs - gu);
-            }
-        }
-    } else {
-        for (int k = 0; k < v.nf; ++k) {
-            const double y = v.yf[k];
-            const double nu = v.nuf[k];
-            const double* arow = v.A + k * v.nh;
-            for (int i = 0; i < v.nx; ++i) {
-                const int idx = bidx(v, k * v.nx + i, j);
-                const double gs = g[idx];
-                if (y == 0.0) {
-                    fn[idx] = gs;
-                    continue;
-                }
-                const int up = y > 0.0 ? j - 1 : j + 1;  // inside the channel: layer >= 1
-                double gu;
-                if (!in_layer(v, up)) {
-                    gu = g[bidx(v, k * v.nx + i, up)];
-                } else {  // a layer donor seen on the bulk nodes
-                    gu = 0.0;
-                    for (int a = 0; a < v.nh; ++a) gu += arow[a] * g[lidx(v, a * v.nx + i, up)];
-                }
-                fn[idx] = gs - nu * (gs - gu);
-            }
-        }
-    }
-}
-
 __device__ inline double wave_sum(double x) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
@@ -195,7 +137,7 @@ __device__ inline double wave_sum(double x) {
 
 // LDS carve shared by the march and post kernels (doubles).
 struct Carve {
-    double *tb, *fa, *fb, *mom, *uo, *ghost, *red;
+    double *tb, *fa, *fb, *mom, *uo, *ghost, *red, *rw, *ifc;
 };
 
 __device__ inline Carve carve(double* lds, const HybChan& C, int S) {
@@ -207,6 +149,9 @@ __device__ inline Carve carve(double* lds, const HybChan& C, int S) {
     c.uo = c.mom + 3 * C.ny;
     c.ghost = c.uo + 2 * C.ny;
     c.red = c.ghost + 2 * C.qh;
+    c.rw = c.red + 4 * (HYB_MARCH_THREADS / 64);  // two slots of wave partials
+    c.ifc = c.rw + 2;                             // [bulk from layer L-1, layer from bulk L, bulk from
+                                                  //  layer ny-L, layer from bulk ny-L-1]
     return c;
 }
 
@@ -214,15 +159,56 @@ __device__ inline int state_doubles(const HybChan& C) {
     return 2 * C.layer * C.qh + (C.ny - 2 * C.layer) * C.qf;
 }
 
+// The interface cells' populations carried to the other zone's nodes, raw (before relaxation):
+// the maps reproduce the equilibrium exactly, so the map of a relaxed distribution is the
+// relaxation, with the donor cell's moments, of the mapped raw one.  ifc holds, in order, the
+// bulk nodes seen from layer cell L - 1, the layer nodes seen from bulk cell L, the bulk nodes
+// seen from layer cell ny - L and the layer nodes seen from bulk cell ny - L - 1.  Items are
+// taken from `first` by `stride`.
+__device__ inline void interface_pass(const HybView& v, const double* f, double* ifc, int first, int stride) {
+    if (v.nb == 0) return;
+    const int per_side = v.qf + v.qh;
+    for (int w = first; w < 2 * per_side; w += stride) {
+        const int side = w < per_side ? 0 : 1;  // 0: lower interface, 1: upper
+        int r = w - side * per_side;
+        const int lay = side == 0 ? v.L - 1 : v.ny - v.L, blk = side == 0 ? v.L : v.ny - v.L - 1;
+        double acc = 0.0;
+        if (r < v.qf) {  // bulk node (k, i) from the layer cell
+            const int k = r / v.nx, i = r - k * v.nx;
+            const double* arow = v.A + k * v.nh;
+            for (int a = 0; a < v.nh; ++a) acc += arow[a] * f[lidx(v, a * v.nx + i, lay)];
+        } else {         // layer node (a, i) from the bulk cell
+            const int q = r - v.qf;
+            const int a = q / v.nx, i = q - a * v.nx;
+            const double* brow = v.B + a * v.nf;
+            for (int k = 0; k < v.nf; ++k) acc += brow[k] * f[bidx(v, k * v.nx + i, blk)];
+        }
+        ifc[side * per_side + r] = acc;
+    }
+}
+
+// relaxed value of one population from its stored value and its cell's moments (Eqs. 1, 5)
+__device__ inline double relaxed(double f, double W, double xx, double y, double r, double jx, double jy, double om) {
+    return f + om * (W * (r + xx * jx + y * jy) - f);
+}
+
 // March every active channel: at most nsteps steps; with solve, stop at the first step whose
-// residual is below tol or not finite.  Block-uniform control throughout: every thread
-// computes the same residual from the same wave partials, so all leave the loop together.
-__global__ void __launch_bounds__(HYB_THREADS) hybrid_march_kernel(const HybChan* __restrict__ chans,
-                                                                   const double* __restrict__ tab,
-                                                                   double* __restrict__ state,
-                                                                   HybCtl* __restrict__ ctl,
-                                                                   double* __restrict__ ring, int64_t nsteps,
-                                                                   double tol, int solve) {
+// residual is below tol or not finite.  Per step:
+//   move     one thread per population: the relaxed value of the population and of its donor
+//            (relaxed on the fly from the donor cell's moments; through the interface map when
+//            the donor is in the other zone; the plate emission at a wall) give the new value
+//   barrier
+//   moments  one thread per cell: rho, j of the new state, the residual terms, and at a wall
+//            cell the density of the next emission from its arriving flux after relaxation
+//   barrier  (the residual: wave sums, then every thread adds the wave partials in order, so
+//            that all threads take the same decision and leave the loop together)
+__global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const HybChan* __restrict__ chans,
+                                                                         const double* __restrict__ tab,
+                                                                         double* __restrict__ state,
+                                                                         HybCtl* __restrict__ ctl,
+                                                                         double* __restrict__ ring, int64_t nsteps,
+                                                                         double tol, int solve) {
+    constexpr int NT = HYB_MARCH_THREADS;
     extern __shared__ double lds[];
     const HybChan C = chans[blockIdx.x];
     if (!C.active) return;
@@ -231,76 +217,194 @@ __global__ void __launch_bounds__(HYB_THREADS) hybrid_march_kernel(const HybChan
     const int tid = threadIdx.x;
     const int S = state_doubles(C);
     const Carve m = carve(lds, C, S);
-    for (int i = tid; i < C.ntab; i += HYB_THREADS) m.tb[i] = tab[C.tab_off + i];
+    for (int i = tid; i < C.ntab; i += NT) m.tb[i] = tab[C.tab_off + i];
     double* gs = state + C.state_off;
-    for (int i = tid; i < S; i += HYB_THREADS) m.fa[i] = gs[i];
+    for (int i = tid; i < S; i += NT) m.fa[i] = gs[i];
     __syncthreads();
     const HybView v = hyb_view(C, m.tb);
-    const int ny = v.ny;
-    for (int j = tid; j < ny; j += HYB_THREADS) {
-        double r, jx, jy;
-        cell_moments(v, m.fa, j, r, jx, jy);
-        m.mom[j] = r;
-        m.mom[ny + j] = jx;
-        m.mom[2 * ny + j] = jy;
-        m.uo[j] = jx / r;
-        m.uo[ny + j] = jy / r;
+    const int ny = v.ny, nl = v.nl, nb = v.nb, nx = v.nx, L = v.L;
+    const int SL = nl * v.qh;  // layer populations
+    const double om = C.omega;
+    double* rho = m.mom;
+    double* jxs = m.mom + ny;
+    double* jys = m.mom + 2 * ny;
+
+    // moments of the cell states in f (the thread of cell j); at a wall cell also the density of
+    // the emission that the relaxation of this state will see: the arriving flux of the relaxed
+    // populations, (1 - omega) Phi(f) + omega (rho A + j_x Bx + j_y By) with Phi(f) the arriving
+    // flux of f, over the flux one unit of emitted density carries (Eq. 9 read as impermeability)
+    auto cell_pass = [&](const double* f, int j, double& ux, double& uy) {
+        double r = 0.0, jx = 0.0, jy = 0.0, phi_dn = 0.0, phi_up = 0.0;
+        if (in_layer(v, j)) {
+            const int c = lcell(v, j);
+            for (int a = 0; a < v.nh; ++a) {
+                double sa = 0.0, sx = 0.0;
+                for (int i = 0; i < nx; ++i) {
+                    const double p = f[(a * nx + i) * nl + c];
+                    sa += p;
+                    sx += v.xx[i] * p;
+                }
+                const double y = v.yh[a];
+                r += sa;
+                jx += sx;
+                jy += y * sa;
+                if (y < 0.0) phi_dn -= y * sa;
+                else phi_up += y * sa;
+            }
+        } else {
+            cell_moments(v, f, j, r, jx, jy);
+        }
+        rho[j] = r;
+        jxs[j] = jx;
+        jys[j] = jy;
+        ux = jx / r;
+        uy = jy / r;
+        if (j == 0) m.rw[0] = C.e_inv * ((1.0 - om) * phi_dn + om * (r * C.wA[0] + jx * C.wBx[0] + jy * C.wBy[0]));
+        if (j == ny - 1) m.rw[1] = C.e_inv * ((1.0 - om) * phi_up + om * (r * C.wA[1] + jx * C.wBx[1] + jy * C.wBy[1]));
+    };
+    double* ifc_bl = m.ifc;                 // bulk nodes seen from layer cell L - 1
+    double* ifc_lb = ifc_bl + v.qf;         // layer nodes seen from bulk cell L
+    double* ifc_bt = ifc_lb + v.qh;         // bulk nodes seen from layer cell ny - L
+    double* ifc_lt = ifc_bt + v.qf;         // layer nodes seen from bulk cell ny - L - 1
+    for (int j = tid; j < ny; j += NT) {
+        double ux, uy;
+        cell_pass(m.fa, j, ux, uy);
+        m.uo[j] = ux;
+        m.uo[ny + j] = uy;
     }
+    interface_pass(v, m.fa, m.ifc, NT - 1 - tid, NT);
+    __syncthreads();
+    // where this thread's populations start, and how they advance by NT, in (plane, cell) terms
+    const int SB = S - SL;  // bulk populations
+    const int lc0 = tid % nl, lal0 = tid / nl, la0 = lal0 / nx, li0 = lal0 % nx;
+    const int ldc = NT % nl, ldal = NT / nl, lda = ldal / nx, ldi = ldal % nx;
+    const int nbs = nb > 0 ? nb : 1;
+    const int bb0 = tid % nbs, bal0 = tid / nbs, bk0 = bal0 / nx, bi0 = bal0 % nx;
+    const int bdb = NT % nbs, bdal = NT / nbs, bdk = bdal / nx, bdi = bdal % nx;
     double* cur = m.fa;
     double* nxt = m.fb;
     int64_t taken = 0;
     int stop = 0;
     double R = ct.residual;
-    while (taken < nsteps) {
-        for (int j = tid; j < ny; j += HYB_THREADS)
-            cell_relax(v, cur, j, m.mom[j], m.mom[ny + j], m.mom[2 * ny + j], C, m.ghost);
+    bool pending = false;  // the residual of step `taken` is still to be formed from its wave partials
+    // The moves of step taken + 1 start before the residual of step `taken` is formed (its wave
+    // partials were complete at the barrier that ended it): the reduction overlaps the moves, and
+    // a converged step leaves the loop with the tentative new state discarded.
+    while (true) {
+        const bool more = taken < nsteps;
+        if (more) {
+            // layer populations p = tid, tid + NT, ...: velocity plane alpha = a nx + i, layer cell c
+            int c = lc0, a = la0, i = li0;
+            for (int p = tid; p < SL; p += NT) {
+                const int j = c < L ? c : c + nb;
+                const double y = v.yh[a], xx = v.xx[i], wxi = v.wx[i], W = v.wh[a] * wxi;
+                const double gsf = relaxed(cur[p], W, xx, y, rho[j], jxs[j], jys[j], om);
+                const int up = y > 0.0 ? j - 1 : j + 1;
+                double gu;
+                if (up < 0) {
+                    gu = W * m.rw[0] * (1.0 + xx * C.u_bottom);
+                } else if (up >= ny) {
+                    gu = W * m.rw[1] * (1.0 + xx * C.u_top);
+                } else if (in_layer(v, up)) {
+                    gu = relaxed(cur[p + (lcell(v, up) - c)], W, xx, y, rho[up], jxs[up], jys[up], om);
+                } else {  // a bulk donor seen on the layer nodes
+                    const double raw = (up == L ? ifc_lb : ifc_lt)[a * nx + i];
+                    gu = relaxed(raw, W, xx, y, rho[up], jxs[up], jys[up], om);
+                }
+                nxt[p] = gsf - v.nuh[a] * (gsf - gu);
+                c += ldc;  // advance by NT populations without a division
+                const int carry = c >= nl ? 1 : 0;
+                c -= carry * nl;
+                i += ldi + carry;
+                a += lda;
+                if (i >= nx) {
+                    i -= nx;
+                    ++a;
+                }
+            }
+            // bulk populations q = tid, tid + NT, ...: velocity plane kappa = k nx + i, bulk cell b
+            int b = bb0, k = bk0;
+            i = bi0;
+            for (int q = tid; q < SB; q += NT) {
+                const int p = SL + q;
+                const int j = L + b;
+                const double y = v.yf[k], xx = v.xx[i], wxi = v.wx[i], W = v.wf[k] * wxi;
+                const double gsf = relaxed(cur[p], W, xx, y, rho[j], jxs[j], jys[j], om);
+                double fnew = gsf;
+                if (y != 0.0) {
+                    const int up = y > 0.0 ? j - 1 : j + 1;  // inside the channel: layer >= 1
+                    double gu;
+                    if (!in_layer(v, up)) {
+                        gu = relaxed(cur[p + (up - j)], W, xx, y, rho[up], jxs[up], jys[up], om);
+                    } else {  // a layer donor seen on the bulk nodes
+                        const double raw = (up == L - 1 ? ifc_bl : ifc_bt)[k * nx + i];
+                        gu = relaxed(raw, W, xx, y, rho[up], jxs[up], jys[up], om);
+                    }
+                    fnew = gsf - v.nuf[k] * (gsf - gu);
+                }
+                nxt[p] = fnew;
+                b += bdb;
+                const int carry = b >= nb ? 1 : 0;
+                b -= carry * nb;
+                i += bdi + carry;
+                k += bdk;
+                if (i >= nx) {
+                    i -= nx;
+                    ++k;
+                }
+            }
+        }
+        if (pending) {
+            const double* rd = m.red + (taken & 1) * 2 * (NT / 64);
+            double sdu = 0.0, suu = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) {
+                sdu += rd[2 * w];
+                suu += rd[2 * w + 1];
+            }
+            R = suu > 0.0 ? sqrt(sdu) / sqrt(suu) : (sdu == 0.0 ? 0.0 : INFINITY);
+            if (tid == 0) ring[C.hist_off + (ct.steps + taken - 1) % HYB_RING] = R;
+            pending = false;
+            if (solve) {  // every thread holds the same R: the exit is block-uniform
+                if (!isfinite(R)) {
+                    stop = 2;
+                    break;
+                }
+                if (R < tol) {
+                    stop = 1;
+                    break;
+                }
+            }
+        }
+        if (!more) break;
         __syncthreads();
         double du = 0.0, uu = 0.0;
-        for (int j = tid; j < ny; j += HYB_THREADS) {
-            cell_transport(v, cur, nxt, j, m.ghost);
-            double r, jx, jy;
-            cell_moments(v, nxt, j, r, jx, jy);
-            m.mom[j] = r;
-            m.mom[ny + j] = jx;
-            m.mom[2 * ny + j] = jy;
-            const double ux = jx / r, uy = jy / r;
+        for (int j = tid; j < ny; j += NT) {
+            double ux, uy;
+            cell_pass(nxt, j, ux, uy);
             const double dx = ux - m.uo[j], dy = uy - m.uo[ny + j];
             du += dx * dx + dy * dy;
             uu += ux * ux + uy * uy;
             m.uo[j] = ux;
             m.uo[ny + j] = uy;
         }
+        interface_pass(v, nxt, m.ifc, NT - 1 - tid, NT);
         du = wave_sum(du);
         uu = wave_sum(uu);
+        ++taken;
         if ((tid & 63) == 0) {
-            m.red[2 * (tid >> 6)] = du;
-            m.red[2 * (tid >> 6) + 1] = uu;
+            double* rd = m.red + (taken & 1) * 2 * (NT / 64);
+            rd[2 * (tid >> 6)] = du;
+            rd[2 * (tid >> 6) + 1] = uu;
         }
         __syncthreads();
-        double sdu = 0.0, suu = 0.0;
-        for (int w = 0; w < NWAVES; ++w) {
-            sdu += m.red[2 * w];
-            suu += m.red[2 * w + 1];
-        }
-        R = suu > 0.0 ? sqrt(sdu) / sqrt(suu) : (sdu == 0.0 ? 0.0 : INFINITY);
-        ++taken;
         double* t = cur;
         cur = nxt;
         nxt = t;
-        if (tid == 0) ring[C.hist_off + (ct.steps + taken - 1) % HYB_RING] = R;
-        if (solve) {
-            if (!isfinite(R)) {
-                stop = 2;
-                break;
-            }
-            if (R < tol) {
-                stop = 1;
-                break;
-            }
-        }
+        pending = true;
     }
     // every write to `cur` happened before the last barrier (or the load's)
-    for (int i = tid; i < S; i += HYB_THREADS) gs[i] = cur[i];
+    for (int i = tid; i < S; i += NT) gs[i] = cur[i];
     if (tid == 0) {
         ct.steps += taken;
         if (taken > 0) ct.residual = R;
@@ -450,7 +554,7 @@ void hybrid_allow_lds(size_t bytes) {
 
 void launch_hybrid_march(const HybChan* d_chans, int n, const double* d_tab, double* d_state, HybCtl* d_ctl,
                          double* d_ring, int64_t nsteps, double tol, int solve, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL(hybrid_march_kernel, dim3(n), dim3(HYB_THREADS), lds, stream, d_chans, d_tab, d_state, d_ctl,
+    hipLaunchKernelGGL(hybrid_march_kernel, dim3(n), dim3(HYB_MARCH_THREADS), lds, stream, d_chans, d_tab, d_state, d_ctl,
                        d_ring, nsteps, tol, solve);
     FDLB_HIP(hipGetLastError());
 }
