@@ -312,8 +312,15 @@ struct HybCtl {
 };
 
 constexpr int HYB_THREADS = 256;         // seeding and output kernels
-constexpr int HYB_MARCH_THREADS = 1024;  // the march kernel: one thread per population
+constexpr int HYB_MARCH_THREADS = 512;   // the march kernel: eight waves
 constexpr int HYB_RING = 1024;   // residuals kept per channel (the most recent ones)
+
+// Plane groups per chunk of 64 cells in the march kernel: enough work items for every wave of
+// the block when the channel has few chunks.
+__host__ __device__ inline int hyb_groups(int chunks) {
+    const int g = (HYB_MARCH_THREADS / 64) / (chunks > 0 ? chunks : 1);
+    return g > 1 ? g : 1;
+}
 
 // LDS bytes a channel's march needs.
 size_t hybrid_lds_bytes(const HybChan& c);

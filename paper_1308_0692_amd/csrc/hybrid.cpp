@@ -376,10 +376,17 @@ void post(fdlb_hybrid& h, int i, std::vector<double>& out) {
 
 }  // namespace
 
+// partial moments of the march kernel: [G][3][ny] and [G][2]
+static size_t hybrid_part_doubles(const HybChan& c) {
+    const int nl = 2 * c.layer, nb = c.ny - 2 * c.layer;
+    const int G = hyb_groups(((nl + 63) >> 6) + ((nb + 63) >> 6));
+    return (size_t)G * (3 * (size_t)c.ny + 2);
+}
+
 size_t hybrid_lds_bytes(const HybChan& c) {
     const size_t S = 2 * (size_t)c.layer * c.qh + (size_t)(c.ny - 2 * c.layer) * c.qf;
     return sizeof(double) * ((size_t)c.ntab + 2 * S + 5 * (size_t)c.ny + 2 * (size_t)c.qh + 4 * (HYB_MARCH_THREADS / 64) + 2 +
-                             2 * ((size_t)c.qh + c.qf));
+                             2 * ((size_t)c.qh + c.qf) + 64 + 8 * ((size_t)c.qh + c.qf) + hybrid_part_doubles(c));
 }
 
 int guard_call(const std::function<int()>& f);

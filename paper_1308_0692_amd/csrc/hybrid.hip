@@ -137,7 +137,7 @@ __device__ inline double wave_sum(double x) {
 
 // LDS carve shared by the march and post kernels (doubles).
 struct Carve {
-    double *tb, *fa, *fb, *mom, *uo, *ghost, *red, *rw, *ifc;
+    double *tb, *fa, *fb, *mom, *uo, *ghost, *red, *rw, *ifc, *lring, *ptab, *part;
 };
 
 __device__ inline Carve carve(double* lds, const HybChan& C, int S) {
@@ -152,6 +152,9 @@ __device__ inline Carve carve(double* lds, const HybChan& C, int S) {
     c.rw = c.red + 4 * (HYB_MARCH_THREADS / 64);  // two slots of wave partials
     c.ifc = c.rw + 2;                             // [bulk from layer L-1, layer from bulk L, bulk from
                                                   //  layer ny-L, layer from bulk ny-L-1]
+    c.lring = c.ifc + 2 * (C.qh + C.qf);          // the current 64-step block of the residual ring
+    c.ptab = c.lring + 64;                        // the march kernel's per-plane constants
+    c.part = c.ptab + 8 * (C.qh + C.qf);          // the march kernel's partial moments
     return c;
 }
 
@@ -194,14 +197,16 @@ __device__ inline double relaxed(double f, double W, double xx, double y, double
 
 // March every active channel: at most nsteps steps; with solve, stop at the first step whose
 // residual is below tol or not finite.  Per step:
-//   move     one thread per population: the relaxed value of the population and of its donor
-//            (relaxed on the fly from the donor cell's moments; through the interface map when
-//            the donor is in the other zone; the plate emission at a wall) give the new value
+//   move     a wave per chunk of 64 cells of one zone, a lane per cell walking every plane of its
+//            zone's set: the relaxed value of the population and of its donor (relaxed on the fly
+//            from the donor cell's moments; the interface value when the donor is in the other
+//            zone; the plate emission at a wall) give the new value, whose moments, residual
+//            terms and (at a wall cell) arriving flux accumulate in the lane's registers
 //   barrier
-//   moments  one thread per cell: rho, j of the new state, the residual terms, and at a wall
-//            cell the density of the next emission from its arriving flux after relaxation
-//   barrier  (the residual: wave sums, then every thread adds the wave partials in order, so
-//            that all threads take the same decision and leave the loop together)
+//   the interface cells' new populations carried to the other zone's nodes
+//   barrier  (the residual of the step is formed from the wave partials during the next moves,
+//            by every thread in the same order, so that all threads take the same decision and
+//            leave the loop together)
 __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const HybChan* __restrict__ chans,
                                                                          const double* __restrict__ tab,
                                                                          double* __restrict__ state,
@@ -220,27 +225,33 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
     for (int i = tid; i < C.ntab; i += NT) m.tb[i] = tab[C.tab_off + i];
     double* gs = state + C.state_off;
     for (int i = tid; i < S; i += NT) m.fa[i] = gs[i];
+    // Residuals go to an LDS copy of the ring's current 64-step block, written back every 64 steps
+    // and at the end: a global store inside the loop would hold its wave at every barrier until
+    // the store completed.
+    const int64_t blk0 = ct.steps & ~(int64_t)63;
+    if (tid < 64) m.lring[tid] = ring[C.hist_off + (blk0 + tid) % HYB_RING];
     __syncthreads();
     const HybView v = hyb_view(C, m.tb);
     const int ny = v.ny, nl = v.nl, nb = v.nb, nx = v.nx, L = v.L;
-    const int SL = nl * v.qh;  // layer populations
     const double om = C.omega;
-    double* rho = m.mom;
-    double* jxs = m.mom + ny;
-    double* jys = m.mom + 2 * ny;
+    double* mc = m.mom;  // [3][ny]: rho, j_x, j_y of the current state's cells
 
-    // moments of the cell states in f (the thread of cell j); at a wall cell also the density of
-    // the emission that the relaxation of this state will see: the arriving flux of the relaxed
-    // populations, (1 - omega) Phi(f) + omega (rho A + j_x Bx + j_y By) with Phi(f) the arriving
-    // flux of f, over the flux one unit of emitted density carries (Eq. 9 read as impermeability)
-    auto cell_pass = [&](const double* f, int j, double& ux, double& uy) {
+    // The density of the emission a wall will see when this state relaxes: the arriving flux of
+    // the relaxed populations, (1 - omega) Phi(f) + omega (rho A + j_x Bx + j_y By) with Phi(f)
+    // the arriving flux of f, over the flux one unit of emitted density carries (Eq. 9 read as
+    // impermeability).
+    auto wall_density = [&](int wall, double phi, double r, double jx, double jy) {
+        return C.e_inv * ((1.0 - om) * phi + om * (r * C.wA[wall] + jx * C.wBx[wall] + jy * C.wBy[wall]));
+    };
+    // moments of the loaded state, a thread per cell
+    for (int j = tid; j < ny; j += NT) {
         double r = 0.0, jx = 0.0, jy = 0.0, phi_dn = 0.0, phi_up = 0.0;
         if (in_layer(v, j)) {
             const int c = lcell(v, j);
             for (int a = 0; a < v.nh; ++a) {
                 double sa = 0.0, sx = 0.0;
                 for (int i = 0; i < nx; ++i) {
-                    const double p = f[(a * nx + i) * nl + c];
+                    const double p = m.fa[(a * nx + i) * nl + c];
                     sa += p;
                     sx += v.xx[i] * p;
                 }
@@ -252,35 +263,51 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
                 else phi_up += y * sa;
             }
         } else {
-            cell_moments(v, f, j, r, jx, jy);
+            cell_moments(v, m.fa, j, r, jx, jy);
         }
-        rho[j] = r;
-        jxs[j] = jx;
-        jys[j] = jy;
-        ux = jx / r;
-        uy = jy / r;
-        if (j == 0) m.rw[0] = C.e_inv * ((1.0 - om) * phi_dn + om * (r * C.wA[0] + jx * C.wBx[0] + jy * C.wBy[0]));
-        if (j == ny - 1) m.rw[1] = C.e_inv * ((1.0 - om) * phi_up + om * (r * C.wA[1] + jx * C.wBx[1] + jy * C.wBy[1]));
-    };
+        mc[j] = r;
+        mc[ny + j] = jx;
+        mc[2 * ny + j] = jy;
+        m.uo[j] = jx / r;
+        m.uo[ny + j] = jy / r;
+        if (j == 0) m.rw[0] = wall_density(0, phi_dn, r, jx, jy);
+        if (j == ny - 1) m.rw[1] = wall_density(1, phi_up, r, jx, jy);
+    }
     double* ifc_bl = m.ifc;                 // bulk nodes seen from layer cell L - 1
     double* ifc_lb = ifc_bl + v.qf;         // layer nodes seen from bulk cell L
     double* ifc_bt = ifc_lb + v.qh;         // bulk nodes seen from layer cell ny - L
     double* ifc_lt = ifc_bt + v.qf;         // layer nodes seen from bulk cell ny - L - 1
-    for (int j = tid; j < ny; j += NT) {
-        double ux, uy;
-        cell_pass(m.fa, j, ux, uy);
-        m.uo[j] = ux;
-        m.uo[ny + j] = uy;
+    // Per-plane constants of both sets, 8 doubles a plane: omega W, omega W xi_x, omega W xi_y, W,
+    // xi_x, xi_y, the Courant number and the sign of xi_y (layer planes, then bulk planes).
+    for (int q = tid; q < v.qh + v.qf; q += NT) {
+        const bool lay = q < v.qh;
+        const int alpha = lay ? q : q - v.qh;
+        const int a = alpha / nx, i = alpha - a * nx;
+        const double y = lay ? v.yh[a] : v.yf[a], W = (lay ? v.wh[a] : v.wf[a]) * v.wx[i], xx = v.xx[i];
+        double* pe = m.ptab + 8 * q;
+        pe[0] = om * W;
+        pe[1] = om * W * xx;
+        pe[2] = om * W * y;
+        pe[3] = W;
+        pe[4] = xx;
+        pe[5] = y;
+        pe[6] = lay ? v.nuh[a] : v.nuf[a];
+        pe[7] = y > 0.0 ? 1.0 : (y < 0.0 ? -1.0 : 0.0);
     }
     interface_pass(v, m.fa, m.ifc, NT - 1 - tid, NT);
     __syncthreads();
-    // where this thread's populations start, and how they advance by NT, in (plane, cell) terms
-    const int SB = S - SL;  // bulk populations
-    const int lc0 = tid % nl, lal0 = tid / nl, la0 = lal0 / nx, li0 = lal0 % nx;
-    const int ldc = NT % nl, ldal = NT / nl, lda = ldal / nx, ldi = ldal % nx;
-    const int nbs = nb > 0 ? nb : 1;
-    const int bb0 = tid % nbs, bal0 = tid / nbs, bk0 = bal0 / nx, bi0 = bal0 % nx;
-    const int bdb = NT % nbs, bdal = NT / nbs, bdk = bdal / nx, bdi = bdal % nx;
+
+    // Work items: a chunk of 64 consecutive cells of one zone (the layer cells in their list
+    // order, then the bulk cells) and one of G groups of its planes (every G-th plane).  A lane
+    // owns one cell and walks the group's planes: the plane index is the same across the wave,
+    // so the tables are read at uniform addresses, and the cell's partial moments accumulate in
+    // registers; the partials of the G groups are summed after the barrier.
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ncl = (nl + 63) >> 6, ncb = (nb + 63) >> 6;
+    const int G = hyb_groups(ncl + ncb);
+    const int nitems = (ncl + ncb) * G;
+    double* part = m.part;                  // [G][3][ny] partial moments, then [G][2] plate fluxes
+    double* pphi = part + 3 * G * ny;
     double* cur = m.fa;
     double* nxt = m.fb;
     int64_t taken = 0;
@@ -293,64 +320,63 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
     while (true) {
         const bool more = taken < nsteps;
         if (more) {
-            // layer populations p = tid, tid + NT, ...: velocity plane alpha = a nx + i, layer cell c
-            int c = lc0, a = la0, i = li0;
-            for (int p = tid; p < SL; p += NT) {
-                const int j = c < L ? c : c + nb;
-                const double y = v.yh[a], xx = v.xx[i], wxi = v.wx[i], W = v.wh[a] * wxi;
-                const double gsf = relaxed(cur[p], W, xx, y, rho[j], jxs[j], jys[j], om);
-                const int up = y > 0.0 ? j - 1 : j + 1;
-                double gu;
-                if (up < 0) {
-                    gu = W * m.rw[0] * (1.0 + xx * C.u_bottom);
-                } else if (up >= ny) {
-                    gu = W * m.rw[1] * (1.0 + xx * C.u_top);
-                } else if (in_layer(v, up)) {
-                    gu = relaxed(cur[p + (lcell(v, up) - c)], W, xx, y, rho[up], jxs[up], jys[up], om);
-                } else {  // a bulk donor seen on the layer nodes
-                    const double raw = (up == L ? ifc_lb : ifc_lt)[a * nx + i];
-                    gu = relaxed(raw, W, xx, y, rho[up], jxs[up], jys[up], om);
-                }
-                nxt[p] = gsf - v.nuh[a] * (gsf - gu);
-                c += ldc;  // advance by NT populations without a division
-                const int carry = c >= nl ? 1 : 0;
-                c -= carry * nl;
-                i += ldi + carry;
-                a += lda;
-                if (i >= nx) {
-                    i -= nx;
-                    ++a;
-                }
-            }
-            // bulk populations q = tid, tid + NT, ...: velocity plane kappa = k nx + i, bulk cell b
-            int b = bb0, k = bk0;
-            i = bi0;
-            for (int q = tid; q < SB; q += NT) {
-                const int p = SL + q;
-                const int j = L + b;
-                const double y = v.yf[k], xx = v.xx[i], wxi = v.wx[i], W = v.wf[k] * wxi;
-                const double gsf = relaxed(cur[p], W, xx, y, rho[j], jxs[j], jys[j], om);
-                double fnew = gsf;
-                if (y != 0.0) {
-                    const int up = y > 0.0 ? j - 1 : j + 1;  // inside the channel: layer >= 1
-                    double gu;
-                    if (!in_layer(v, up)) {
-                        gu = relaxed(cur[p + (up - j)], W, xx, y, rho[up], jxs[up], jys[up], om);
-                    } else {  // a layer donor seen on the bulk nodes
-                        const double raw = (up == L - 1 ? ifc_bl : ifc_bt)[k * nx + i];
-                        gu = relaxed(raw, W, xx, y, rho[up], jxs[up], jys[up], om);
+            const double rw0 = m.rw[0], rw1 = m.rw[1];
+            for (int item = wave; item < nitems; item += NT / 64) {
+                const int chunk = item / G, g = item - chunk * G;
+                const bool layer = chunk < ncl;
+                const int ci = (layer ? chunk : chunk - ncl) * 64 + lane;  // index in the zone's cell list
+                const int ncell = layer ? nl : nb;
+                const bool act = ci < ncell;
+                const int cc = act ? ci : ncell - 1;                        // idle lanes shadow the last cell
+                const int j = layer ? (cc < L ? cc : cc + nb) : L + cc;
+                const int jm = j > 0 ? j - 1 : j, jp = j < ny - 1 ? j + 1 : j;
+                const double r0 = mc[j], x0 = mc[ny + j], y0m = mc[2 * ny + j];
+                const double rm = mc[jm], xm = mc[ny + jm], ym = mc[2 * ny + jm];
+                const double rp = mc[jp], xp = mc[ny + jp], yp = mc[2 * ny + jp];
+                const int qz = layer ? v.qh : v.qf;
+                const double* pz = m.ptab + (layer ? 0 : 8 * v.qh);  // this zone's plane constants
+                // a donor across the zone boundary is seen through the interface values
+                const bool lo_other = (j - 1 >= 0) && (in_layer(v, j - 1) != layer);
+                const bool hi_other = (j + 1 < ny) && (in_layer(v, j + 1) != layer);
+                const double* ifc_lo = layer ? ifc_lt : ifc_bl;  // donor j - 1 in the other zone
+                const double* ifc_hi = layer ? ifc_lb : ifc_bt;  // donor j + 1 in the other zone
+                const int cm = layer ? lcell(v, jm) : jm - L, cp = layer ? lcell(v, jp) : jp - L;
+                const int base = layer ? 0 : nl * v.qh;
+                double nr = 0.0, njx = 0.0, njy = 0.0, phi_dn = 0.0, phi_up = 0.0;
+                for (int alpha = g; alpha < qz; alpha += G) {
+                    const double* pe = pz + 8 * alpha;  // the same address in every lane
+                    const double ow = pe[0], owx = pe[1], owy = pe[2], W = pe[3], xx = pe[4], y = pe[5];
+                    const double nu = pe[6];
+                    const int dir = __builtin_amdgcn_readfirstlane((int)pe[7]);  // sign of xi_y
+                    const int pl = base + alpha * ncell;
+                    const double f0 = cur[pl + cc];
+                    const double gsf = f0 + ((ow * r0 + owx * x0 + owy * y0m) - om * f0);
+                    double fnew = gsf;
+                    if (dir > 0) {          // donor below
+                        const double fd = lo_other ? ifc_lo[alpha] : cur[pl + cm];
+                        double gu = fd + ((ow * rm + owx * xm + owy * ym) - om * fd);
+                        if (j == 0) gu = W * rw0 * (1.0 + xx * C.u_bottom);
+                        fnew = gsf - nu * (gsf - gu);
+                    } else if (dir < 0) {   // donor above
+                        const double fd = hi_other ? ifc_hi[alpha] : cur[pl + cp];
+                        double gu = fd + ((ow * rp + owx * xp + owy * yp) - om * fd);
+                        if (j == ny - 1) gu = W * rw1 * (1.0 + xx * C.u_top);
+                        fnew = gsf - nu * (gsf - gu);
                     }
-                    fnew = gsf - v.nuf[k] * (gsf - gu);
+                    if (act) nxt[pl + cc] = fnew;
+                    nr += fnew;
+                    njx += xx * fnew;
+                    njy += y * fnew;
+                    if (dir < 0) phi_dn -= y * fnew;
+                    else phi_up += y * fnew;
                 }
-                nxt[p] = fnew;
-                b += bdb;
-                const int carry = b >= nb ? 1 : 0;
-                b -= carry * nb;
-                i += bdi + carry;
-                k += bdk;
-                if (i >= nx) {
-                    i -= nx;
-                    ++k;
+                if (act) {
+                    double* pg = part + 3 * g * ny;
+                    pg[j] = nr;
+                    pg[ny + j] = njx;
+                    pg[2 * ny + j] = njy;
+                    if (j == 0) pphi[2 * g] = phi_dn;
+                    if (j == ny - 1) pphi[2 * g + 1] = phi_up;
                 }
             }
         }
@@ -363,7 +389,10 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
                 suu += rd[2 * w + 1];
             }
             R = suu > 0.0 ? sqrt(sdu) / sqrt(suu) : (sdu == 0.0 ? 0.0 : INFINITY);
-            if (tid == 0) ring[C.hist_off + (ct.steps + taken - 1) % HYB_RING] = R;
+            const int64_t sn = ct.steps + taken;  // step number of this residual (from 1)
+            if (tid == 0) m.lring[(sn - 1) & 63] = R;
+            if ((sn & 63) == 0 && tid < 64)       // a full block: written back by wave 0
+                ring[C.hist_off + (sn - 64 + tid) % HYB_RING] = m.lring[tid];
             pending = false;
             if (solve) {  // every thread holds the same R: the exit is block-uniform
                 if (!isfinite(R)) {
@@ -378,24 +407,43 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
         }
         if (!more) break;
         __syncthreads();
+        // the new state's moments from the groups' partials (a thread per cell), its residual
+        // terms and the plates' next emission densities; the interface values of the new state
         double du = 0.0, uu = 0.0;
         for (int j = tid; j < ny; j += NT) {
-            double ux, uy;
-            cell_pass(nxt, j, ux, uy);
+            double r = 0.0, jx = 0.0, jy = 0.0;
+            for (int g = 0; g < G; ++g) {
+                const double* pg = part + 3 * g * ny;
+                r += pg[j];
+                jx += pg[ny + j];
+                jy += pg[2 * ny + j];
+            }
+            mc[j] = r;
+            mc[ny + j] = jx;
+            mc[2 * ny + j] = jy;
+            const double ux = jx / r, uy = jy / r;
             const double dx = ux - m.uo[j], dy = uy - m.uo[ny + j];
             du += dx * dx + dy * dy;
             uu += ux * ux + uy * uy;
             m.uo[j] = ux;
             m.uo[ny + j] = uy;
+            if (j == 0 || j == ny - 1) {
+                for (int wall = 0; wall < 2; ++wall) {
+                    if (j != (wall == 0 ? 0 : ny - 1)) continue;
+                    double phi = 0.0;
+                    for (int g = 0; g < G; ++g) phi += pphi[2 * g + wall];
+                    m.rw[wall] = wall_density(wall, phi, r, jx, jy);
+                }
+            }
         }
         interface_pass(v, nxt, m.ifc, NT - 1 - tid, NT);
         du = wave_sum(du);
         uu = wave_sum(uu);
         ++taken;
-        if ((tid & 63) == 0) {
+        if (lane == 0) {
             double* rd = m.red + (taken & 1) * 2 * (NT / 64);
-            rd[2 * (tid >> 6)] = du;
-            rd[2 * (tid >> 6) + 1] = uu;
+            rd[2 * wave] = du;
+            rd[2 * wave + 1] = uu;
         }
         __syncthreads();
         double* t = cur;
@@ -403,8 +451,14 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
         nxt = t;
         pending = true;
     }
-    // every write to `cur` happened before the last barrier (or the load's)
+    // every write to `cur` happened before the last barrier (or the load's); the ring's last
+    // block holds every residual recorded (wave 0 wrote them, in order)
     for (int i = tid; i < S; i += NT) gs[i] = cur[i];
+    {
+        const int64_t sn = ct.steps + taken - (pending ? 1 : 0);  // last residual recorded
+        if (tid < 64 && (sn & 63) != 0 && sn > blk0 && tid < (int)(sn & 63))
+            ring[C.hist_off + ((sn & ~(int64_t)63) + tid) % HYB_RING] = m.lring[tid];
+    }
     if (tid == 0) {
         ct.steps += taken;
         if (taken > 0) ct.residual = R;
