@@ -4,7 +4,8 @@ Couette flow (plates at y = 0 and 1 sliding at -u_w and +u_w): the slip at the p
 shear stress against the free-molecular value, the quantities of the paper's Couette figures,
 for a half-range lattice (the paper's method) or the standard full-range one.  Lid-driven
 cavity: the drag on the lid and the recirculating flow rate through the vertical mid-line, the
-quantities of the paper's cavity table, and the mid-line velocity profile.
+quantities of the paper's cavity table, and the mid-line velocity profile.  Couette flow on the
+half-range / full-range hybrid that the paper proposes (the library's fdlb_hybrid_* channels).
 
 Conventions (all in the units of Eq. (1); Kn is Eq. (1)'s Knudsen number):
   slip          1 - u_t(wall) / u_w at the upper plate, u_t the tangential velocity of the face
@@ -27,7 +28,7 @@ the Richardson value 2 v(2N) - v(N) is reported beside the values of both grids.
 from __future__ import annotations
 
 import math
-from typing import Dict, Iterable, List, Sequence, Tuple
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -164,4 +165,50 @@ def cavity_sweep(kns: Sequence[float], lattice="D2Qh16", n: int = 64, refine: bo
         for r in rows:
             r["D"], r["G"] = r["D_N"], r["G_N"]
     b.close()
+    return rows
+
+
+def hybrid_couette_sweep(kns: Sequence[float], delta: float = 0.2, ny: int = 200, n_half: int = 4,
+                         n_full: Optional[int] = None, qx: Rule = ("full", 3), refine: bool = True,
+                         u_w: float = 0.01, tol: float = 1e-12, max_steps: int = 4_000_000,
+                         device="cuda:0") -> List[dict]:
+    """Couette flow on the half-range / full-range hybrid (layers of thickness ``delta`` next to
+    the plates on ``n_half`` nodes per half-line, the bulk on ``n_full`` full-range nodes), every
+    Kn and grid one channel of a single hybrid launch.
+
+    Per Kn: ``slip`` and ``pxy_over_pfm`` at the upper plate (Richardson values from ny and 2 ny
+    cells when ``refine``), ``defect`` = the relative difference of the momentum flux through the
+    upper interface as the bulk and the layer see it (the coupling's conservation defect; 0
+    without a bulk), the values of each grid and the steps taken."""
+    from . import Hybrid
+    if n_full is None:
+        n_full = n_half
+    grids = [ny, 2 * ny] if refine else [ny]
+    chans = [dict(ny=n, layer=max(1, int(round(delta * n))), kn=float(kn), u_w=(-u_w, u_w), n_half=n_half,
+                  n_full=n_full, qx=qx) for n in grids for kn in kns]
+    h = Hybrid(chans, device=device)
+    h.init_all()
+    code, reps = h.solve(tol, max_steps)
+    bad = [i for i, r in enumerate(reps) if r["status"] != 0]
+    if bad:
+        h.close()
+        raise RuntimeError(f"hybrid channels {bad} did not converge to {tol:g}")
+    pfm = p_free_molecular(u_w)
+    rows = []
+    for j, kn in enumerate(kns):
+        row = {"kn": float(kn), "kn_printed": math.sqrt(2.0) * float(kn)}
+        for g, tag in zip(range(len(grids)), ("_N", "_2N")):
+            i = g * len(kns) + j
+            f = h.faces(i)
+            row["slip" + tag] = 1.0 - float(f[2]) / u_w
+            row["pxy_over_pfm" + tag] = float(f[3]) / pfm
+            row["defect" + tag] = 0.0 if math.isnan(f[6]) else abs(float(f[6]) / float(f[7]) - 1.0)
+            row["steps" + tag] = int(reps[i]["steps"])
+        rows.append(row)
+    if refine:
+        _richardson(rows, ("slip", "pxy_over_pfm", "defect"))
+    else:
+        for r in rows:
+            r["slip"], r["pxy_over_pfm"], r["defect"] = r["slip_N"], r["pxy_over_pfm_N"], r["defect_N"]
+    h.close()
     return rows

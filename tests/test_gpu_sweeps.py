@@ -104,3 +104,25 @@ def test_cavity_sweep_against_printed_table(S, lattice):
         G_printed = table[kn][lattice][1]
         assert abs(r["D"] - D_printed) <= 0.03 * D_printed, (lattice, kn, r["D"], D_printed)
         assert abs(r["G"] - G_printed) <= 0.03 * G_printed, (lattice, kn, r["G"], G_printed)
+
+
+def test_hybrid_couette_sweep_matches_semi_analytic_coupling(S):
+    """The hybrid sweep's Richardson values (100 and 200 cells, layers of 0.2) against the
+    semi-analytic solution of the coupling, for 2 nodes per half with a 2-node bulk and 4 per
+    half with a 3-node bulk; with layers 10 Kn thick the 2/2 hybrid is the half-range model."""
+    from oracle.hybrid import HybridSolution
+    pfm = -math.sqrt(2 / math.pi)
+    for nh, nf in ((2, 2), (4, 3)):
+        rows = S.hybrid_couette_sweep([0.1, 0.3], delta=0.2, ny=100, n_half=nh, n_full=nf, u_w=1.0)
+        for r in rows:
+            ex = HybridSolution(nh, nf, r["kn"], 0.2, 1.0)
+            u_wall = -ex.wall_u()   # upper plate by antisymmetry
+            assert abs((1 - r["slip"]) - u_wall) <= 2e-4 * abs(u_wall), (nh, nf, r)
+            assert abs(r["pxy_over_pfm"] - ex.pxy_layer() / pfm) <= 2e-4 * abs(ex.pxy_layer() / pfm), (nh, nf, r)
+    rows = S.hybrid_couette_sweep([0.02], delta=0.2, ny=100, n_half=2, n_full=2, u_w=1.0)
+    pure = couette.CouetteSolution(2, 0.02, 1.0)
+    assert abs(rows[0]["pxy_over_pfm"] - pure.pxy() / pfm) <= 1e-3 * abs(pure.pxy() / pfm)
+    # the interface's flux defect is a first-order discretisation error here (the coupling's own
+    # is ~1e-7 at this depth): it halves with the grid and extrapolates to nearly nothing
+    assert 1.7 < rows[0]["defect_N"] / rows[0]["defect_2N"] < 2.3
+    assert abs(rows[0]["defect"]) < 5e-3
