@@ -354,8 +354,9 @@ int solve(fdlb_hybrid& h, double tol, int64_t max_steps, int64_t chunk, fdlb_rep
         if (r.history && r.history_cap > 0 && taken > 0) {
             const int64_t len = std::min<int64_t>({(int64_t)r.history_cap, taken, (int64_t)HYB_RING});
             std::vector<double> ring(HYB_RING);
-            FDLB_HIP(hipMemcpy(ring.data(), d_ring(h) + (size_t)c * HYB_RING, HYB_RING * sizeof(double),
-                               hipMemcpyDeviceToHost));
+            FDLB_HIP(hipMemcpyAsync(ring.data(), d_ring(h) + (size_t)c * HYB_RING, HYB_RING * sizeof(double),
+                                    hipMemcpyDeviceToHost, h.stream));
+            FDLB_HIP(hipStreamSynchronize(h.stream));
             const int64_t last = ctl[c].steps;  // step numbers last - len + 1 .. last
             for (int64_t s = 0; s < len; ++s) r.history[s] = ring[(last - len + s) % HYB_RING];
             r.history_len = (int32_t)len;
