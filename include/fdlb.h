@@ -627,8 +627,9 @@ int fdlb_hybrid_info(const fdlb_hybrid *h, int i, int32_t *q_layer, int32_t *q_b
                      int64_t *state_doubles, double *dt, double *omega);
 
 /* Bind the arenas (256-byte aligned) and a stream; uploads the tables (synchronous).
- * FDLB_EINVAL if a channel's LDS footprint (16 bytes per population plus 40 per cell and
- * its tables) exceeds what one workgroup may hold on the current device. */
+ * FDLB_EINVAL if a channel's LDS footprint (16 bytes per population, 64-232 bytes per cell
+ * for its moments and their partial sums, and its tables) exceeds what one workgroup may
+ * hold on the current device. */
 int fdlb_hybrid_bind(fdlb_hybrid *h, void *d_state, void *d_workspace, void *stream);
 
 /* Seed channel i at f = w (rho + xi . rho u) on each cell's own set from host arrays of ny

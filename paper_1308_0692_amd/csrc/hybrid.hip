@@ -6,13 +6,14 @@
 // rule (the paper's method, where the Knudsen layers live); the cells between use the x rule
 // times a full-range y rule, the cheaper set that the paper's closing remarks propose for the
 // bulk.  The march kernel keeps the populations and each cell's moments in LDS; a step is one
-// pass with a thread per population (relax the population and its donor from the moments of
-// their cells, transport by the donor cell, the donor seen through the interface map when it
-// lies in the other zone, the plate emission at a wall) and one pass with a thread per cell
-// (moments of the new state, the residual terms, the next emission density), two barriers in
-// all and no global memory traffic inside the loop.  A small channel's step is a few
-// microseconds of one CU instead of a kernel launch, and a batch of channels (a Kn sweep) fills
-// the chip with one workgroup each.
+// pass with a wave per chunk of 64 cells of one zone and group of planes (a lane relaxes its
+// cell's population and its donor from the moments of their cells, transports by the donor
+// cell, sees a donor in the other zone through the interface map and the plate emission at a
+// wall, and keeps its cell's partial moments in registers) and one pass with a thread per cell
+// (moments of the new state from the partials, the residual terms, the next emission density),
+// two barriers in all and no global memory traffic inside the loop but a write-back of the
+// residuals every 64 steps.  A small channel's step is a few microseconds of one CU instead of
+// a kernel launch, and a batch of channels (a Kn sweep) fills the chip with one workgroup each.
 #include "fdlb_internal.h"
 
 namespace fdlb {
