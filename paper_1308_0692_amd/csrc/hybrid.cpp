@@ -130,6 +130,18 @@ void create(fdlb_hybrid& h, const fdlb_hybrid_desc* descs, int n) {
         const int ka = std::min(d.n_half, d.n_full) - 1, kb = d.n_full - 1;
         put(transfer(yh, yf, wf, ka));
         put(transfer(yf, yh, wh, kb));
+        // per-plane constants of the march kernel (layer planes, then bulk planes)
+        for (int zone = 0; zone < 2; ++zone) {
+            const std::vector<double>& yz = zone == 0 ? yh : yf;
+            const std::vector<double>& wz = zone == 0 ? wh : wf;
+            for (size_t a = 0; a < yz.size(); ++a)
+                for (int i = 0; i < (int)xx.size(); ++i) {
+                    const double W = wz[a] * wx[i], y = yz[a];
+                    const double e[8] = {omega * W, omega * W * xx[i], omega * W * y, W, xx[i], y,
+                                         dt * std::fabs(y) * d.ny, y > 0 ? 1.0 : (y < 0 ? -1.0 : 0.0)};
+                    h.tab.insert(h.tab.end(), e, e + 8);
+                }
+        }
         double sx = 0, leave = 0;
         for (double w : wx) sx += w;
         for (int a = 0; a < nh; ++a)
@@ -387,7 +399,7 @@ static size_t hybrid_part_doubles(const HybChan& c) {
 size_t hybrid_lds_bytes(const HybChan& c) {
     const size_t S = 2 * (size_t)c.layer * c.qh + (size_t)(c.ny - 2 * c.layer) * c.qf;
     return sizeof(double) * ((size_t)c.ntab + 2 * S + 5 * (size_t)c.ny + 2 * (size_t)c.qh + 4 * (HYB_MARCH_THREADS / 64) + 2 +
-                             2 * ((size_t)c.qh + c.qf) + 64 + 8 * ((size_t)c.qh + c.qf) + hybrid_part_doubles(c));
+                             2 * ((size_t)c.qh + c.qf) + 64 + hybrid_part_doubles(c));
 }
 
 int guard_call(const std::function<int()>& f);

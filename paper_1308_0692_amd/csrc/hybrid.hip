@@ -131,14 +131,46 @@ __device__ inline void cell_relax(const HybView& v, double* f, int j, double r, 
     }
 }
 
+// A double moved across lanes by a DPP control (both 32-bit halves); lanes without a source
+// get 0.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double x) {
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    const int l = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xf, false);
+    const int h = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, false);
+    return __hiloint2double(h, l);
+}
+
+__device__ inline double lane_value(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Sum over the 64 lanes of a wave, the same value in every lane: a scan within each row of 16
+// lanes (row_shr 1, 2, 4, 8), then the row totals carried across rows (row_bcast 15 and 31),
+// read from the last lane.  DPP moves are register operations: no LDS round trip.
 __device__ inline double wave_sum(double x) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    x += dpp_move<0x111, 0xf>(x);  // row_shr:1
+    x += dpp_move<0x112, 0xf>(x);  // row_shr:2
+    x += dpp_move<0x114, 0xf>(x);  // row_shr:4
+    x += dpp_move<0x118, 0xf>(x);  // row_shr:8
+    x += dpp_move<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_move<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return lane_value(x, 63);
+}
+
+// Sum of the first 16 lanes' values, the same in every lane (row 0's scan).
+__device__ inline double row0_sum(double x) {
+    x += dpp_move<0x111, 0xf>(x);
+    x += dpp_move<0x112, 0xf>(x);
+    x += dpp_move<0x114, 0xf>(x);
+    x += dpp_move<0x118, 0xf>(x);
+    return lane_value(x, 15);
 }
 
 // LDS carve shared by the march and post kernels (doubles).
 struct Carve {
-    double *tb, *fa, *fb, *mom, *uo, *ghost, *red, *rw, *ifc, *lring, *ptab, *part;
+    double *tb, *fa, *fb, *mom, *uo, *ghost, *red, *rw, *ifc, *lring, *part;
 };
 
 __device__ inline Carve carve(double* lds, const HybChan& C, int S) {
@@ -154,8 +186,7 @@ __device__ inline Carve carve(double* lds, const HybChan& C, int S) {
     c.ifc = c.rw + 2;                             // [bulk from layer L-1, layer from bulk L, bulk from
                                                   //  layer ny-L, layer from bulk ny-L-1]
     c.lring = c.ifc + 2 * (C.qh + C.qf);          // the current 64-step block of the residual ring
-    c.ptab = c.lring + 64;                        // the march kernel's per-plane constants
-    c.part = c.ptab + 8 * (C.qh + C.qf);          // the march kernel's partial moments
+    c.part = c.lring + 64;                        // the march kernel's partial moments
     return c;
 }
 
@@ -235,6 +266,10 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
     const HybView v = hyb_view(C, m.tb);
     const int ny = v.ny, nl = v.nl, nb = v.nb, nx = v.nx, L = v.L;
     const double om = C.omega;
+    // per-plane constants (after the maps in the channel's table), 8 doubles a plane: omega W,
+    // omega W xi_x, omega W xi_y, W, xi_x, xi_y, the Courant number and the sign of xi_y, layer
+    // planes then bulk planes
+    const double* __restrict__ ptab = tab + C.tab_off + (v.B + v.nh * v.nf - m.tb);
     double* mc = m.mom;  // [3][ny]: rho, j_x, j_y of the current state's cells
 
     // The density of the emission a wall will see when this state relaxes: the arriving flux of
@@ -278,23 +313,6 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
     double* ifc_lb = ifc_bl + v.qf;         // layer nodes seen from bulk cell L
     double* ifc_bt = ifc_lb + v.qh;         // bulk nodes seen from layer cell ny - L
     double* ifc_lt = ifc_bt + v.qf;         // layer nodes seen from bulk cell ny - L - 1
-    // Per-plane constants of both sets, 8 doubles a plane: omega W, omega W xi_x, omega W xi_y, W,
-    // xi_x, xi_y, the Courant number and the sign of xi_y (layer planes, then bulk planes).
-    for (int q = tid; q < v.qh + v.qf; q += NT) {
-        const bool lay = q < v.qh;
-        const int alpha = lay ? q : q - v.qh;
-        const int a = alpha / nx, i = alpha - a * nx;
-        const double y = lay ? v.yh[a] : v.yf[a], W = (lay ? v.wh[a] : v.wf[a]) * v.wx[i], xx = v.xx[i];
-        double* pe = m.ptab + 8 * q;
-        pe[0] = om * W;
-        pe[1] = om * W * xx;
-        pe[2] = om * W * y;
-        pe[3] = W;
-        pe[4] = xx;
-        pe[5] = y;
-        pe[6] = lay ? v.nuh[a] : v.nuf[a];
-        pe[7] = y > 0.0 ? 1.0 : (y < 0.0 ? -1.0 : 0.0);
-    }
     interface_pass(v, m.fa, m.ifc, NT - 1 - tid, NT);
     __syncthreads();
 
@@ -303,7 +321,7 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
     // owns one cell and walks the group's planes: the plane index is the same across the wave,
     // so the tables are read at uniform addresses, and the cell's partial moments accumulate in
     // registers; the partials of the G groups are summed after the barrier.
-    const int wave = tid >> 6, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int ncl = (nl + 63) >> 6, ncb = (nb + 63) >> 6;
     const int G = hyb_groups(ncl + ncb);
     const int nitems = (ncl + ncb) * G;
@@ -335,7 +353,9 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
                 const double rm = mc[jm], xm = mc[ny + jm], ym = mc[2 * ny + jm];
                 const double rp = mc[jp], xp = mc[ny + jp], yp = mc[2 * ny + jp];
                 const int qz = layer ? v.qh : v.qf;
-                const double* pz = m.ptab + (layer ? 0 : 8 * v.qh);  // this zone's plane constants
+                // this zone's plane constants, read from the global table at addresses uniform across
+                // the wave (scalar loads, off the LDS queue)
+                const double* __restrict__ pz = ptab + (layer ? 0 : 8 * v.qh);
                 // a donor across the zone boundary is seen through the interface values
                 const bool lo_other = (j - 1 >= 0) && (in_layer(v, j - 1) != layer);
                 const bool hi_other = (j + 1 < ny) && (in_layer(v, j + 1) != layer);
@@ -345,10 +365,10 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
                 const int base = layer ? 0 : nl * v.qh;
                 double nr = 0.0, njx = 0.0, njy = 0.0, phi_dn = 0.0, phi_up = 0.0;
                 for (int alpha = g; alpha < qz; alpha += G) {
-                    const double* pe = pz + 8 * alpha;  // the same address in every lane
+                    const double* __restrict__ pe = pz + 8 * alpha;
                     const double ow = pe[0], owx = pe[1], owy = pe[2], W = pe[3], xx = pe[4], y = pe[5];
                     const double nu = pe[6];
-                    const int dir = __builtin_amdgcn_readfirstlane((int)pe[7]);  // sign of xi_y
+                    const int dir = (int)pe[7];  // sign of xi_y
                     const int pl = base + alpha * ncell;
                     const double f0 = cur[pl + cc];
                     const double gsf = f0 + ((ow * r0 + owx * x0 + owy * y0m) - om * f0);
@@ -382,13 +402,12 @@ __global__ void __launch_bounds__(HYB_MARCH_THREADS) hybrid_march_kernel(const H
             }
         }
         if (pending) {
+            // lane w < NT / 64 of every wave reads wave w's partials; a row scan adds them
+            static_assert(NT / 64 <= 16, "the residual's wave partials must fit one row of lanes");
             const double* rd = m.red + (taken & 1) * 2 * (NT / 64);
-            double sdu = 0.0, suu = 0.0;
-#pragma unroll
-            for (int w = 0; w < NT / 64; ++w) {
-                sdu += rd[2 * w];
-                suu += rd[2 * w + 1];
-            }
+            const bool has = lane < NT / 64;
+            const double sdu = row0_sum(has ? rd[2 * lane] : 0.0);
+            const double suu = row0_sum(has ? rd[2 * lane + 1] : 0.0);
             R = suu > 0.0 ? sqrt(sdu) / sqrt(suu) : (sdu == 0.0 ? 0.0 : INFINITY);
             const int64_t sn = ct.steps + taken;  // step number of this residual (from 1)
             if (tid == 0) m.lring[(sn - 1) & 63] = R;
