@@ -73,6 +73,36 @@ int main(void) {
             fdlb_mlp_destroy(m);
         }
     }
+    /* hybrid channels: valid and invalid descriptions, layouts (host only, never bound) */
+    for (int k = 0; k < 200; ++k) {
+        fdlb_hybrid_desc hd = {0};
+        hd.ny = 2 + (k * 37) % 300;
+        hd.layer = 1 + (k * 13) % (hd.ny / 2 + 2);   /* sometimes past ny / 2: invalid */
+        hd.kn = (k % 11 == 0) ? INFINITY : 0.01 + 0.1 * (k % 7);
+        hd.u_bottom = -0.01;
+        hd.u_top = 0.01;
+        hd.cfl = (k % 17 == 0) ? 1.5 : 0.9;
+        hd.qx_kind = k % 2;
+        hd.qx_n = (k % 2 == 0) ? 1 + k % 6 : 1 + k % 4;
+        hd.n_half = 1 + k % 9;
+        hd.n_full = 1 + k % 17;
+        fdlb_hybrid *hy = NULL;
+        int r = fdlb_hybrid_create(&hd, 1, &hy);
+        if (r == FDLB_OK) {
+            int32_t ql = 0, qb = 0;
+            int64_t sd = 0;
+            double dt = 0, om = 0;
+            (void)fdlb_hybrid_info(hy, 0, &ql, &qb, &sd, &dt, &om);
+            (void)fdlb_hybrid_info(hy, 1, NULL, NULL, NULL, NULL, NULL);
+            (void)fdlb_hybrid_state_bytes(hy);
+            (void)fdlb_hybrid_workspace_bytes(hy);
+            if (fdlb_hybrid_step(hy, 1) != FDLB_ESTATE) { printf("unbound hybrid stepped\n"); bad++; }
+            fdlb_hybrid_destroy(hy);
+        } else if (hy != NULL) {
+            printf("hybrid handle set on error\n");
+            bad++;
+        }
+    }
     char buf[8];
     for (int prec = 0; prec < 3; ++prec)
         for (int t = -1; t < 40; ++t) (void)fdlb_tile_describe(prec, t, buf, sizeof buf);

@@ -4,7 +4,7 @@
 The library is rebuilt with host-side instrumentation only (-Xarch_host -fsanitize=...; the
 device code is not instrumented) and tests/asan/harness.c drives every host-only entry point:
 quadrature of every order, seeded valid and invalid problem descriptions, batches, networks,
-tile descriptions and error messages.  No GPU call is made."""
+hybrid channels, tile descriptions and error messages.  No GPU call is made."""
 import glob
 import os
 import subprocess
