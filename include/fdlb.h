@@ -511,7 +511,7 @@ typedef struct fdlb_mlp fdlb_mlp; /* opaque host handle */
 int fdlb_mlp_create(int hidden_layers, int64_t max_batch, fdlb_mlp **out);
 void fdlb_mlp_destroy(fdlb_mlp *m);
 int64_t fdlb_mlp_param_count(const fdlb_mlp *m);
-size_t fdlb_mlp_workspace_bytes(const fdlb_mlp *m); /* activations, partial gradients, bf16 weights */
+size_t fdlb_mlp_workspace_bytes(const fdlb_mlp *m); /* bf16 weights, bf16 activation and gradient transposes, partial gradients */
 
 /* Glorot-uniform weights (bound sqrt(6 / (fan_in + fan_out)), splitmix64 stream from
  * `seed`) and zero biases into a caller host array of fdlb_mlp_param_count floats. */

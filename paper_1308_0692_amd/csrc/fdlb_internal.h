@@ -186,7 +186,9 @@ char* static_scratch();
 
 // Warm-start network (mlp.hip / mlp.cpp).
 constexpr int MLP_WIDTH = 128;     // hidden width (the matrix-core tiles assume it)
-constexpr int MLP_TILE = 64;       // samples per block
+constexpr int MLP_TILE = 64;       // samples per block of the inference kernel
+constexpr int MLP_TRAIN_TILE = 32; // samples per block of the training kernel
+constexpr int MLP_SLICE = 256;     // samples per block of the hidden weight-gradient kernel
 constexpr int MLP_MAX_HIDDEN = 8;  // hidden layers
 
 struct MlpArgs {
@@ -196,12 +198,14 @@ struct MlpArgs {
     const float* in;            // [.][3] encoded inputs (unless cells_nx > 0)
     const int32_t* rows;        // optional: sample g reads row rows[g] of in and target
     const float* target;        // [.][3]
-    float* out;                 // [n][3] outputs (sample order)
-    float* act;                 // [hidden][n_cap][128] fp32 activations (training)
-    float* partial;             // [blocks][P] per-block gradients
-    double* loss_part;          // [blocks] per-block squared errors
+    float* out;                 // [n][3] outputs (sample order, inference)
+    uint16_t* hT;               // training: bf16 h_l, [hidden-1][n_cap/16][128][16] (l = 0..hidden-2)
+    uint16_t* dzT;              // training: bf16 dE/dz_l, [hidden-1][n_cap/16][128][16] (l = 1..hidden-1)
+    float* part_w;              // [slices][hidden-1][128][128] hidden weight gradients per sample slice
+    float* part_thin;           // [thin][nb_cap] the other parameters' gradients per training block
+    double* loss_part;          // [nb_cap] per-block squared errors
     float *f_rho, *f_ux, *f_uy; // field outputs: rho = 1 + u_w y0, u = u_w (y1, y2)
-    int64_t n, n_cap;
+    int64_t n, n_cap, nb_cap;   // samples; samples per hT/dzT layer (multiple of MLP_SLICE); part_thin row length
     int32_t hidden, P;
     int32_t off_w[MLP_MAX_HIDDEN + 1], off_b[MLP_MAX_HIDDEN + 1];
     int32_t cells_nx, cells_ny; // > 0: inputs are the cells of this grid
@@ -211,13 +215,17 @@ struct MlpArgs {
     int32_t pad;
 };
 
+// Parameters that are not hidden-to-hidden weights ("thin": W_0, b_0, the hidden biases,
+// W_L, b_L), numbered W_0 (3 x 128), b_0, b_1 .. b_{hidden-1}, W_L (3 x 128), b_L.
+__host__ __device__ inline int mlp_thin_count(int hidden) { return 4 * MLP_WIDTH + (hidden - 1) * MLP_WIDTH + 3 * MLP_WIDTH + 3; }
+
 void launch_mlp_weights_bf16(const MlpArgs& a, uint16_t* wbf, uint16_t* wbfT, hipStream_t s);
-void launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s);
-void launch_mlp_backward(const MlpArgs& a, hipStream_t s);
-void launch_mlp_reduce(const float* partial, int nblocks, int P, float* grad, const double* loss_part, double inv_3n,
-                       double* loss, hipStream_t s);
-void launch_mlp_adam(float* p, const float* g, float* m, float* v, int P, float lr, float b1, float b2, float eps,
-                     float c1, float c2, hipStream_t s);
+void launch_mlp_forward(const MlpArgs& a, hipStream_t s);
+void launch_mlp_train(const MlpArgs& a, hipStream_t s);
+void launch_mlp_wgrad(const MlpArgs& a, hipStream_t s);
+void launch_mlp_reduce(const MlpArgs& a, float* grad, double inv_3n, double* loss, hipStream_t s);
+void launch_mlp_adam(const MlpArgs& a, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
+                     float eps, float c1, float c2, uint16_t* wbf, uint16_t* wbfT, hipStream_t s);
 void launch_field_samples(const double* post, int nx, int ny, float kn_feat, double inv_uw, float* in, float* target,
                           hipStream_t s);
 // Encoded Knudsen-number input of the network: (log10 Kn + 0.5) / 1.5 maps [0.01, 10] to [-1, 1].

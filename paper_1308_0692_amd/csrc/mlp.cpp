@@ -12,9 +12,11 @@ struct fdlb_mlp {
     int hidden = 4;
     int P = 0;
     int64_t max_batch = 0;
-    int nblk = 0;  // blocks of a full training batch
+    int64_t n_cap = 0;  // samples per layer of the bf16 transposes: max_batch rounded up to a slice
+    int64_t nb_cap = 0; // training blocks of a full batch
     int32_t off_w[fdlb::MLP_MAX_HIDDEN + 1]{}, off_b[fdlb::MLP_MAX_HIDDEN + 1]{};
-    size_t off_wbf = 0, off_wbfT = 0, off_act = 0, off_out = 0, off_part = 0, off_lossp = 0, off_loss = 0;
+    size_t off_wbf = 0, off_wbfT = 0, off_hT = 0, off_dzT = 0, off_partw = 0, off_partt = 0, off_lossp = 0,
+           off_loss = 0;
     size_t work_bytes = 0;
     float *params = nullptr, *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     char* work = nullptr;
@@ -85,21 +87,25 @@ void mlp_create(fdlb_mlp& m, int hidden, int64_t max_batch) {
         k += out;
     }
     m.P = k;
-    m.nblk = (int)((max_batch + MLP_TILE - 1) / MLP_TILE);
-    const size_t wsz = (size_t)(hidden - 1) * MLP_WIDTH * MLP_WIDTH * sizeof(uint16_t);
+    m.n_cap = (max_batch + MLP_SLICE - 1) / MLP_SLICE * MLP_SLICE;
+    m.nb_cap = (max_batch + MLP_TRAIN_TILE - 1) / MLP_TRAIN_TILE;
+    const size_t hw = (size_t)(hidden - 1) * MLP_WIDTH * MLP_WIDTH;
+    const size_t tr = (size_t)(hidden - 1) * MLP_WIDTH * m.n_cap * sizeof(uint16_t);
     size_t off = 0;
     m.off_wbf = off;
-    off += align256(wsz);
+    off += align256(hw * sizeof(uint16_t));
     m.off_wbfT = off;
-    off += align256(wsz);
-    m.off_act = off;
-    off += align256((size_t)hidden * max_batch * MLP_WIDTH * sizeof(float));
-    m.off_out = off;
-    off += align256((size_t)max_batch * 3 * sizeof(float));
-    m.off_part = off;
-    off += align256((size_t)m.nblk * m.P * sizeof(float));
+    off += align256(hw * sizeof(uint16_t));
+    m.off_hT = off;
+    off += align256(tr);
+    m.off_dzT = off;
+    off += align256(tr);
+    m.off_partw = off;
+    off += align256((size_t)(m.n_cap / MLP_SLICE) * hw * sizeof(float));
+    m.off_partt = off;
+    off += align256((size_t)mlp_thin_count(hidden) * m.nb_cap * sizeof(float));
     m.off_lossp = off;
-    off += align256((size_t)m.nblk * sizeof(double));
+    off += align256((size_t)m.nb_cap * sizeof(double));
     m.off_loss = off;
     off += 256;
     m.work_bytes = off;
@@ -109,8 +115,11 @@ void mlp_create(fdlb_mlp& m, int hidden, int64_t max_batch) {
 
 using namespace fdlb;
 
-// One training evaluation (forward, loss, gradient) of n samples; rows may be NULL.
-static void backward_of(fdlb_mlp& M, const float* d_in, const float* d_target, const int32_t* d_rows, int64_t n) {
+// One training evaluation (forward, loss, gradient) of n samples; rows may be NULL.  The bf16
+// weight copies are refreshed from the parameters unless the caller knows them current (the
+// Adam kernel of the previous step of fdlb_mlp_train wrote them).
+static void backward_of(fdlb_mlp& M, const float* d_in, const float* d_target, const int32_t* d_rows, int64_t n,
+                        bool refresh = true) {
     require_bound(M);
     if (n < 1 || n > M.max_batch) throw Error(FDLB_EINVAL, "n must be 1..max_batch");
     if (!d_in || !d_target) throw Error(FDLB_EINVAL, "NULL input or target");
@@ -119,18 +128,18 @@ static void backward_of(fdlb_mlp& M, const float* d_in, const float* d_target, c
     a.target = d_target;
     a.rows = d_rows;
     a.n = n;
-    a.n_cap = M.max_batch;
-    a.out = (float*)(M.work + M.off_out);
-    a.act = (float*)(M.work + M.off_act);
-    a.partial = (float*)(M.work + M.off_part);
+    a.n_cap = M.n_cap;
+    a.nb_cap = M.nb_cap;
+    a.hT = (uint16_t*)(M.work + M.off_hT);
+    a.dzT = (uint16_t*)(M.work + M.off_dzT);
+    a.part_w = (float*)(M.work + M.off_partw);
+    a.part_thin = (float*)(M.work + M.off_partt);
     a.loss_part = (double*)(M.work + M.off_lossp);
     a.inv_3n = (float)(1.0 / (3.0 * (double)n));
-    refresh_bf16(M, a);
-    launch_mlp_forward(a, true, M.stream);
-    launch_mlp_backward(a, M.stream);
-    const int nb = (int)((n + MLP_TILE - 1) / MLP_TILE);
-    launch_mlp_reduce(a.partial, nb, M.P, M.grad, a.loss_part, 1.0 / (3.0 * (double)n),
-                      (double*)(M.work + M.off_loss), M.stream);
+    if (refresh) refresh_bf16(M, a);
+    launch_mlp_train(a, M.stream);
+    launch_mlp_wgrad(a, M.stream);
+    launch_mlp_reduce(a, M.grad, 1.0 / (3.0 * (double)n), (double*)(M.work + M.off_loss), M.stream);
     M.have_loss = true;
 }
 
@@ -143,8 +152,9 @@ static void check_adam(double lr, double beta1, double beta2, double eps, int64_
 static void adam_of(fdlb_mlp& M, double lr, double beta1, double beta2, double eps, int64_t step) {
     const double c1 = 1.0 / (1.0 - std::pow(beta1, (double)step));
     const double c2 = 1.0 / (1.0 - std::pow(beta2, (double)step));
-    launch_mlp_adam(M.params, M.grad, M.adam_m, M.adam_v, M.P, (float)lr, (float)beta1, (float)beta2, (float)eps,
-                    (float)c1, (float)c2, M.stream);
+    launch_mlp_adam(base_args(M), M.params, M.grad, M.adam_m, M.adam_v, (float)lr, (float)beta1, (float)beta2,
+                    (float)eps, (float)c1, (float)c2, (uint16_t*)(M.work + M.off_wbf), (uint16_t*)(M.work + M.off_wbfT),
+                    M.stream);
 }
 
 extern "C" {
@@ -216,7 +226,7 @@ int fdlb_mlp_forward(fdlb_mlp* m, const float* d_in, int64_t n, float* d_out) {
         a.out = d_out;
         a.n = n;
         refresh_bf16(M, a);
-        launch_mlp_forward(a, false, M.stream);
+        launch_mlp_forward(a, M.stream);
         return FDLB_OK;
     });
 }
@@ -265,7 +275,7 @@ int fdlb_mlp_train(fdlb_mlp* m, const float* d_in, const float* d_target, const 
         for (int64_t s = 0; s < steps; ++s) check_adam(lr[s], beta1, beta2, eps, first_step + s);
         for (int64_t s = 0; s < steps; ++s) {
             const int64_t r0 = s * batch, n = std::min(batch, n_rows - r0);
-            backward_of(M, d_in, d_target, d_rows + r0, n);
+            backward_of(M, d_in, d_target, d_rows + r0, n, s == 0);
             adam_of(M, lr[s], beta1, beta2, eps, first_step + s);
         }
         return FDLB_OK;
@@ -291,7 +301,7 @@ int fdlb_mlp_predict_fields(fdlb_mlp* m, double kn, int nx, int ny, double u_w, 
         a.f_ux = d_ux;
         a.f_uy = d_uy;
         refresh_bf16(M, a);
-        launch_mlp_forward(a, false, M.stream);
+        launch_mlp_forward(a, M.stream);
         return FDLB_OK;
     });
 }

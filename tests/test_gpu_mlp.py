@@ -233,3 +233,28 @@ def test_train_and_predict_reject_bad_arguments(F):
     for u_w in (float("nan"), float("inf")):
         with pytest.raises(F.FdlbError):
             net.predict_fields(0.1, 8, 8, u_w)
+
+
+def test_poisoned_workspace_gives_the_same_training(F):
+    """Workspace filled with NaN bytes before binding: a read of memory the kernels did not
+    write first (activation and gradient transposes past the samples, partials of blocks or
+    slices that do not exist) would show up as NaN; gradient, loss and three training steps
+    equal those of a clean workspace to the bit (ragged batch, two hidden-layer counts)."""
+    import torch
+    for hidden, n in ((4, 777), (2, 33)):
+        theta = f32(W.mlp_params(100 + hidden, 128, hidden))
+        a, t = W.mlp_samples(n, 101)
+        A, T = dev(torch, f32(a)), dev(torch, f32(t))
+        rows = dev(torch, np.random.default_rng(102).permutation(n).astype(np.int32), np.int32)
+        out = []
+        for poison in (False, True):
+            net = F.Mlp(hidden=hidden, params=theta, max_batch=1024, poison=poison)
+            net.backward(A, T)
+            g = net.grad.clone()
+            E = net.last_loss()
+            net.train_steps(A, T, rows, n // 3, [3e-3, 2e-3, 1e-3])
+            out.append((g, E, net.params.clone(), net.last_loss()))
+            net.close()
+        (g0, E0, p0, L0), (g1, E1, p1, L1) = out
+        assert torch.isfinite(g1).all() and torch.equal(g0, g1) and E0 == E1
+        assert torch.equal(p0, p1) and L0 == L1
