@@ -542,7 +542,8 @@ int fdlb_mlp_adam_step(fdlb_mlp *m, double lr, double beta1, double beta2, doubl
 
 /*
  * `steps` minibatch steps, each fdlb_mlp_backward then fdlb_mlp_adam_step, enqueued back to back
- * (the same kernels in the same order as the two calls, hence the same parameters to the bit).
+ * (the same arithmetic in the same order as the two calls, the update applied inside the
+ * gradient reduction, hence the same parameters to the bit).
  * Step s uses the samples d_rows[s batch .. min((s + 1) batch, n_rows)) (device int32 row indices,
  * e.g. a permutation of 0..n_rows-1), learning rate lr[s] (host array of `steps` values) and Adam
  * step count first_step + s.  FDLB_EINVAL if batch is not in 1..max_batch, if a step would start

@@ -223,9 +223,16 @@ void launch_mlp_weights_bf16(const MlpArgs& a, uint16_t* wbf, uint16_t* wbfT, hi
 void launch_mlp_forward(const MlpArgs& a, hipStream_t s);
 void launch_mlp_train(const MlpArgs& a, hipStream_t s);
 void launch_mlp_wgrad(const MlpArgs& a, hipStream_t s);
-void launch_mlp_reduce(const MlpArgs& a, float* grad, double inv_3n, double* loss, hipStream_t s);
-void launch_mlp_adam(const MlpArgs& a, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
-                     float eps, float c1, float c2, uint16_t* wbf, uint16_t* wbfT, hipStream_t s);
+// One Adam step: parameters, moments, hyper-parameters with the bias corrections c1 = 1 / (1 -
+// b1^t), c2 = 1 / (1 - b2^t), and the bf16 weight copies it refreshes.
+struct AdamArgs {
+    float *p, *m, *v;
+    float lr, b1, b2, eps, c1, c2;
+    uint16_t *wbf, *wbfT;
+};
+void launch_mlp_reduce(const MlpArgs& a, float* grad, double inv_3n, double* loss, const AdamArgs* adam,
+                       hipStream_t s);
+void launch_mlp_adam(const MlpArgs& a, const float* g, const AdamArgs& adam, hipStream_t s);
 void launch_field_samples(const double* post, int nx, int ny, float kn_feat, double inv_uw, float* in, float* target,
                           hipStream_t s);
 // Encoded Knudsen-number input of the network: (log10 Kn + 0.5) / 1.5 maps [0.01, 10] to [-1, 1].

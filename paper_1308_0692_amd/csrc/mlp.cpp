@@ -117,9 +117,10 @@ using namespace fdlb;
 
 // One training evaluation (forward, loss, gradient) of n samples; rows may be NULL.  The bf16
 // weight copies are refreshed from the parameters unless the caller knows them current (the
-// Adam kernel of the previous step of fdlb_mlp_train wrote them).
+// Adam update of the previous step of fdlb_mlp_train wrote them); with `adam`, the gradient
+// reduction applies that Adam step too.
 static void backward_of(fdlb_mlp& M, const float* d_in, const float* d_target, const int32_t* d_rows, int64_t n,
-                        bool refresh = true) {
+                        bool refresh = true, const AdamArgs* adam = nullptr) {
     require_bound(M);
     if (n < 1 || n > M.max_batch) throw Error(FDLB_EINVAL, "n must be 1..max_batch");
     if (!d_in || !d_target) throw Error(FDLB_EINVAL, "NULL input or target");
@@ -139,7 +140,7 @@ static void backward_of(fdlb_mlp& M, const float* d_in, const float* d_target, c
     if (refresh) refresh_bf16(M, a);
     launch_mlp_train(a, M.stream);
     launch_mlp_wgrad(a, M.stream);
-    launch_mlp_reduce(a, M.grad, 1.0 / (3.0 * (double)n), (double*)(M.work + M.off_loss), M.stream);
+    launch_mlp_reduce(a, M.grad, 1.0 / (3.0 * (double)n), (double*)(M.work + M.off_loss), adam, M.stream);
     M.have_loss = true;
 }
 
@@ -149,12 +150,25 @@ static void check_adam(double lr, double beta1, double beta2, double eps, int64_
         throw Error(FDLB_EINVAL, "bad Adam hyper-parameters");
 }
 
+// Adam step `step` (from 1) of the bound parameters.
+static AdamArgs adam_args(fdlb_mlp& M, double lr, double beta1, double beta2, double eps, int64_t step) {
+    AdamArgs d;
+    d.p = M.params;
+    d.m = M.adam_m;
+    d.v = M.adam_v;
+    d.lr = (float)lr;
+    d.b1 = (float)beta1;
+    d.b2 = (float)beta2;
+    d.eps = (float)eps;
+    d.c1 = (float)(1.0 / (1.0 - std::pow(beta1, (double)step)));
+    d.c2 = (float)(1.0 / (1.0 - std::pow(beta2, (double)step)));
+    d.wbf = (uint16_t*)(M.work + M.off_wbf);
+    d.wbfT = (uint16_t*)(M.work + M.off_wbfT);
+    return d;
+}
+
 static void adam_of(fdlb_mlp& M, double lr, double beta1, double beta2, double eps, int64_t step) {
-    const double c1 = 1.0 / (1.0 - std::pow(beta1, (double)step));
-    const double c2 = 1.0 / (1.0 - std::pow(beta2, (double)step));
-    launch_mlp_adam(base_args(M), M.params, M.grad, M.adam_m, M.adam_v, (float)lr, (float)beta1, (float)beta2,
-                    (float)eps, (float)c1, (float)c2, (uint16_t*)(M.work + M.off_wbf), (uint16_t*)(M.work + M.off_wbfT),
-                    M.stream);
+    launch_mlp_adam(base_args(M), M.grad, adam_args(M, lr, beta1, beta2, eps, step), M.stream);
 }
 
 extern "C" {
@@ -275,8 +289,10 @@ int fdlb_mlp_train(fdlb_mlp* m, const float* d_in, const float* d_target, const 
         for (int64_t s = 0; s < steps; ++s) check_adam(lr[s], beta1, beta2, eps, first_step + s);
         for (int64_t s = 0; s < steps; ++s) {
             const int64_t r0 = s * batch, n = std::min(batch, n_rows - r0);
-            backward_of(M, d_in, d_target, d_rows + r0, n, s == 0);
-            adam_of(M, lr[s], beta1, beta2, eps, first_step + s);
+            // the reduction of the gradient applies the update as it goes (the same arithmetic
+            // as fdlb_mlp_adam_step)
+            const AdamArgs d = adam_args(M, lr[s], beta1, beta2, eps, first_step + s);
+            backward_of(M, d_in, d_target, d_rows + r0, n, s == 0, &d);
         }
         return FDLB_OK;
     });

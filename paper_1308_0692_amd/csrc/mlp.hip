@@ -18,8 +18,9 @@
 //   mlp_wgrad_kernel   dE/dW_l = sum_s dz_l[s]^T h_{l-1}[s] of the hidden layers over slices of
 //                      256 samples on the matrix cores (eight waves per slice and layer);
 //   mlp_reduce_kernel  slices and blocks summed in a fixed order (the gradient is
-//                      reproducible to the bit), and the loss;
-//   mlp_adam_kernel    the update, which also writes the bf16 weight copies of the next step.
+//                      reproducible to the bit), and the loss; in a training loop it also
+//                      applies Adam, which writes the bf16 weight copies of the next step
+//                      (mlp_adam_kernel: the same update on its own).
 //
 // MFMA 32x32x16 lane layout (lane l, 8 bf16 per operand register, 16 fp32 results):
 //   A[i][k]: i = l % 32, k = 8 (l / 32) + t;   B[k][j]: j = l % 32, k = 8 (l / 32) + t;
@@ -496,32 +497,54 @@ __device__ __forceinline__ int thin_param(const MlpArgs& A, int k) {
 }
 }  // namespace
 
+// Adam (bias-corrected first and second moments), fp32, of parameter k with gradient gk; an
+// updated hidden-to-hidden weight also goes to its bf16 copies ([o][i] and [i][o]) that the next
+// training step multiplies by.  One function for the stand-alone update and the one fused into
+// the gradient reduction, so both give the same bits.
+__device__ __forceinline__ void adam_update(const MlpArgs& A, const AdamArgs& D, int k, float gk) {
+    const float mk = D.b1 * D.m[k] + (1.f - D.b1) * gk;
+    const float vk = D.b2 * D.v[k] + (1.f - D.b2) * gk * gk;
+    D.m[k] = mk;
+    D.v[k] = vk;
+    const float pk = D.p[k] - D.lr * (mk * D.c1) / (sqrtf(vk * D.c2) + D.eps);
+    D.p[k] = pk;
+    for (int l = 1; l < A.hidden; ++l) {
+        const int e = k - A.off_w[l];
+        if (e >= 0 && e < MW * MW) {
+            const uint16_t bb = to_bf16(pk);
+            D.wbf[(int64_t)(l - 1) * MW * MW + e] = bb;
+            D.wbfT[(int64_t)(l - 1) * MW * MW + (e % MW) * MW + e / MW] = bb;
+        }
+    }
+}
+
 // Gradient = the sum of the slice partials (hidden weights, a thread each, four running sums
 // combined pairwise) and of the block partials (the other parameters, a wave each, lanes
 // striding over the blocks and a butterfly across the wave), in a fixed order; loss = sum of
-// squared errors / (3 n) (the last wave).
+// squared errors / (3 n) (the last wave).  ADAM: the update follows, parameter by parameter.
+template <bool ADAM>
 __global__ void __launch_bounds__(256) mlp_reduce_kernel(const MlpArgs A, int nslices, int nblocks,
                                                          float* __restrict__ grad, double inv_3n,
-                                                         double* __restrict__ loss) {
+                                                         double* __restrict__ loss, const AdamArgs D) {
     const int HW = (A.hidden - 1) * MW * MW;
     const int nA = HW / 256;
     if ((int)blockIdx.x < nA) {
         const int k = blockIdx.x * 256 + threadIdx.x;
         const float* p = A.part_w + k;
+        // slice b goes to running sum b % 4, in increasing b; sixteen loads in flight
         float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
         int b = 0;
-        for (; b + 8 <= nslices; b += 8) {  // eight loads in flight, the same order of sums
-            float v[8];
+        for (; b + 16 <= nslices; b += 16) {
+            float v[16];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = p[(int64_t)(b + q) * HW];
-            a0 += v[0];
-            a1 += v[1];
-            a2 += v[2];
-            a3 += v[3];
-            a0 += v[4];
-            a1 += v[5];
-            a2 += v[6];
-            a3 += v[7];
+            for (int q = 0; q < 16; ++q) v[q] = p[(int64_t)(b + q) * HW];
+#pragma unroll
+            for (int q = 0; q < 16; q += 4) {
+                a0 += v[q];
+                a1 += v[q + 1];
+                a2 += v[q + 2];
+                a3 += v[q + 3];
+            }
         }
         for (; b + 4 <= nslices; b += 4) {
             a0 += p[(int64_t)b * HW];
@@ -533,7 +556,10 @@ __global__ void __launch_bounds__(256) mlp_reduce_kernel(const MlpArgs A, int ns
         if (b + 1 < nslices) a1 += p[(int64_t)(b + 1) * HW];
         if (b + 2 < nslices) a2 += p[(int64_t)(b + 2) * HW];
         const int l = 1 + k / (MW * MW);
-        grad[A.off_w[l] + k % (MW * MW)] = (a0 + a1) + (a2 + a3);
+        const int kp = A.off_w[l] + k % (MW * MW);
+        const float g = (a0 + a1) + (a2 + a3);
+        grad[kp] = g;
+        if (ADAM) adam_update(A, D, kp, g);
         return;
     }
     const int lane = threadIdx.x & 63;
@@ -545,7 +571,11 @@ __global__ void __launch_bounds__(256) mlp_reduce_kernel(const MlpArgs A, int ns
         for (int b = lane; b < nblocks; b += 64) s += p[b];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) grad[thin_param(A, k)] = s;
+        if (lane == 0) {
+            const int kp = thin_param(A, k);
+            grad[kp] = s;
+            if (ADAM) adam_update(A, D, kp, s);
+        }
     } else if (k == T) {
         double e = 0.0;
         for (int b = lane; b < nblocks; b += 64) e += A.loss_part[b];
@@ -555,30 +585,11 @@ __global__ void __launch_bounds__(256) mlp_reduce_kernel(const MlpArgs A, int ns
     }
 }
 
-// Adam (bias-corrected first and second moments), fp32; the updated hidden-to-hidden weights
-// also go to their bf16 copies ([o][i] and [i][o]) that the next training step multiplies by.
-__global__ void __launch_bounds__(256) mlp_adam_kernel(const MlpArgs A, float* __restrict__ p,
-                                                       const float* __restrict__ g, float* __restrict__ m,
-                                                       float* __restrict__ v, float lr, float b1, float b2,
-                                                       float eps, float c1, float c2, uint16_t* __restrict__ wbf,
-                                                       uint16_t* __restrict__ wbfT) {
+// Stand-alone Adam step of every parameter from the gradient buffer.
+__global__ void __launch_bounds__(256) mlp_adam_kernel(const MlpArgs A, const float* __restrict__ g,
+                                                       const AdamArgs D) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.P) return;
-    const float gk = g[k];
-    const float mk = b1 * m[k] + (1.f - b1) * gk;
-    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
-    m[k] = mk;
-    v[k] = vk;
-    const float pk = p[k] - lr * (mk * c1) / (sqrtf(vk * c2) + eps);
-    p[k] = pk;
-    for (int l = 1; l < A.hidden; ++l) {
-        const int e = k - A.off_w[l];
-        if (e >= 0 && e < MW * MW) {
-            const uint16_t bb = to_bf16(pk);
-            wbf[(int64_t)(l - 1) * MW * MW + e] = bb;
-            wbfT[(int64_t)(l - 1) * MW * MW + (e % MW) * MW + e / MW] = bb;
-        }
-    }
+    if (k < A.P) adam_update(A, D, k, g[k]);
 }
 
 // bf16 copies of the hidden-to-hidden weights, as stored ([o][i]) and transposed ([i][o]).
@@ -652,19 +663,23 @@ void launch_mlp_wgrad(const MlpArgs& a, hipStream_t s) {
     FDLB_HIP(hipGetLastError());
 }
 
-void launch_mlp_reduce(const MlpArgs& a, float* grad, double inv_3n, double* loss, hipStream_t s) {
+void launch_mlp_reduce(const MlpArgs& a, float* grad, double inv_3n, double* loss, const AdamArgs* adam,
+                       hipStream_t s) {
     const int64_t n32 = (a.n + TT - 1) / TT * TT;
     const int nslices = (int)grid_for(n32, SL), nblocks = (int)grid_for(a.n, TT);
     const int nA = (a.hidden - 1) * MW * MW / 256, waves = mlp_thin_count(a.hidden) + 1;
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(nA + grid_for(waves, 4)), dim3(256), 0, s, a, nslices, nblocks, grad,
-                       inv_3n, loss);
+    const dim3 grid(nA + grid_for(waves, 4)), block(256);
+    if (adam)
+        hipLaunchKernelGGL(mlp_reduce_kernel<true>, grid, block, 0, s, a, nslices, nblocks, grad, inv_3n, loss,
+                           *adam);
+    else
+        hipLaunchKernelGGL(mlp_reduce_kernel<false>, grid, block, 0, s, a, nslices, nblocks, grad, inv_3n, loss,
+                           AdamArgs{});
     FDLB_HIP(hipGetLastError());
 }
 
-void launch_mlp_adam(const MlpArgs& a, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
-                     float eps, float c1, float c2, uint16_t* wbf, uint16_t* wbfT, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3(grid_for(a.P, 256)), dim3(256), 0, s, a, p, g, m, v, lr, b1, b2, eps,
-                       c1, c2, wbf, wbfT);
+void launch_mlp_adam(const MlpArgs& a, const float* g, const AdamArgs& adam, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3(grid_for(a.P, 256)), dim3(256), 0, s, a, g, adam);
     FDLB_HIP(hipGetLastError());
 }
 
