@@ -57,7 +57,7 @@ def test_forward_matches_oracle(F, n, seed):
     assert np.abs(y - y64).max() <= 3e-2 * np.abs(y64).max()
 
 
-@pytest.mark.parametrize("n,hidden", [(777, 4), (130, 2), (64, 1), (65, 4), (1, 3)])
+@pytest.mark.parametrize("n,hidden", [(777, 4), (130, 2), (64, 1), (65, 4), (1, 3), (97, 5), (300, 8)])
 def test_gradient_matches_oracle(F, n, hidden):
     import torch
     theta = f32(W.mlp_params(3 + n, 128, hidden))
