@@ -24,6 +24,8 @@
 
 namespace fdlb {
 void promote(fdlb_problem& p);
+void promote_async(fdlb_problem& p);
+void init_rest_async(fdlb_problem& p);
 double* partials_of(fdlb_problem& p, int parity);
 void field_samples(fdlb_problem& p, float* in, float* target);
 void build_problem(fdlb_problem& p, const fdlb_problem_desc& d);
@@ -554,7 +556,38 @@ int batch_solve(fdlb_batch& b, double tol, int64_t max_steps, int32_t check_ever
     return status;
 }
 
-double batch_autotune(fdlb_batch& b, int steps) {
+// Time of one step of the whole batch on its current tiles: one untimed step (a shape's first
+// launch also loads its code), one timed step, and, unless that step already took over twice the
+// best time so far (its further steps would not change the choice), `steps` more timed steps.  A
+// large batch's poor shapes thus cost two steps each instead of all of them.  `parity` follows
+// the steps enqueued.
+static double time_batch_shape(fdlb_batch& b, int steps, int& parity, double best, hipEvent_t e0, hipEvent_t e1) {
+    enqueue_batch_chunk(b, 1, parity, false);
+    parity ^= 1;
+    auto timed = [&](int k) {
+        FDLB_HIP(hipEventRecord(e0, b.stream));
+        enqueue_batch_chunk(b, k, parity, false);
+        if (k & 1) parity ^= 1;
+        FDLB_HIP(hipEventRecord(e1, b.stream));
+        FDLB_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        FDLB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return (double)ms / k;
+    };
+    const double first = timed(1);
+    if (first > 2.0 * best) return first;
+    return timed(steps);
+}
+
+// Every member at rest (as fdlb_batch_init_equilibrium with no fields), one wait for all.
+static void reseed_all(fdlb_batch& b) {
+    for (auto& p : b.probs) init_rest_async(*p);
+    FDLB_HIP(hipStreamSynchronize(b.stream));
+}
+
+// reseed: put the members back at rest at the end (the double group's pass, when it follows,
+// re-seeds them itself).
+double batch_autotune(fdlb_batch& b, int steps, bool reseed) {
     if (!b.bound) throw Error(FDLB_ESTATE, "batch is not bound to device memory");
     if (steps < 1) throw Error(FDLB_EINVAL, "steps must be >= 1");
     hipEvent_t e0, e1;
@@ -566,7 +599,7 @@ double batch_autotune(fdlb_batch& b, int steps) {
     // Seeded once (every member in the primary group's precision): a step's cost does not depend
     // on the values it marches, so the shapes are timed one after another on the evolving state,
     // with the step parity carried over, and the members are re-seeded once at the end.
-    for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+    reseed_all(b);
     int parity = 0;
     try {
         for (int t = 0; t < (int)tile_shapes(prec_of_group(g)).size(); ++t) {
@@ -576,16 +609,9 @@ double batch_autotune(fdlb_batch& b, int steps) {
             b.active.clear();
             for (size_t i = 0; i < b.probs.size(); ++i) b.active.push_back((int)i);
             upload_map(b);
-            enqueue_batch_chunk(b, 2, parity, false);
-            FDLB_HIP(hipEventRecord(e0, b.stream));
-            enqueue_batch_chunk(b, steps, parity, false);
-            if (steps & 1) parity ^= 1;
-            FDLB_HIP(hipEventRecord(e1, b.stream));
-            FDLB_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            FDLB_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms / steps < best) {
-                best = ms / steps;
+            const double ms = time_batch_shape(b, steps, parity, best, e0, e1);
+            if (ms < best) {
+                best = ms;
                 best_tile = t;
             }
         }
@@ -597,7 +623,7 @@ double batch_autotune(fdlb_batch& b, int steps) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     group_set_tile(b, g, best_tile);
-    for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+    if (reseed) reseed_all(b);
     return best;
 }
 
@@ -611,10 +637,9 @@ static void batch_autotune_promoted(fdlb_batch& b, int steps) {
     FDLB_HIP(hipEventCreate(&e1));
     double best = 1e300;
     int best_tile = b.grp[1].tile;
-    for (size_t i = 0; i < b.probs.size(); ++i) {
-        init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
-        promote(*b.probs[i]);
-    }
+    reseed_all(b);
+    for (auto& p : b.probs) promote_async(*p);
+    FDLB_HIP(hipStreamSynchronize(b.stream));
     int parity = 0;
     try {
         for (int t = 0; t < (int)tile_shapes(FDLB_FP64).size(); ++t) {
@@ -624,16 +649,9 @@ static void batch_autotune_promoted(fdlb_batch& b, int steps) {
             b.active.clear();
             for (size_t i = 0; i < b.probs.size(); ++i) b.active.push_back((int)i);
             upload_map(b);
-            enqueue_batch_chunk(b, 2, parity, false);
-            FDLB_HIP(hipEventRecord(e0, b.stream));
-            enqueue_batch_chunk(b, steps, parity, false);
-            if (steps & 1) parity ^= 1;
-            FDLB_HIP(hipEventRecord(e1, b.stream));
-            FDLB_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            FDLB_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms / steps < best) {
-                best = ms / steps;
+            const double ms = time_batch_shape(b, steps, parity, best, e0, e1);
+            if (ms < best) {
+                best = ms;
                 best_tile = t;
             }
         }
@@ -645,7 +663,7 @@ static void batch_autotune_promoted(fdlb_batch& b, int steps) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     group_set_tile(b, 1, best_tile);
-    for (size_t i = 0; i < b.probs.size(); ++i) init_equilibrium(*b.probs[i], nullptr, nullptr, nullptr, 0);
+    reseed_all(b);
 }
 
 }  // namespace fdlb
@@ -805,13 +823,14 @@ int fdlb_batch_autotune(fdlb_batch* b, int steps, double* best_ms_per_step) {
                 if (ok) {
                     group_set_tile(B, g, t);
                     if (ta >= 0 && B.grp[1].used && g != 1) group_set_tile(B, 1, ta);
-                    for (auto& p : B.probs) init_equilibrium(*p, nullptr, nullptr, nullptr, 0);
+                    reseed_all(B);
                     if (best_ms_per_step) *best_ms_per_step = ms;
                     return FDLB_OK;
                 }
             }
         }
-        const double ms = batch_autotune(B, steps);
+        const bool promoted = B.precision == FDLB_MIXED && B.grp[1].used;
+        const double ms = batch_autotune(B, steps, !promoted);
         batch_autotune_promoted(B, steps);
         if (!key.empty())
             tune_cache_put(key, B.grp[primary_group(B)].tile,

@@ -364,7 +364,9 @@ static const VelEntry<double>* vel64(fdlb_problem& p) { return (const VelEntry<d
 static double* io(fdlb_problem& p) { return (double*)(p.d_work + p.off_io); }
 
 // Reset the step counter and convergence records (host-to-device copy, never inside a graph).
-static void reset_ctrl(fdlb_problem& p, double tol) {
+// Without `sync` the copy from the problem's pinned slot may still be pending on return: the
+// caller synchronizes the stream before that slot is written again.
+static void reset_ctrl(fdlb_problem& p, double tol, bool sync = true) {
     double* h = p.pinned;
     std::fill(h, h + 8, 0.0);
     h[CTRL_FIRST_BELOW] = -1.0;
@@ -373,7 +375,7 @@ static void reset_ctrl(fdlb_problem& p, double tol) {
     h[CTRL_FREEZE] = 0.0;
     p.freeze_on = false;
     FDLB_HIP(hipMemcpyAsync(ctrl(p), h, 8 * sizeof(double), hipMemcpyHostToDevice, p.stream));
-    FDLB_HIP(hipStreamSynchronize(p.stream));
+    if (sync) FDLB_HIP(hipStreamSynchronize(p.stream));
 }
 
 // Recompute the moment and wall-flux buffers of the current state.
@@ -427,6 +429,24 @@ void init_equilibrium(fdlb_problem& p, const double* rho, const double* ux, cons
     FDLB_HIP(hipStreamSynchronize(p.stream));  // r is a host temporary
     p.seeded = true;
     reset_ctrl(p, 0.0);
+}
+
+// The state at rest (rho = 1, u = 0), as init_equilibrium with no fields, enqueued without
+// waiting: the caller synchronizes the stream before the problem's pinned slot is reused (a batch
+// re-seeds all its members and waits once).
+void init_rest_async(fdlb_problem& p) {
+    require_bound(p);
+    p.parity = 0;
+    restart_precision(p);
+    if (p.prec == FDLB_FP32)
+        launch_seed<float>((float*)pop_buf(p, 0), p.q, p.plane, vel64(p), nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, p.stream);
+    else
+        launch_seed<double>((double*)pop_buf(p, 0), p.q, p.plane, vel64(p), nullptr, nullptr, nullptr, nullptr,
+                            nullptr, nullptr, nullptr, p.stream);
+    refresh_moments(p);
+    p.seeded = true;
+    reset_ctrl(p, 0.0, false);
 }
 
 void init_equilibrium_dev(fdlb_problem& p, const float* rho, const float* ux, const float* uy, int renorm) {
@@ -646,7 +666,8 @@ static void unfreeze(fdlb_problem& p) {
 // Mixed precision: carry the current float state over to double in place (the widened
 // values are exact), then recompute its moments and wall fluxes with the double kernels so
 // that the next step sees exactly what a double run from this state would.
-void promote(fdlb_problem& p) {
+// Widen a mixed-precision problem's state to double, enqueued on its stream.
+void promote_async(fdlb_problem& p) {
     require_seeded(p);
     if (p.d.precision != FDLB_MIXED) throw Error(FDLB_EINVAL, "only a FDLB_MIXED problem changes precision");
     if (p.prec == FDLB_FP64) return;
@@ -656,6 +677,10 @@ void promote(fdlb_problem& p) {
     launch_copy(pop_buf(p, par), pop_buf(p, par ^ 1), (size_t)n * sizeof(double), p.stream);
     set_active(p, FDLB_FP64);
     refresh_moments(p);
+}
+
+void promote(fdlb_problem& p) {
+    promote_async(p);
     FDLB_HIP(hipStreamSynchronize(p.stream));
 }
 

@@ -43,10 +43,11 @@ def generate(kns: Iterable[float], n: int = 64, order: int = 4, u_w: float = 0.0
     b.set_pseudo_time(pseudo)
     t0 = time.perf_counter()
     if autotune:
-        b.autotune(steps=3)
+        b.autotune(steps=3)  # leaves every member at rest
     tune_s = time.perf_counter() - t0
-    for i in range(len(kns)):
-        b.init_equilibrium(i)
+    if not autotune:
+        for i in range(len(kns)):
+            b.init_equilibrium(i)
     t0 = time.perf_counter()
     status, reps = b.solve(tol, max_steps, check_every=check_every)
     wall = time.perf_counter() - t0
