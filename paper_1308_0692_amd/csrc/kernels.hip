@@ -684,10 +684,13 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
                 vload<VX>(m2, A.mom_in + 2 * plane + o);
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    const double r0 = 1.0 + m0[v];
-                    const double ux0 = m1[v] / r0, uy0 = m2[v] / r0;
-                    const double r1 = 1.0 + ar[r][v];
-                    const double ux1 = ax[r][v] / r1, uy1 = ay[r][v] / r1;
+                    // one double division per cell: 1 / r0 = r1 / (r0 r1), 1 / r1 = r0 / (r0 r1)
+                    // (a few ulp; this epilogue runs on one wave of the tile while the others wait)
+                    const double r0 = 1.0 + m0[v], r1 = 1.0 + ar[r][v];
+                    const double inv = 1.0 / (r0 * r1);
+                    const double i0 = r1 * inv, i1 = r0 * inv;
+                    const double ux0 = m1[v] * i0, uy0 = m2[v] * i0;
+                    const double ux1 = ax[r][v] * i1, uy1 = ay[r][v] * i1;
                     const double dx = ux1 - ux0, dy = uy1 - uy0;
                     const double u2 = ux1 * ux1 + uy1 * uy1;
                     num += dx * dx + dy * dy;
