@@ -607,13 +607,17 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
     quadrant(std::integral_constant<int, -1>{}, std::integral_constant<int, -1>{}, A.quad_begin[3],
              A.quad_begin[4]);
 
-    // Sum the partial moments of the WA waves that share this tile (fixed order: wave 0 adds
-    // the others' contributions in increasing wa).
+    double num = 0.0, den = 0.0, umax = 0.0;
     if constexpr (WA > 1) {
+        // The WA waves that share this tile meet in LDS: every wave leaves its partial sums there,
+        // and cell c = r VX + v of each lane is then summed (wave 0's partial first, then in
+        // increasing wave order), written and checked by wave c % WA, the wall sums by wave 0.
+        // The epilogue is spread over the tile's waves instead of running on one while the others
+        // wait; the sums are the same whichever wave forms them.
         constexpr int NM = 3 * K * VX + K + VX;  // doubles per lane
-        __shared__ double xred[WA - 1][WPT][NM][64];
-        if (wa > 0) {
-            double* o = &xred[wa - 1][wt][0][lane];
+        __shared__ double xred[WA][WPT][NM][64];
+        {
+            double* o = &xred[wa][wt][0][lane];
             int i = 0;
 #pragma unroll
             for (int r = 0; r < K; ++r)
@@ -629,30 +633,49 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
             for (int v = 0; v < VX; ++v) o[64 * i++] = phy[v];
         }
         __syncthreads();
+        auto total = [&](const int i) {
+            double t = xred[0][wt][i][lane];
+#pragma unroll
+            for (int w = 1; w < WA; ++w) t += xred[w][wt][i][lane];
+            return t;
+        };
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const int c = r * VX + v;
+                if (c % WA != wa || !rv[r]) continue;
+                const double sr = total(3 * c), sx = total(3 * c + 1), sy = total(3 * c + 2);
+                const int64_t o = (int64_t)(y0 + r) * nx + x0 + v;
+                A.mom_out[o] = sr;
+                A.mom_out[plane + o] = sx;
+                A.mom_out[2 * plane + o] = sy;
+                // residual terms against the old moments, re-read; one double division per
+                // cell: 1 / r0 = r1 / (r0 r1), 1 / r1 = r0 / (r0 r1)
+                const double r0 = 1.0 + A.mom_in[o], r1 = 1.0 + sr;
+                const double inv = 1.0 / (r0 * r1);
+                const double i0 = r1 * inv, i1 = r0 * inv;
+                const double ux0 = A.mom_in[plane + o] * i0, uy0 = A.mom_in[2 * plane + o] * i0;
+                const double ux1 = sx * i1, uy1 = sy * i1;
+                const double dx = ux1 - ux0, dy = uy1 - uy0;
+                const double u2 = ux1 * ux1 + uy1 * uy1;
+                num += dx * dx + dy * dy;
+                den += u2;
+                umax = fmax(umax, u2);
+            }
         if (wa == 0) {
-#pragma unroll 1
-            for (int w = 0; w < WA - 1; ++w) {
-                const double* o = &xred[w][wt][0][lane];
-                int i = 0;
+            if (on_left || on_right) {
 #pragma unroll
                 for (int r = 0; r < K; ++r)
+                    if (rv[r]) A.phi_out[xw * L + y0 + r] = total(3 * K * VX + r);
+            }
+            if (on_bot || on_top) {
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        ar[r][v] += o[64 * i++];
-                        ax[r][v] += o[64 * i++];
-                        ay[r][v] += o[64 * i++];
-                    }
-#pragma unroll
-                for (int r = 0; r < K; ++r) phx[r] += o[64 * i++];
-#pragma unroll
-                for (int v = 0; v < VX; ++v) phy[v] += o[64 * i++];
+                for (int v = 0; v < VX; ++v) A.phi_out[yw * L + x0 + v] = total(3 * K * VX + K + v);
             }
         }
-    }
-
-    // Outputs for the next step (one wave per tile row writes them).
-    double num = 0.0, den = 0.0, umax = 0.0;
-    if (wa == 0) {
+    } else {
+        // Outputs for the next step.
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             if (rv[r]) {
@@ -685,7 +708,7 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
                     // one double division per cell: 1 / r0 = r1 / (r0 r1), 1 / r1 = r0 / (r0 r1)
-                    // (a few ulp; this epilogue runs on one wave of the tile while the others wait)
+                    // (a few ulp)
                     const double r0 = 1.0 + m0[v], r1 = 1.0 + ar[r][v];
                     const double inv = 1.0 / (r0 * r1);
                     const double i0 = r1 * inv, i1 = r0 * inv;
@@ -703,21 +726,23 @@ __device__ __forceinline__ void step_body(const StepArgs<T>& A, const int bid, c
     num = wave_sum(num);
     den = wave_sum(den);
     umax = wave_max(umax);
-    __shared__ double red[WPT][3];
-    if (lane == 0 && wa == 0) {
-        red[wt][0] = num;
-        red[wt][1] = den;
-        red[wt][2] = umax;
+    __shared__ double red[WA][WPT][3];
+    if (lane == 0) {
+        red[wa][wt][0] = num;
+        red[wa][wt][1] = den;
+        red[wa][wt][2] = umax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double a = 0, b = 0, m = 0;
 #pragma unroll
-        for (int w = 0; w < WPT; ++w) {
-            a += red[w][0];
-            b += red[w][1];
-            m = fmax(m, red[w][2]);
-        }
+        for (int j = 0; j < WA; ++j)
+#pragma unroll
+            for (int w = 0; w < WPT; ++w) {
+                a += red[j][w][0];
+                b += red[j][w][1];
+                m = fmax(m, red[j][w][2]);
+            }
         part[0] = a;
         part[1] = b;
         part[2] = m;
