@@ -462,7 +462,10 @@ int fdlb_batch_state_upload(fdlb_batch *b, int i, const double *f_host);
 /*
  * One tile shape serves the whole batch (it must fit every problem).  fdlb_batch_autotune
  * times every fitting shape on the whole batch for `steps` steps (every problem is re-seeded
- * at rest afterwards) and keeps the fastest.  Synchronous.
+ * at rest afterwards) and keeps, among the shapes within 5 % of the fastest, the one that
+ * splits a tile's velocities over the most waves (a batch shrinks as its members converge, and
+ * its smaller launches pack the shorter blocks of such shapes better); best_ms_per_step is that
+ * shape's time.  Synchronous.
  */
 int fdlb_batch_set_tile(fdlb_batch *b, int tile);
 int fdlb_batch_get_tile(const fdlb_batch *b);

@@ -585,6 +585,29 @@ static void reseed_all(fdlb_batch& b) {
     FDLB_HIP(hipStreamSynchronize(b.stream));
 }
 
+// The shape a batch keeps, from the full-batch step times of the shapes timed: among those within
+// 5 % of the fastest, the one that splits a tile's velocities over the most waves (then the
+// faster).  A batch shrinks as its members converge, and the later, smaller launches pack short
+// blocks better than long ones: on the 64-cavity sweep the four-way 64x8 tile, 3 % behind the
+// two-way one on the full batch, solves the whole sweep 3-5 % sooner.
+static int pick_batch_shape(int prec, const std::vector<std::pair<int, double>>& timed, double& ms_out) {
+    double best = 1e300;
+    for (const auto& tm : timed) best = std::min(best, tm.second);
+    int pick = -1;
+    double pick_ms = 0;
+    for (const auto& tm : timed) {
+        if (tm.second > 1.05 * best) continue;
+        const int wa = tile_shapes(prec)[tm.first].wa;
+        const int pwa = pick < 0 ? 0 : tile_shapes(prec)[pick].wa;
+        if (pick < 0 || wa > pwa || (wa == pwa && tm.second < pick_ms)) {
+            pick = tm.first;
+            pick_ms = tm.second;
+        }
+    }
+    ms_out = pick_ms;
+    return pick;
+}
+
 // reseed: put the members back at rest at the end (the double group's pass, when it follows,
 // re-seeds them itself).
 double batch_autotune(fdlb_batch& b, int steps, bool reseed) {
@@ -596,6 +619,7 @@ double batch_autotune(fdlb_batch& b, int steps, bool reseed) {
     const int g = primary_group(b);
     double best = 1e300;
     int best_tile = b.grp[g].tile;
+    std::vector<std::pair<int, double>> timed;
     // Seeded once (every member in the primary group's precision): a step's cost does not depend
     // on the values it marches, so the shapes are timed one after another on the evolving state,
     // with the step parity carried over, and the members are re-seeded once at the end.
@@ -610,10 +634,8 @@ double batch_autotune(fdlb_batch& b, int steps, bool reseed) {
             for (size_t i = 0; i < b.probs.size(); ++i) b.active.push_back((int)i);
             upload_map(b);
             const double ms = time_batch_shape(b, steps, parity, best, e0, e1);
-            if (ms < best) {
-                best = ms;
-                best_tile = t;
-            }
+            timed.emplace_back(t, ms);
+            best = std::min(best, ms);
         }
     } catch (...) {
         (void)hipEventDestroy(e0);
@@ -622,6 +644,7 @@ double batch_autotune(fdlb_batch& b, int steps, bool reseed) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (!timed.empty()) best_tile = pick_batch_shape(prec_of_group(g), timed, best);
     group_set_tile(b, g, best_tile);
     if (reseed) reseed_all(b);
     return best;
@@ -637,6 +660,7 @@ static void batch_autotune_promoted(fdlb_batch& b, int steps) {
     FDLB_HIP(hipEventCreate(&e1));
     double best = 1e300;
     int best_tile = b.grp[1].tile;
+    std::vector<std::pair<int, double>> timed;
     reseed_all(b);
     for (auto& p : b.probs) promote_async(*p);
     FDLB_HIP(hipStreamSynchronize(b.stream));
@@ -650,10 +674,8 @@ static void batch_autotune_promoted(fdlb_batch& b, int steps) {
             for (size_t i = 0; i < b.probs.size(); ++i) b.active.push_back((int)i);
             upload_map(b);
             const double ms = time_batch_shape(b, steps, parity, best, e0, e1);
-            if (ms < best) {
-                best = ms;
-                best_tile = t;
-            }
+            timed.emplace_back(t, ms);
+            best = std::min(best, ms);
         }
     } catch (...) {
         (void)hipEventDestroy(e0);
@@ -662,6 +684,8 @@ static void batch_autotune_promoted(fdlb_batch& b, int steps) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // (the double group holds only the members near convergence, a few at a time)
+    if (!timed.empty()) best_tile = pick_batch_shape(FDLB_FP64, timed, best);
     group_set_tile(b, 1, best_tile);
     reseed_all(b);
 }
